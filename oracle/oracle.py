@@ -1,0 +1,188 @@
+"""ctypes binding of the FP64 CPU reference (``oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the simulator.  It imports nothing
+from the simulator package; callers hand it plain numpy arrays and dicts
+(the seeded generator's output widened to float64).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.cpp")
+
+TYPE_FIELDS = ("mass", "Ixx", "Iyy", "Izz", "arm", "alpha", "k_f", "k_m",
+               "tau_m", "drag", "w_max", "w_ref")
+GLOBAL_FIELDS = ("g", "r_sat", "ipos_max", "iatt_max", "irate_max", "az_min_frac")
+
+
+class OracleType(C.Structure):
+    _fields_ = [(f, C.c_double) for f in TYPE_FIELDS] + [
+        ("gains", C.c_double * 9), ("step_budget", C.c_int64)]
+
+
+class OracleGlobals(C.Structure):
+    _fields_ = [(f, C.c_double) for f in GLOBAL_FIELDS]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with g++ (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
+                               "-ffp-contract=off", "-fno-fast-math", SRC_PATH, "-o", tmp])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        L.oracle_rollout.argtypes = [P, I, P, I, I, P, I64, I64, P, P, I64, P, P, I, I, I64,
+                                     I64, D, I64, I]
+        L.oracle_jacobian.argtypes = [P, I, P, P, I64, I64, P, P, I64, P, I, I, I64, I64, D,
+                                      I64, P, I]
+        L.oracle_derivative.argtypes = [P, D, P, P, P]
+        L.oracle_controller.argtypes = [P, P, P, P, P, P, D, P]
+        L.oracle_allocation.argtypes = [P, P, P]
+        L.oracle_count_ops.argtypes = [P, P, I, D, P]
+        for fn in ("oracle_rollout", "oracle_jacobian", "oracle_derivative", "oracle_controller",
+                   "oracle_allocation", "oracle_count_ops", "oracle_max_threads"):
+            getattr(L, fn).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def make_type(t: dict) -> OracleType:
+    """Widen one type dict (float32 scalars, gains, budget) to FP64."""
+    o = OracleType()
+    for f in TYPE_FIELDS:
+        setattr(o, f, float(t[f]))
+    for k in range(9):
+        o.gains[k] = float(t["gains"][k])
+    o.step_budget = int(t["budget"])
+    return o
+
+
+def make_types(types) -> C.Array:
+    arr = (OracleType * len(types))()
+    for i, t in enumerate(types):
+        arr[i] = make_type(t)
+    return arr
+
+
+def make_globals(g: dict) -> OracleGlobals:
+    o = OracleGlobals()
+    for f in GLOBAL_FIELDS:
+        setattr(o, f, float(g[f]))
+    return o
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threads_default() -> int:
+    return int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+
+
+def rollout(state, types, glob, mode, dt, n_steps, *, type_idx=None, gains=None,
+            motor_cmd=None, wp=None, resample_every=0, step0=0, renorm=True, threads=None):
+    """Advance a copy of ``state`` ([30, N], widened to FP64) and return it."""
+    s = np.array(state, dtype=np.float64, copy=True, order="C")
+    n = s.shape[1]
+    ti = None if type_idx is None else np.ascontiguousarray(type_idx, dtype=np.int32)
+    gn, mc, w = _f64(gains), _f64(motor_cmd), _f64(wp)
+    ne = 0 if w is None else w.shape[0]
+    cmd_ld = n
+    tarr, garr = make_types(types), make_globals(glob)
+    rc = lib().oracle_rollout(C.addressof(tarr), len(types), C.addressof(garr), int(mode),
+                              int(bool(renorm)), _p(s), n, n, _p(ti), _p(gn), n, _p(mc), _p(w),
+                              ne, int(resample_every), cmd_ld, int(step0), float(dt),
+                              int(n_steps), int(threads or threads_default()))
+    if rc != 0:
+        raise ValueError("oracle_rollout rejected its arguments")
+    return s
+
+
+def jacobian(state, types, glob, dt, n_steps, *, wp, type_idx=None, gains=None,
+             resample_every=0, step0=0, threads=None):
+    """Closed-loop rollout with forward-mode dual numbers.
+
+    Returns (final state [30, N], jac [N, 30, 39]) where jac[a, r, c] is
+    d x_N[r] / d (x0[0..29], gains[0..8])[c] of agent a.
+    """
+    s = np.array(state, dtype=np.float64, copy=True, order="C")
+    n = s.shape[1]
+    jac = np.zeros((n, 30, 39), dtype=np.float64)
+    ti = None if type_idx is None else np.ascontiguousarray(type_idx, dtype=np.int32)
+    gn, w = _f64(gains), _f64(wp)
+    tarr, garr = make_types(types), make_globals(glob)
+    rc = lib().oracle_jacobian(C.addressof(tarr), len(types), C.addressof(garr), _p(s), n, n,
+                               _p(ti), _p(gn), n, _p(w), w.shape[0], int(resample_every), n,
+                               int(step0), float(dt), int(n_steps), _p(jac),
+                               int(threads or threads_default()))
+    if rc != 0:
+        raise ValueError("oracle_jacobian rejected its arguments")
+    return s, jac
+
+
+def derivative(t: dict, g: float, x, wcmd):
+    """f(x) of one agent; x[18] with absolute rotor speeds (rows 13-16) and J last."""
+    x = _f64(x); wc = _f64(wcmd); dx = np.zeros(18)
+    o = make_type(t)
+    if lib().oracle_derivative(C.byref(o), float(g), _p(x), _p(wc), _p(dx)) != 0:
+        raise ValueError("oracle_derivative failed")
+    return dx
+
+
+def controller(t: dict, glob: dict, x, mem, wp, dt, gains=None):
+    """One controller evaluation; returns (absolute rotor commands[4], new memory[12])."""
+    x = _f64(x); m = np.array(mem, dtype=np.float64, copy=True); w = _f64(wp)
+    gn = _f64(gains); out = np.zeros(4)
+    o, gl = make_type(t), make_globals(glob)
+    if lib().oracle_controller(C.byref(o), C.byref(gl), _p(gn), _p(x), _p(m), _p(w), float(dt),
+                               _p(out)) != 0:
+        raise ValueError("oracle_controller failed")
+    return out, m
+
+
+def allocation(t: dict):
+    """(G, G^-1) of eq. (3) for one type."""
+    G = np.zeros((4, 4)); Gi = np.zeros((4, 4))
+    o = make_type(t)
+    if lib().oracle_allocation(C.byref(o), _p(G), _p(Gi)) != 0:
+        raise ValueError("singular allocation matrix")
+    return G, Gi
+
+
+def count_ops(t: dict, glob: dict, mode: int, dt: float) -> dict:
+    """Operations of one agent-step of the reference arithmetic."""
+    c = np.zeros(5, dtype=np.int64)
+    o, gl = make_type(t), make_globals(glob)
+    if lib().oracle_count_ops(C.byref(o), C.byref(gl), int(mode), float(dt), _p(c)) != 0:
+        raise ValueError("oracle_count_ops failed")
+    d = dict(zip(("add", "mul", "div", "sqrt", "cmp"), (int(v) for v in c)))
+    d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
+    return d
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

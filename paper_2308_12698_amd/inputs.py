@@ -1,0 +1,244 @@
+"""Seeded synthetic swarms shaped like the paper's quadrotor workloads.
+
+This module is the only code that both the HIP path and the FP64 reference
+see.  It produces data and nothing else: initial states, commands,
+waypoints, per-type physical parameters and gains, all drawn from numpy
+PCG64 streams and rounded to float32 so that both sides start from the same
+bits.  It performs none of the simulator's arithmetic (no controller, no
+dynamics, no integration).
+
+The paper benchmarks a batch of identical nonlinear quadrotors flying under
+a PID body-rate controller (Sec. III, Table I and Fig. "run_time"); it
+publishes no dataset, so every workload here is synthetic.
+
+State layout (structure of arrays, ``float32[30][ld]``, one column per agent):
+
+====== ===================================================================
+rows   meaning
+====== ===================================================================
+0-2    position p, inertial ENU frame [m]
+3-5    velocity v, inertial frame [m/s]
+6-9    attitude quaternion q = (w, x, y, z), body FLU -> inertial, Hamilton
+10-12  body rates omega [rad/s]
+13-16  rotor speeds, stored as the deviation from the type's reference
+       speed ``w_ref`` [rad/s]
+17-19  position-loop integral
+20-22  attitude-loop integral
+23-25  rate-loop integral
+26-28  body rates at the previous control step (rate-loop derivative)
+29     running cost J = integral of the sum of squared rotor speeds
+====== ===================================================================
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+N_ROWS = 30
+N_GAINS = 9
+SEED_BASE = 12698
+
+# Base airframe of the homogeneous workloads (mass, inertia, arm, rotor
+# coefficients, motor time constant, linear drag, speed limit).
+BASE_QUAD = dict(mass=1.0, Ixx=0.0082, Iyy=0.0082, Izz=0.0149, arm=0.17,
+                 alpha=math.pi / 4.0, k_f=6.1e-6, k_m=1.5e-7, tau_m=0.02,
+                 drag=0.1, w_max=2500.0)
+# Cascade gains [kpp, kip, kdp, kpa, kia, kda, kpr, kir, kdr].
+DEFAULT_GAINS = (2.0, 0.1, 2.0, 8.0, 0.2, 0.1, 25.0, 2.0, 0.02)
+# Controller limits shared by all types.
+DEFAULT_GLOBALS = dict(g=9.81, r_sat=2.0, ipos_max=5.0, iatt_max=1.0,
+                       irate_max=1.0, az_min_frac=0.5)
+NO_BUDGET = 2**31 - 1
+BOX = (100.0, 100.0, 20.0)
+
+TYPE_FIELDS = ("mass", "Ixx", "Iyy", "Izz", "arm", "alpha", "k_f", "k_m",
+               "tau_m", "drag", "w_max", "w_ref")
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32)
+
+
+def rng(config: int, stream: int) -> np.random.Generator:
+    """PCG64 stream ``SEED_BASE + 100*config + stream``."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + 100 * config + stream))
+
+
+@dataclass
+class Swarm:
+    """One synthetic workload.  Every float array is float32."""
+    name: str
+    mode: int                      # 0 open loop (motor commands), 1 closed loop
+    dt: float
+    n_steps: int
+    state: np.ndarray              # [30, N]
+    types: list                    # list of dicts, float32 scalars + gains + budget
+    glob: dict                     # controller limits, float32 scalars
+    type_idx: np.ndarray | None = None     # uint8 [N]
+    gains: np.ndarray | None = None        # [9, N] per-agent gains
+    motor_cmd: np.ndarray | None = None    # [4, N] deviation from w_ref
+    wp: np.ndarray | None = None           # [E, 3, N]
+    resample_every: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.state.shape[1]
+
+
+def hover_reference_speed(mass, k_f, g) -> np.float32:
+    """Rotor speed at which four rotors carry the weight, rounded to float32.
+
+    Used only to pick the reference point of the stored rotor-speed
+    deviation and the hovering initial condition; any reference works.
+    """
+    return np.float32(math.sqrt(float(mass) * float(g) / (4.0 * float(k_f))))
+
+
+def make_type(mass, Ixx, Iyy, Izz, arm, k_f, k_m, tau_m=0.02, drag=0.1,
+              w_max=2500.0, alpha=math.pi / 4.0, gains=DEFAULT_GAINS,
+              budget=NO_BUDGET, g=DEFAULT_GLOBALS["g"], w_ref=None) -> dict:
+    t = dict(mass=mass, Ixx=Ixx, Iyy=Iyy, Izz=Izz, arm=arm, alpha=alpha,
+             k_f=k_f, k_m=k_m, tau_m=tau_m, drag=drag, w_max=w_max)
+    t = {k: np.float32(v) for k, v in t.items()}
+    if w_ref is None:
+        w_ref = hover_reference_speed(t["mass"], t["k_f"], np.float32(g))
+    t["w_ref"] = np.float32(w_ref)
+    t["gains"] = f32(gains)
+    t["budget"] = int(budget)
+    return t
+
+
+def base_type(**over) -> dict:
+    kw = dict(BASE_QUAD)
+    kw.update(over)
+    return make_type(**kw)
+
+
+def globals_f32(**over) -> dict:
+    d = dict(DEFAULT_GLOBALS)
+    d.update(over)
+    return {k: np.float32(v) for k, v in d.items()}
+
+
+def _box_positions(r: np.random.Generator, n: int) -> np.ndarray:
+    return np.stack([r.uniform(0.0, BOX[0], n), r.uniform(0.0, BOX[1], n),
+                     r.uniform(0.0, BOX[2], n)])
+
+
+def hover_state(pos: np.ndarray) -> np.ndarray:
+    """Level, at rest, rotors at the reference speed, controller memory zero."""
+    n = pos.shape[1]
+    s = np.zeros((N_ROWS, n), dtype=np.float64)
+    s[0:3] = pos
+    s[6] = 1.0
+    return f32(s)
+
+
+def config0(n: int = 1000, n_steps: int = 1000, drag: float | None = None) -> Swarm:
+    """Open-loop plain swarm: identical quads, per-motor commands uniform
+    within +/-10 % of hover, constant over the rollout."""
+    r = rng(0, 0)
+    t = base_type() if drag is None else base_type(drag=drag)
+    state = hover_state(_box_positions(r, n))
+    u = r.uniform(0.9, 1.1, size=(4, n))
+    cmd = f32((u - 1.0) * float(t["w_ref"]))
+    return Swarm("open-loop", 0, 1e-3, n_steps, state, [t], globals_f32(), motor_cmd=cmd)
+
+
+def config1(n: int = 5000, n_steps: int = 10000) -> Swarm:
+    """Closed-loop plain swarm: hovering in the box, one random waypoint each."""
+    r = rng(1, 0)
+    state = hover_state(_box_positions(r, n))
+    wp = f32(_box_positions(r, n)[None])
+    return Swarm("closed-loop", 1, 1e-3, n_steps, state, [base_type()], globals_f32(),
+                 wp=wp, resample_every=0)
+
+
+def config2(n: int = 1 << 20, n_steps: int = 10000, resample_every: int = 2000) -> Swarm:
+    """Scale workload: closed loop, waypoints redrawn every ``resample_every`` steps."""
+    r = rng(2, 0)
+    state = hover_state(_box_positions(r, n))
+    n_ep = max(1, -(-n_steps // resample_every))
+    wp = f32(np.stack([_box_positions(r, n) for _ in range(n_ep)]))
+    return Swarm("scale", 1, 1e-3, n_steps, state, [base_type()], globals_f32(),
+                 wp=wp, resample_every=resample_every)
+
+
+HETERO_COUNTS = (1024, 4096, 16384, 65536, 131072, 262144, 524288, 3072)
+# Base airframe inertia divided by mass*arm^2 (x, y, z).
+INERTIA_SHAPE = (0.0082 / (1.0 * 0.17**2), 0.0082 / (1.0 * 0.17**2), 0.0149 / (1.0 * 0.17**2))
+
+
+def hetero_types(n_types: int = 8, seed_stream: int = 0) -> list:
+    """Eight airframes: mass U[0.3, 3] kg, arm U[0.08, 0.35] m, inertia
+    mass*arm^2 times the base shape, rotor coefficients for a thrust to
+    weight ratio of 2 at the speed limit, budgets 1000*(t+1) steps."""
+    r = rng(3, seed_stream)
+    g = DEFAULT_GLOBALS["g"]
+    types = []
+    for t in range(n_types):
+        m = float(np.float32(r.uniform(0.3, 3.0)))
+        L = float(np.float32(r.uniform(0.08, 0.35)))
+        w_max = 2500.0
+        k_f = m * g / (2.0 * w_max**2)
+        k_m = k_f * (1.5e-7 / 6.1e-6)
+        I = [m * L * L * s for s in INERTIA_SHAPE]
+        types.append(make_type(m, I[0], I[1], I[2], L, k_f, k_m, w_max=w_max,
+                               budget=1000 * (t + 1)))
+    return types
+
+
+def config3(scale: int = 1, counts=HETERO_COUNTS) -> Swarm:
+    """Heterogeneous swarm: 8 types with uneven counts and step budgets.
+
+    ``scale`` divides every count (for small parity cases).  Counts are
+    assigned to types by a seeded permutation and the per-agent type labels
+    are shuffled, so neighbouring agents generally differ in type.
+    """
+    r = rng(3, 1)
+    types = hetero_types()
+    counts = [max(1, c // scale) for c in counts]
+    perm = r.permutation(len(types))
+    labels = np.concatenate([np.full(c, perm[i], dtype=np.uint8) for i, c in enumerate(counts)])
+    r.shuffle(labels)
+    n = labels.size
+    state = hover_state(_box_positions(r, n))
+    # Reference speed is per type; the hovering state stores deviation 0.
+    n_steps = max(t["budget"] for t in types)
+    n_ep = -(-n_steps // 2000)
+    wp = f32(np.stack([_box_positions(r, n) for _ in range(n_ep)]))
+    return Swarm("hetero", 1, 1e-3, n_steps, state, types, globals_f32(),
+                 type_idx=labels, wp=wp, resample_every=2000,
+                 extra=dict(counts=counts, type_of_count=perm))
+
+
+def config4(n: int = 65536, n_steps: int = 500, dt: float = 2e-3) -> Swarm:
+    """Differentiable rollout: per-agent gains (defaults x U[0.8, 1.2]),
+    target = start + U[-1, 1]^3, waypoint = target."""
+    r = rng(4, 0)
+    pos = _box_positions(r, n)
+    state = hover_state(pos)
+    target = f32(pos + r.uniform(-1.0, 1.0, size=(3, n)))
+    gains = f32(np.asarray(DEFAULT_GAINS)[:, None] * r.uniform(0.8, 1.2, size=(N_GAINS, n)))
+    return Swarm("diff", 1, dt, n_steps, state, [base_type()], globals_f32(),
+                 gains=gains, wp=target[None].copy(), resample_every=0,
+                 extra=dict(target=target, ckpt_every=50, cost_weight=1e-4))
+
+
+def subset(sw: Swarm, idx: np.ndarray) -> Swarm:
+    """The same workload restricted to the agents ``idx`` (column gather)."""
+    idx = np.asarray(idx)
+    pick = lambda a, ax: None if a is None else np.ascontiguousarray(np.take(a, idx, axis=ax))
+    extra = dict(sw.extra)
+    if "target" in extra:
+        extra["target"] = pick(extra["target"], 1)
+    return Swarm(sw.name, sw.mode, sw.dt, sw.n_steps, pick(sw.state, 1), sw.types, sw.glob,
+                 type_idx=pick(sw.type_idx, 0), gains=pick(sw.gains, 1),
+                 motor_cmd=pick(sw.motor_cmd, 1), wp=pick(sw.wp, 2),
+                 resample_every=sw.resample_every, extra=extra)
+
+
+CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
