@@ -1,0 +1,273 @@
+"""Throughput benchmark of the batched quadrotor step on one MI355X.
+
+Workload (one bench "step"): the closed-loop scale swarm -- 1,048,576
+quadrotors hovering in a 100 x 100 x 20 m box, random waypoints redrawn
+every 2,000 steps, cascaded PID + X mixer + rotor lag + quaternion rigid
+body + RK4 at dt = 1 ms, 10,000 time steps, FP32 structure of arrays, fused
+kernel (many steps per launch, state in registers) replayed from a hipGraph,
+launch shape from the autotuner.  value = agent-steps per second over the K
+timed rollouts, inputs resident in HBM.
+
+Also reported, on the same GPU: the plain one-step-per-launch kernel on the
+same swarm, the fused form without the graph, the heterogeneous 8-type batch
+in one launch per rollout, and (when the adjoint is built) forward+backward
+of the differentiable rollout.  cpu_baseline times the FP64 reference on a
+bounded sample of the same workload on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "quadrotor agent-steps/s at 1M agents (fwd, fwd+bwd) vs plain kernel, 1e-4"
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (256 CUs, 2.4 GHz)
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_12698_amd", "csrc", f)
+                  for f in ("quad_step.h", "kernels.hip", "kernels.h")]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed rollouts")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed rollouts")
+    ap.add_argument("--agents", type=int, default=1 << 20)
+    ap.add_argument("--sim-steps", type=int, default=10000)
+    ap.add_argument("--no-extra", action="store_true", help="skip the other forms")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the quadrotor step has no cross-agent coupling, "
+              "so a multi-GPU run is N independent copies of this one (see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    sw = I.config2(n=args.agents, n_steps=args.sim_steps)
+    N, T = sw.n, args.sim_steps
+    log(f"inputs: {N} agents, {T} steps, {sw.wp.shape[0]} waypoint epochs")
+    state = torch.from_numpy(sw.state).to(dev)
+    wp = torch.from_numpy(sw.wp).to(dev)
+    sim = Simulator(sw.types, sw.glob, mode=1, form="fused", use_graph=True)
+    tuned = sim.autotune(state, sw.dt, 200, wp=wp, resample_every=sw.resample_every)
+    sim.set_options(form="fused", use_graph=True, **tuned)
+    log(f"autotuned launch shape: {tuned}")
+    launches = -(-T // tuned["steps_per_launch"])
+
+    def rollout():
+        sim.step(state, T, sw.dt, wp=wp, resample_every=sw.resample_every)
+
+    for _ in range(args.warmup):
+        rollout()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        rollout()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [a.elapsed_time(b) for a, b in ev]
+    value = N * T * args.steps / wall
+    log(f"fused+graph: {value:.4e} agent-steps/s, rollout {np.mean(ev_ms):.2f} ms (events)")
+    assert torch.isfinite(state).all().item(), "non-finite state after the rollouts"
+
+    # roofline of the fused kernel: ALU bound, algorithmic flops from the
+    # reference's operation count per agent-step
+    from oracle import oracle as O
+    ops = O.count_ops(sw.types[0], sw.glob, 1, sw.dt)
+    launch_ms = float(np.mean(ev_ms)) / launches
+    achieved_tflops = ops["flops"] * N * tuned["steps_per_launch"] / (launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "traffic": measured_traffic("fused"),
+                "kernel": "k_rollout<closed loop> (fused)",
+                "flops_per_agent_step": ops["flops"],
+                "avg_launch_ms": round(launch_ms, 4), "agents_per_launch": N,
+                "steps_per_launch": tuned["steps_per_launch"]}
+
+    forms = {"fused_graph": {"agent_steps_per_s": value, "rollout_ms": float(np.mean(ev_ms))}}
+    if not args.no_extra:
+        forms.update(extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops))
+    sim.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(O, sw)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"closed-loop scale swarm: {N} quadrotors, {T} RK4 steps at dt=1 ms, "
+                               "waypoints redrawn every 2,000 steps; fused kernel in a hipGraph",
+                   "n_agents": N, "sim_steps": T, **tuned},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
+    res = {}
+    N = sw.n
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    # plain: one launch per step, state round-trips HBM every step
+    steps_plain = 1000
+    plain = Simulator(sw.types, sw.glob, mode=1, form="plain", use_graph=True)
+    ms = timed(lambda: plain.step(state, steps_plain, sw.dt, wp=wp, resample_every=sw.resample_every))
+    plain.close()
+    bytes_step = (37 + 37 + 3) * 4      # state rows in and out + waypoint
+    launch_ms = ms / steps_plain
+    gbs = bytes_step * N / (launch_ms * 1e-3) / 1e9
+    res["plain"] = {"agent_steps_per_s": N * steps_plain / (ms * 1e-3), "steps_timed": steps_plain,
+                    "avg_launch_ms": launch_ms,
+                    "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                 "bytes_per_agent_step": bytes_step,
+                                 "traffic": measured_traffic("plain")}}
+    log(f"plain: {res['plain']['agent_steps_per_s']:.4e} agent-steps/s, {gbs:.0f} GB/s")
+
+    # fused without the graph (host launches)
+    sim.set_options(form="fused", use_graph=False, block=sim.opts.block,
+                    steps_per_launch=sim.opts.steps_per_launch, grid_blocks=sim.opts.grid_blocks)
+    ms = timed(lambda: sim.step(state, 2000, sw.dt, wp=wp, resample_every=sw.resample_every))
+    res["fused_eager"] = {"agent_steps_per_s": N * 2000 / (ms * 1e-3), "steps_timed": 2000}
+    log(f"fused eager: {res['fused_eager']['agent_steps_per_s']:.4e} agent-steps/s")
+
+    # heterogeneous: 8 types, budgets 1,000..8,000, one launch per rollout
+    hw = I.config3()
+    hsim = Simulator(hw.types, hw.glob, mode=1, form="fused", steps_per_launch=hw.n_steps)
+    hs = torch.from_numpy(hw.state).to(dev)
+    ti = torch.from_numpy(hw.type_idx).to(dev)
+    hwp = torch.from_numpy(hw.wp).to(dev)
+    work = sum(int(c) * hw.types[t]["budget"] for t, c in enumerate(hw.extra["counts"]))
+    for label, perm in (("hetero_unordered", None), ("hetero", hsim.order_by_type(ti))):
+        s0 = hs.clone()
+        ms = timed(lambda: hsim.step(s0, hw.n_steps, hw.dt, type_idx=ti, perm=perm, wp=hwp,
+                                     resample_every=hw.resample_every), reps=1)
+        res[label] = {"agent_steps_per_s": work / (ms * 1e-3), "agent_steps": work,
+                      "n_agents": hw.n, "rollout_ms": ms}
+        log(f"{label}: {res[label]['agent_steps_per_s']:.4e} agent-steps/s")
+    hsim.close()
+
+    # forward (with checkpoints) + hand-written adjoint of the differentiable
+    # rollout: 500 steps at dt = 2 ms, checkpoints every 50 steps, at the
+    # workload's own 65,536 agents and at 1,048,576 agents
+    for n_agents in (65536, N):
+        dw = I.config4(n=n_agents)
+        K = dw.extra["ckpt_every"]
+        dsim = Simulator(dw.types, dw.glob, mode=1, form="fused", steps_per_launch=100)
+        x0 = torch.from_numpy(dw.state).to(dev)
+        x = x0.clone()
+        gains = torch.from_numpy(dw.gains).to(dev)
+        dwp = torch.from_numpy(dw.wp).to(dev)
+        tgt = torch.from_numpy(dw.extra["target"]).to(dev)
+        ckpt = torch.empty((dw.n_steps // K, 37, dw.n), device=dev)
+        gfin = torch.empty((30, dw.n), device=dev)
+        ws = None
+
+        def fwd():
+            x.copy_(x0)
+            dsim.step(x, dw.n_steps, dw.dt, gains=gains, wp=dwp, ckpt=ckpt, ckpt_every=K)
+
+        def bwd():
+            gfin.zero_()
+            gfin[0:3] = 2.0 * (x[0:3] - tgt)
+            gfin[29] = dw.extra["cost_weight"]
+            return dsim.step_backward(ckpt, K, dw.n_steps, dw.dt, gfin, gains=gains, wp=dwp,
+                                      workspace=ws)
+
+        fwd(); gx, gg = bwd()
+        torch.cuda.synchronize()
+        ms_f = timed(fwd)
+        ms_fb = timed(lambda: (fwd(), bwd()))
+        key = "fwd_bwd" if n_agents == N else "fwd_bwd_65536"
+        res[key] = {"agent_steps_per_s": dw.n * dw.n_steps / (ms_fb * 1e-3), "n_agents": dw.n,
+                    "sim_steps": dw.n_steps, "ckpt_every": K, "fwd_ms": ms_f,
+                    "fwd_bwd_ms": ms_fb, "bwd_ms": ms_fb - ms_f}
+        log(f"{key}: {res[key]['agent_steps_per_s']:.4e} agent-steps/s (fwd {ms_f:.2f} ms, "
+            f"fwd+bwd {ms_fb:.2f} ms)")
+        dsim.close()
+        del ckpt, x, x0
+    return res
+
+
+def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000):
+    """FP64 reference on the host cores, bounded sample of the same workload."""
+    from paper_2308_12698_amd import inputs as I
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sub = I.subset(sw, np.arange(min(sample_agents, sw.n)))
+    t0 = time.perf_counter()
+    O.rollout(sub.state, sub.types, sub.glob, 1, sub.dt, sample_steps, wp=sub.wp,
+              resample_every=sub.resample_every, threads=threads)
+    dt = time.perf_counter() - t0
+    v = sub.n * sample_steps / dt
+    log(f"cpu baseline: {v:.4e} agent-steps/s on {threads} threads ({dt:.1f} s)")
+    return {"value": v, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sub.n} agents of the same swarm x {sample_steps} steps, FP64, "
+                      f"{dt:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * potato.h -- C ABI of the MI355X batched quadrotor simulator.
+ *
+ * The library advances N independent nonlinear quadrotors held as
+ * structure-of-arrays FP32 device buffers.  One time step of one agent is:
+ *   1. controller (closed loop): position -> attitude -> body-rate PID
+ *      cascade whose innermost loop is the body-rate PID of Sec. II-B, then
+ *      the mixer, which solves the allocation of eq. (3) for the four rotor
+ *      thrusts, saturates them and inverts the rotor model of eq. (2);
+ *      open loop instead holds caller-given rotor-speed commands;
+ *   2. classical fourth-order Runge-Kutta over the rigid-body model of
+ *      eqs. (qd1)-(qd4) (Sec. II-B), with rotor thrust and torque
+ *      k_f W^2, k_m W^2 (eq. 2), first-order rotor lag and linear drag,
+ *      the command held through the four stages;
+ *   3. renormalisation of the attitude quaternion.
+ * Batching homogeneous agents in tensors is the data-oriented design of
+ * Sec. II-A (Fig. 1); several airframe types in one batch through a
+ * per-agent type index replace the paper's one-process-per-type scheme.
+ *
+ * Conventions shared by every entry point:
+ *   - All pointers named "device" are HIP device pointers owned by the
+ *     caller; the library never frees them and never keeps them after the
+ *     call returns (except inside a cached hipGraph, see potato_options).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *     and the call returns without synchronising.
+ *   - Host-detectable errors return a status with no side effect and no
+ *     work enqueued; launch failures return POTATO_EHIP.  The message of the
+ *     last failure on the calling thread is potato_last_error().
+ *   - No C++ exception crosses this interface.
+ *
+ * State layout: float32 rows[37][ld], one column per agent (ld >= n_agents):
+ *   0-2 position (ENU inertial, m)      3-5 velocity (m/s)
+ *   6-9 quaternion w,x,y,z (body FLU -> inertial, Hamilton product)
+ *   10-12 body rates (rad/s)
+ *   13-16 rotor speeds minus the type's w_ref (rad/s); rotors are numbered
+ *         front-left, front-right, back-right, back-left; 1 and 3 give
+ *         positive yaw reaction torque
+ *   17-19 position-loop integral   20-22 attitude-loop integral
+ *   23-25 rate-loop integral       26-28 body rates at the previous step
+ *   29 running cost J = time integral of the sum of squared rotor speeds
+ *   30-32, 33-35, 36: rounding carries of position, velocity and J.  The
+ *         integrator keeps the low-order bits that an FP32 update drops
+ *         (compensated summation); the represented value is row + carry.
+ *         Set them to 0 when writing a state; they are < 1 ulp of the row.
+ * Open-loop mode reads and writes rows 0-16 and 30-35 only.
+ */
+#ifndef POTATO_H
+#define POTATO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct potato_ctx potato_ctx;
+
+typedef enum {
+    POTATO_OK = 0,
+    POTATO_EINVAL = 1,       /* invalid argument (nothing was enqueued) */
+    POTATO_ENOMEM = 2,       /* host or device allocation failed */
+    POTATO_EHIP = 3,         /* HIP runtime or launch failure */
+    POTATO_EUNSUPPORTED = 4  /* valid but not implemented combination */
+} potato_status;
+
+enum { POTATO_OPEN_LOOP = 0, POTATO_CLOSED_LOOP = 1 };
+enum { POTATO_FORM_AUTO = 0, POTATO_FORM_PLAIN = 1, POTATO_FORM_FUSED = 2 };
+enum { POTATO_ROWS = 37, POTATO_GAINS = 9, POTATO_MAX_TYPES = 256 };
+
+/* One airframe type (all FP32, SI units).  alpha is the rotor-arm angle of
+ * the allocation matrix of eq. (3) (pi/4 for an X frame); k_f, k_m are the
+ * thrust and torque coefficients of eq. (2) in N/(rad/s)^2 and N m/(rad/s)^2;
+ * tau_m the rotor time constant (s); drag the linear drag coefficient (N s/m);
+ * w_max the rotor speed limit (rad/s); w_ref the reference speed the stored
+ * rotor rows are relative to (any value; the hover speed keeps them small).
+ * gains = [kpp kip kdp kpa kia kda kpr kir kdr] (position, attitude, rate
+ * loops; P, I, D).  step_budget: an agent of this type is advanced only
+ * while its global step index is below it (INT32_MAX = unlimited). */
+typedef struct {
+    float mass, Ixx, Iyy, Izz, arm, alpha, k_f, k_m, tau_m, drag, w_max, w_ref;
+    float gains[9];
+    int32_t step_budget;
+} potato_type_params;
+
+/* Controller limits shared by all types: gravity g, position-error
+ * saturation radius r_sat (m), integral clamps, and the lower bound of the
+ * commanded vertical acceleration as a fraction of g. */
+typedef struct {
+    float g, r_sat, ipos_max, iatt_max, irate_max, az_min_frac;
+} potato_limits;
+
+/* Launch policy.  form: plain = one launch per time step (state round-trips
+ * through HBM every step); fused = steps_per_launch steps per launch with
+ * the state in registers; auto = fused.  block / steps_per_launch /
+ * grid_blocks = 0 select the tuned value (potato_autotune) or a default.
+ * use_graph != 0 captures the launches of a potato_step call in a hipGraph
+ * cached on the context and replays it when the same call (same pointers,
+ * sizes, step index and time step) is made again. */
+typedef struct {
+    int32_t mode;              /* POTATO_OPEN_LOOP or POTATO_CLOSED_LOOP */
+    int32_t form;              /* POTATO_FORM_* */
+    int32_t block;             /* threads per block: 64, 128, 256, 512 or 0 */
+    int32_t steps_per_launch;  /* fused form, >= 1 or 0 */
+    int32_t grid_blocks;       /* fused form: blocks in the grid-stride loop, 0 = one agent per thread */
+    int32_t use_graph;
+} potato_options;
+
+/* Device state rows[37][ld] (in place). */
+typedef struct {
+    float* rows;
+    int64_t ld;
+} potato_state;
+
+/* Optional per-agent data (device pointers; each may be NULL):
+ *   type   uint8[n_agents] type index into the context's table (NULL: all
+ *          type 0).  Values >= n_types are undefined behaviour (not checked
+ *          on the device).
+ *   perm   int32[n_agents] processing order: lane j advances agent perm[j]
+ *          (a permutation of 0..n_agents-1, e.g. from
+ *          potato_order_by_type).  NULL = identity.
+ *   gains  float[9][gains_ld] per-agent gains (NULL: the type's gains). */
+typedef struct {
+    const uint8_t* type;
+    const int32_t* perm;
+    const float* gains;
+    int64_t gains_ld;
+} potato_params;
+
+/* Commands (device pointers):
+ *   motor_cmd float[4][ld] open-loop rotor commands relative to w_ref,
+ *             held for the whole call;
+ *   wp        float[n_epochs][3][ld] closed-loop waypoints; the step with
+ *             global index k uses epoch min(k / resample_every, n_epochs-1)
+ *             (resample_every <= 0: epoch 0);
+ *   step0     global index of the first step of the call (for the waypoint
+ *             epoch and the step budget). */
+typedef struct {
+    const float* motor_cmd;
+    const float* wp;
+    int32_t n_epochs;
+    int32_t resample_every;
+    int64_t ld;
+    int64_t step0;
+} potato_cmds;
+
+/* Create a context for `n_types` airframe types (1..256).  Validates the
+ * table (positive mass, inertia, arm, k_f, k_m, tau_m; finite values),
+ * derives per-type constants once on the host (in double, rounded to FP32;
+ * all per-agent arithmetic on the device is FP32) and copies the table to
+ * the current HIP device.  *out is NULL on failure. */
+potato_status potato_create(potato_ctx** out, const potato_type_params* types, int32_t n_types,
+                            const potato_limits* limits, const potato_options* opts);
+
+/* Release the context, its device table and cached graphs.  NULL is a no-op. */
+potato_status potato_destroy(potato_ctx* ctx);
+
+/* Replace the launch policy (also drops cached graphs). */
+potato_status potato_set_options(potato_ctx* ctx, const potato_options* opts);
+
+/*
+ * Advance agents 0..n_agents-1 by n_steps time steps of length dt in place.
+ * An agent of type t takes min(n_steps, max(0, step_budget_t - step0))
+ * steps.  Errors (POTATO_EINVAL): ctx/state/params/cmds NULL, rows NULL,
+ * n_agents < 1, ld < n_agents, n_steps < 0, dt not finite and > 0, missing
+ * motor_cmd (open loop) or wp / n_epochs < 1 (closed loop), cmds->ld <
+ * n_agents, gains_ld < n_agents when gains are given, ckpt set with
+ * ckpt_every < 1.  n_steps == 0 is a no-op.
+ * ckpt (optional, device float[ceil(n_steps/ckpt_every)][37][ld]): slot c
+ * receives the state at call-relative step c*ckpt_every, before that step;
+ * it is what potato_step_backward consumes.  Requires the fused form.
+ */
+potato_status potato_step(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                          const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
+                          float* ckpt, int32_t ckpt_every, void* stream);
+
+/*
+ * Time the fused form over a grid of (block, steps per launch, grid size)
+ * on a scratch copy of the given inputs (the caller's buffers are not
+ * modified), store the fastest on the context for this mode and type
+ * layout, and return it in *best (may be NULL).  probe_steps is the number
+ * of time steps per timed trial.  Allocates scratch memory for the
+ * duration of the call and synchronises `stream`.
+ */
+potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                              const potato_cmds* cmds, float dt, int64_t n_agents, int32_t probe_steps,
+                              potato_options* best, void* stream);
+
+/*
+ * Build a processing order for heterogeneous batches: perm (device
+ * int32[n_agents]) lists agents grouped by type, types ordered by step
+ * budget (longest first, ties by type index), agents of one type in
+ * increasing index order.  Waves then hold one type and the longest
+ * budgets are scheduled first.  type (device uint8[n_agents]) must be
+ * < n_types.  workspace: device buffer of at least
+ * potato_order_workspace_bytes(n_agents, n_types) bytes.
+ */
+int64_t potato_order_workspace_bytes(int64_t n_agents, int32_t n_types);
+potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t n_agents,
+                                   int32_t* perm, void* workspace, int64_t workspace_bytes,
+                                   void* stream);
+
+/*
+ * Reverse mode of a closed-loop potato_step call that wrote checkpoints:
+ * given grad_final = dL/dx_N (device float[30][ld], the 30 physical rows of
+ * the final state), compute grad_x0 = dL/dx_0 (device float[30][ld]) and,
+ * if grad_gains is not NULL, dL/dgains per agent (device float[9][ld]; with
+ * type gains the caller sums over the agents of a type).  This is the
+ * vector-Jacobian product of the rollout map (x_0, gains) -> x_N through
+ * every step of the forward pass: controller, mixer, RK4 stages and
+ * renormalisation (the time discretisation of Sec. II-B differentiated
+ * exactly, not the continuous adjoint).  A carry row has the cotangent of
+ * its row.
+ *   params, cmds, dt, n_agents, n_steps: exactly as in the forward call;
+ *   ckpt, ckpt_every: the checkpoints that call wrote (37 rows per slot);
+ *   workspace: device scratch of potato_backward_workspace_bytes() bytes
+ *   (per-thread recomputation tape of ckpt_every steps).
+ * Each segment of ckpt_every steps is recomputed from its checkpoint, then
+ * reversed.  Errors: POTATO_EINVAL as in potato_step, plus null ckpt,
+ * grad_final or grad_x0, ckpt_every < 1 or a workspace that is too small;
+ * POTATO_EUNSUPPORTED in open-loop mode.  grad_x0 may alias grad_final.
+ */
+int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* params, int64_t n_agents,
+                                        int32_t ckpt_every);
+potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params, const potato_cmds* cmds,
+                                   float dt, int64_t n_agents, int32_t n_steps, const float* ckpt,
+                                   int32_t ckpt_every, int64_t ld, const float* grad_final,
+                                   float* grad_x0, float* grad_gains, void* workspace,
+                                   int64_t workspace_bytes, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* potato_last_error(void);
+
+/* Library version string. */
+const char* potato_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POTATO_H */

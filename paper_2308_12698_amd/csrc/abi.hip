@@ -1,0 +1,525 @@
+/*
+ * abi.hip -- host side of the C ABI declared in include/potato.h: argument
+ * validation, per-type constant derivation, launch policy (plain / fused,
+ * autotuned block, steps per launch and grid), hipGraph capture and replay,
+ * and the type-ordering helper for heterogeneous batches.
+ */
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/potato.h"
+#include "kernels.h"
+
+using namespace potato;
+
+namespace {
+
+thread_local std::string g_err;
+
+potato_status fail(potato_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+potato_status hip_fail(hipError_t e, const char* where) {
+    return fail(POTATO_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+
+struct TuneKey {
+    int mode, het, gains, perm;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(mode, het, gains, perm) < std::tie(o.mode, o.het, o.gains, o.perm);
+    }
+};
+struct Tuned { int block, steps, grid; };
+
+}  // namespace
+
+struct potato_ctx {
+    int device = 0;
+    int n_types = 0;
+    std::vector<potato_type_params> params;
+    std::vector<TypeConst> consts;
+    TypeConst* d_table = nullptr;
+    int32_t* d_rank = nullptr;         /* rank of each type by budget (longest first) */
+    potato_limits limits{};
+    potato_options opts{};
+    hipStream_t cap_stream = nullptr;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    std::map<TuneKey, Tuned> tuned;
+    std::mutex mu;
+};
+
+namespace {
+
+/* Per-type constants.  Derived once per context on the host in double and
+ * rounded to FP32; every per-agent operation on the device is FP32. */
+TypeConst derive(const potato_type_params& p, const potato_limits& L) {
+    TypeConst c{};
+    const double m = p.mass, kf = p.k_f, km = p.k_m, w = p.w_ref;
+    const double ls = (double)p.arm * std::sin((double)p.alpha);
+    const double lc = (double)p.arm * std::cos((double)p.alpha);
+    const double F0 = 4.0 * kf * w * w / m;
+    c.mass = p.mass;
+    c.inv_m = (float)(1.0 / m);
+    c.cd_m = (float)(p.drag / m);
+    c.Ix = p.Ixx; c.Iy = p.Iyy; c.Iz = p.Izz;
+    c.iIx = (float)(1.0 / p.Ixx); c.iIy = (float)(1.0 / p.Iyy); c.iIz = (float)(1.0 / p.Izz);
+    c.F0 = (float)F0;
+    c.F0_g = (float)(F0 - (double)L.g);
+    c.kf_m = (float)(kf / m);
+    c.kf_ls = (float)(kf * ls);
+    c.kf_lc = (float)(kf * lc);
+    c.km = p.k_m;
+    c.w_ref = p.w_ref;
+    c.two_w = (float)(2.0 * w);
+    c.four_w2 = (float)(4.0 * w * w);
+    c.inv_tau = (float)(1.0 / p.tau_m);
+    c.mix_x = (float)(1.0 / (4.0 * ls));
+    c.mix_y = (float)(1.0 / (4.0 * lc));
+    c.mix_z = (float)(kf / (4.0 * km));
+    c.f_max = (float)(kf * (double)p.w_max * (double)p.w_max);
+    c.inv_kf = (float)(1.0 / kf);
+    for (int k = 0; k < 9; ++k) c.gains[k] = p.gains[k];
+    c.budget = p.step_budget;
+    return c;
+}
+
+Limits make_limits(const potato_limits& L, float dt) {
+    Limits r{};
+    r.g = L.g;
+    r.r_sat = L.r_sat;
+    r.r_sat2 = L.r_sat * L.r_sat;
+    r.ipos_max = L.ipos_max;
+    r.iatt_max = L.iatt_max;
+    r.irate_max = L.irate_max;
+    r.az_min = L.az_min_frac * L.g;
+    r.dt = dt;
+    r.half_dt = 0.5f * dt;
+    r.dt6 = dt / 6.0f;
+    r.inv_dt = 1.0f / dt;
+    return r;
+}
+
+potato_status check_type(const potato_type_params& p, int t) {
+    const float vals[] = {p.mass, p.Ixx, p.Iyy, p.Izz, p.arm, p.k_f, p.k_m, p.tau_m};
+    for (float v : vals)
+        if (!finite_pos(v)) return fail(POTATO_EINVAL, "type %d: mass, inertia, arm, k_f, k_m, tau_m must be finite and > 0", t);
+    if (!std::isfinite(p.alpha) || std::fabs(std::sin(p.alpha)) < 1e-6f || std::fabs(std::cos(p.alpha)) < 1e-6f)
+        return fail(POTATO_EINVAL, "type %d: alpha must be finite with sin and cos away from 0", t);
+    if (!std::isfinite(p.drag) || p.drag < 0.0f || !std::isfinite(p.w_max) || p.w_max < 0.0f ||
+        !std::isfinite(p.w_ref) || p.w_ref < 0.0f)
+        return fail(POTATO_EINVAL, "type %d: drag, w_max, w_ref must be finite and >= 0", t);
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(p.gains[k])) return fail(POTATO_EINVAL, "type %d: gains must be finite", t);
+    return POTATO_OK;
+}
+
+potato_status check_limits(const potato_limits& L) {
+    if (!finite_pos(L.g) || !finite_pos(L.r_sat) || !std::isfinite(L.ipos_max) || L.ipos_max < 0 ||
+        !std::isfinite(L.iatt_max) || L.iatt_max < 0 || !std::isfinite(L.irate_max) || L.irate_max < 0 ||
+        !finite_pos(L.az_min_frac))
+        return fail(POTATO_EINVAL, "limits: g, r_sat, az_min_frac must be > 0; integral clamps >= 0");
+    return POTATO_OK;
+}
+
+potato_status check_options(const potato_options& o) {
+    if (o.mode != POTATO_OPEN_LOOP && o.mode != POTATO_CLOSED_LOOP)
+        return fail(POTATO_EINVAL, "options.mode must be 0 (open loop) or 1 (closed loop)");
+    if (o.form < POTATO_FORM_AUTO || o.form > POTATO_FORM_FUSED)
+        return fail(POTATO_EINVAL, "options.form must be 0, 1 or 2");
+    if (!(o.block == 0 || o.block == 64 || o.block == 128 || o.block == 256 || o.block == 512))
+        return fail(POTATO_EINVAL, "options.block must be 0, 64, 128, 256 or 512");
+    if (o.steps_per_launch < 0 || o.grid_blocks < 0)
+        return fail(POTATO_EINVAL, "options.steps_per_launch and grid_blocks must be >= 0");
+    return POTATO_OK;
+}
+
+void drop_graphs(potato_ctx* ctx) {
+    for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+}
+
+struct Plan {
+    Variant v;
+    StepArgs a;
+    int block, steps, grid;
+};
+
+potato_status validate_step(const potato_ctx* ctx, const potato_state* st, const potato_params* pp,
+                            const potato_cmds* cm, float dt, int64_t n, int32_t n_steps,
+                            const float* ckpt, int32_t ckpt_every) {
+    if (!ctx || !st || !pp || !cm) return fail(POTATO_EINVAL, "ctx, state, params and cmds must be non-null");
+    if (!st->rows) return fail(POTATO_EINVAL, "state.rows is null");
+    if (n < 1) return fail(POTATO_EINVAL, "n_agents must be >= 1");
+    if (n > 0x7fffffffLL) return fail(POTATO_EINVAL, "n_agents must fit in int32");
+    if (st->ld < n) return fail(POTATO_EINVAL, "state.ld (%lld) < n_agents (%lld)", (long long)st->ld, (long long)n);
+    if (n_steps < 0) return fail(POTATO_EINVAL, "n_steps must be >= 0");
+    if (!std::isfinite(dt) || !(dt > 0.0f)) return fail(POTATO_EINVAL, "dt must be finite and > 0");
+    if (cm->ld < n) return fail(POTATO_EINVAL, "cmds.ld < n_agents");
+    if (cm->step0 < 0) return fail(POTATO_EINVAL, "cmds.step0 must be >= 0");
+    if (ctx->opts.mode == POTATO_OPEN_LOOP) {
+        if (!cm->motor_cmd) return fail(POTATO_EINVAL, "open loop needs cmds.motor_cmd");
+        if (ckpt) return fail(POTATO_EUNSUPPORTED, "checkpoints are only produced in closed loop");
+    } else {
+        if (!cm->wp || cm->n_epochs < 1) return fail(POTATO_EINVAL, "closed loop needs cmds.wp and n_epochs >= 1");
+    }
+    if (pp->gains && pp->gains_ld < n) return fail(POTATO_EINVAL, "params.gains_ld < n_agents");
+    if (ckpt && ckpt_every < 1) return fail(POTATO_EINVAL, "ckpt_every must be >= 1 when ckpt is given");
+    if (ckpt && ctx->opts.form == POTATO_FORM_PLAIN)
+        return fail(POTATO_EUNSUPPORTED, "checkpoints need the fused form");
+    if (pp->type == nullptr && pp->perm != nullptr)
+        return fail(POTATO_EUNSUPPORTED, "params.perm needs params.type");
+    return POTATO_OK;
+}
+
+Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp, const potato_cmds* cm,
+               float dt, int64_t n, float* ckpt, int32_t ckpt_every) {
+    Plan P{};
+    P.v.mode = ctx->opts.mode;
+    P.v.het = pp->type != nullptr;
+    P.v.gains = ctx->opts.mode == POTATO_CLOSED_LOOP && pp->gains != nullptr;
+    P.v.ckpt = ckpt != nullptr;
+    P.v.perm = P.v.het && pp->perm != nullptr;
+    StepArgs& a = P.a;
+    a.rows = st->rows; a.ld = st->ld; a.n = n;
+    a.type = pp->type; a.perm = P.v.perm ? pp->perm : nullptr;
+    a.gains = P.v.gains ? pp->gains : nullptr; a.gains_ld = pp->gains_ld;
+    a.motor_cmd = cm->motor_cmd; a.wp = cm->wp; a.cmd_ld = cm->ld;
+    a.n_epochs = cm->n_epochs < 1 ? 1 : cm->n_epochs; a.resample = cm->resample_every;
+    a.step0 = cm->step0; a.k0 = 0; a.n_steps = 0;
+    a.ckpt = ckpt; a.ckpt_every = ckpt_every > 0 ? ckpt_every : 1;
+    a.n_types = ctx->n_types; a.table = ctx->d_table;
+    a.lim = make_limits(ctx->limits, dt);
+    a.tc0 = ctx->consts[0];
+    if (!P.v.het) {
+        /* homogeneous launch: type 0's constants travel in the argument segment */
+        a.n_types = 1;
+    }
+
+    const potato_options& o = ctx->opts;
+    Tuned t{256, 100, 0};
+    auto it = ctx->tuned.find(TuneKey{P.v.mode, P.v.het, P.v.gains, P.v.perm});
+    if (it != ctx->tuned.end()) t = it->second;
+    if (o.form == POTATO_FORM_PLAIN) {
+        P.block = o.block ? o.block : t.block;
+        P.steps = 1;
+        P.grid = 0;
+    } else {
+        P.block = o.block ? o.block : t.block;
+        P.steps = o.steps_per_launch ? o.steps_per_launch : t.steps;
+        P.grid = o.grid_blocks ? o.grid_blocks : t.grid;
+    }
+    return P;
+}
+
+hipError_t enqueue(const Plan& P, int32_t n_steps, hipStream_t s) {
+    StepArgs a = P.a;
+    for (int32_t k0 = 0; k0 < n_steps; k0 += P.steps) {
+        a.k0 = k0;
+        a.step0 = P.a.step0 + k0;
+        a.n_steps = std::min(P.steps, n_steps - k0);
+        hipError_t e = launch_rollout(P.v, a, P.block, P.grid, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+std::vector<int64_t> graph_key(const Plan& P, int32_t n_steps, float dt) {
+    const StepArgs& a = P.a;
+    int32_t dtbits;
+    std::memcpy(&dtbits, &dt, 4);
+    return {(int64_t)a.rows, a.ld, a.n, (int64_t)a.type, (int64_t)a.perm, (int64_t)a.gains, a.gains_ld,
+            (int64_t)a.motor_cmd, (int64_t)a.wp, a.cmd_ld, a.n_epochs, a.resample, a.step0, n_steps,
+            dtbits, (int64_t)a.ckpt, a.ckpt_every, P.block, P.steps, P.grid, P.v.mode};
+}
+
+}  // namespace
+
+extern "C" {
+
+potato_status potato_create(potato_ctx** out, const potato_type_params* types, int32_t n_types,
+                            const potato_limits* limits, const potato_options* opts) {
+    if (!out) return fail(POTATO_EINVAL, "out is null");
+    *out = nullptr;
+    if (!types || !limits || !opts) return fail(POTATO_EINVAL, "types, limits and opts must be non-null");
+    if (n_types < 1 || n_types > POTATO_MAX_TYPES) return fail(POTATO_EINVAL, "n_types must be in [1, 256]");
+    for (int t = 0; t < n_types; ++t) {
+        potato_status s = check_type(types[t], t);
+        if (s != POTATO_OK) return s;
+    }
+    potato_status s = check_limits(*limits);
+    if (s != POTATO_OK) return s;
+    s = check_options(*opts);
+    if (s != POTATO_OK) return s;
+
+    potato_ctx* ctx = new (std::nothrow) potato_ctx();
+    if (!ctx) return fail(POTATO_ENOMEM, "host allocation failed");
+    ctx->n_types = n_types;
+    ctx->params.assign(types, types + n_types);
+    ctx->limits = *limits;
+    ctx->opts = *opts;
+    for (int t = 0; t < n_types; ++t) ctx->consts.push_back(derive(types[t], *limits));
+    /* rank of each type: longest budget first, ties by index */
+    std::vector<int32_t> order(n_types), rank(n_types);
+    for (int t = 0; t < n_types; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return types[a].step_budget > types[b].step_budget; });
+    for (int r = 0; r < n_types; ++r) rank[order[r]] = r;
+
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_table, sizeof(TypeConst) * n_types);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_rank, sizeof(int32_t) * n_types);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_table, ctx->consts.data(), sizeof(TypeConst) * n_types, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_rank, rank.data(), sizeof(int32_t) * n_types, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        potato_destroy(ctx);
+        return hip_fail(e, "potato_create");
+    }
+    *out = ctx;
+    return POTATO_OK;
+}
+
+potato_status potato_destroy(potato_ctx* ctx) {
+    if (!ctx) return POTATO_OK;
+    drop_graphs(ctx);
+    if (ctx->d_table) hipFree(ctx->d_table);
+    if (ctx->d_rank) hipFree(ctx->d_rank);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return POTATO_OK;
+}
+
+potato_status potato_set_options(potato_ctx* ctx, const potato_options* opts) {
+    if (!ctx || !opts) return fail(POTATO_EINVAL, "ctx and opts must be non-null");
+    potato_status s = check_options(*opts);
+    if (s != POTATO_OK) return s;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->opts = *opts;
+    drop_graphs(ctx);
+    return POTATO_OK;
+}
+
+potato_status potato_step(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                          const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
+                          float* ckpt, int32_t ckpt_every, void* stream) {
+    potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, n_steps, ckpt, ckpt_every);
+    if (s != POTATO_OK) return s;
+    if (n_steps == 0) return POTATO_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    Plan P = make_plan(ctx, state, params, cmds, dt, n_agents, ckpt, ckpt_every);
+    if (!ctx->opts.use_graph) {
+        hipError_t e = enqueue(P, n_steps, hs);
+        return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_step launch");
+    }
+    std::vector<int64_t> key = graph_key(P, n_steps, dt);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 64) drop_graphs(ctx);
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = enqueue(P, n_steps, ctx->cap_stream);
+        e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "potato_step capture"); }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        it = ctx->graphs.emplace(key, exec).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, hs);
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                              const potato_cmds* cmds, float dt, int64_t n_agents, int32_t probe_steps,
+                              potato_options* best, void* stream) {
+    potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, probe_steps, nullptr, 0);
+    if (s != POTATO_OK) return s;
+    if (probe_steps < 1) return fail(POTATO_EINVAL, "probe_steps must be >= 1");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(float) * kRows * (size_t)state->ld;
+    float* scratch = nullptr;
+    hipError_t e = hipMalloc(&scratch, bytes);
+    if (e != hipSuccess) return fail(POTATO_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(scratch, state->rows, bytes, hipMemcpyDeviceToDevice, hs);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    potato_state ss{scratch, state->ld};
+    int n_cu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    Tuned win{256, 100, 0};
+    double win_ms = 1e300;
+    const int blocks[] = {64, 128, 256, 512};
+    const int steps_opts[] = {25, 50, 100, 200};
+    const potato_options saved = ctx->opts;
+    ctx->opts.form = POTATO_FORM_FUSED;
+    for (int b : blocks) {
+        if (e != hipSuccess) break;
+        Plan P = make_plan(ctx, &ss, params, cmds, dt, n_agents, nullptr, 0);
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rollout_kernel(P.v), b,
+                                                         rollout_lds_bytes(P.v, ctx->n_types));
+        if (e != hipSuccess) break;
+        const int64_t full = (n_agents + b - 1) / b;
+        std::vector<int> grids = {0};
+        for (int mult : {1, 2}) {
+            const int64_t gsz = (int64_t)per_cu * n_cu * mult;
+            if (gsz > 0 && gsz < full) grids.push_back((int)gsz);
+        }
+        for (int S : steps_opts) {
+            for (int gsz : grids) {
+                P.block = b; P.steps = std::min(S, probe_steps); P.grid = gsz;
+                e = enqueue(P, P.steps, hs);                 /* warm-up */
+                if (e == hipSuccess) e = hipEventRecord(t0, hs);
+                if (e == hipSuccess) e = enqueue(P, probe_steps, hs);
+                if (e == hipSuccess) e = hipEventRecord(t1, hs);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) break;
+                if (ms < win_ms) { win_ms = ms; win = Tuned{b, P.steps, gsz}; }
+            }
+            if (e != hipSuccess) break;
+        }
+    }
+    ctx->opts = saved;
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+    hipStreamSynchronize(hs);
+    hipFree(scratch);
+    if (e != hipSuccess) return hip_fail(e, "potato_autotune");
+    const bool het = params->type != nullptr;
+    ctx->tuned[TuneKey{ctx->opts.mode, het, ctx->opts.mode == 1 && params->gains != nullptr,
+                       het && params->perm != nullptr}] = win;
+    drop_graphs(ctx);
+    if (best) {
+        *best = ctx->opts;
+        best->form = POTATO_FORM_FUSED;
+        best->block = win.block;
+        best->steps_per_launch = win.steps;
+        best->grid_blocks = win.grid;
+    }
+    return POTATO_OK;
+}
+
+namespace {
+
+/* Grid of the adjoint launch: enough resident blocks to fill the chip,
+ * never more than the agents need (one tape column per thread). */
+int adjoint_grid(potato_ctx* ctx, bool het, bool gains, bool perm, int64_t n) {
+    int per_cu = 0, n_cu = 0;
+    const size_t lds = het ? (size_t)ctx->n_types * sizeof(TypeConst) : 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adjoint_kernel(het, gains, perm), kAdjBlock, lds) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+        return -1;
+    int64_t resident = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
+    int64_t need = (n + kAdjBlock - 1) / kAdjBlock;
+    return (int)std::min(resident, need);
+}
+
+}  // namespace
+
+int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* params, int64_t n_agents,
+                                        int32_t ckpt_every) {
+    if (!ctx || !params || n_agents < 1 || ckpt_every < 1) return -1;
+    const bool het = params->type != nullptr;
+    const int grid = adjoint_grid(ctx, het, params->gains != nullptr, het && params->perm != nullptr, n_agents);
+    if (grid < 1) return -1;
+    return (int64_t)ckpt_every * 30 * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
+}
+
+potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params, const potato_cmds* cmds,
+                                   float dt, int64_t n_agents, int32_t n_steps, const float* ckpt,
+                                   int32_t ckpt_every, int64_t ld, const float* grad_final, float* grad_x0,
+                                   float* grad_gains, void* workspace, int64_t workspace_bytes, void* stream) {
+    if (!ctx || !params || !cmds) return fail(POTATO_EINVAL, "ctx, params and cmds must be non-null");
+    if (ctx->opts.mode != POTATO_CLOSED_LOOP)
+        return fail(POTATO_EUNSUPPORTED, "the adjoint is implemented for closed-loop rollouts");
+    if (!ckpt || !grad_final || !grad_x0 || !workspace)
+        return fail(POTATO_EINVAL, "ckpt, grad_final, grad_x0 and workspace must be non-null");
+    if (n_agents < 1 || n_agents > 0x7fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^31)");
+    if (ld < n_agents) return fail(POTATO_EINVAL, "ld < n_agents");
+    if (n_steps < 0) return fail(POTATO_EINVAL, "n_steps must be >= 0");
+    if (ckpt_every < 1) return fail(POTATO_EINVAL, "ckpt_every must be >= 1");
+    if (!std::isfinite(dt) || !(dt > 0.0f)) return fail(POTATO_EINVAL, "dt must be finite and > 0");
+    if (!cmds->wp || cmds->n_epochs < 1 || cmds->ld < n_agents || cmds->step0 < 0)
+        return fail(POTATO_EINVAL, "closed loop needs cmds.wp, n_epochs >= 1, cmds.ld >= n_agents, step0 >= 0");
+    if (params->gains && params->gains_ld < n_agents) return fail(POTATO_EINVAL, "params.gains_ld < n_agents");
+    if (!params->type && params->perm) return fail(POTATO_EUNSUPPORTED, "params.perm needs params.type");
+    const bool het = params->type != nullptr;
+    const bool gains = params->gains != nullptr;
+    const bool perm = het && params->perm != nullptr;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const int grid = adjoint_grid(ctx, het, gains, perm, n_agents);
+    if (grid < 1) return fail(POTATO_EHIP, "occupancy query failed");
+    const int64_t need = (int64_t)ckpt_every * 30 * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
+    if (workspace_bytes < need)
+        return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
+    AdjArgs a{};
+    a.ckpt = ckpt; a.ld = ld; a.n = n_agents;
+    a.type = params->type; a.perm = perm ? params->perm : nullptr;
+    a.gains = params->gains; a.gains_ld = params->gains_ld;
+    a.wp = cmds->wp; a.cmd_ld = cmds->ld; a.n_epochs = cmds->n_epochs; a.resample = cmds->resample_every;
+    a.step0 = cmds->step0; a.n_steps = n_steps; a.K = ckpt_every;
+    a.grad_final = grad_final; a.grad_x0 = grad_x0; a.grad_gains = grad_gains;
+    a.tape = reinterpret_cast<float*>(workspace); a.tape_ld = (int64_t)grid * kAdjBlock;
+    a.n_types = het ? ctx->n_types : 1; a.table = ctx->d_table;
+    a.lim = make_limits(ctx->limits, dt);
+    a.tc0 = ctx->consts[0];
+    hipError_t e = launch_adjoint(het, gains, perm, a, kAdjBlock, grid, reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_step_backward launch");
+}
+
+int64_t potato_order_workspace_bytes(int64_t n_agents, int32_t n_types) {
+    if (n_agents < 1 || n_types < 1 || n_types > POTATO_MAX_TYPES) return -1;
+    const int64_t nb = (n_agents + kOrderBlock - 1) / kOrderBlock;
+    return 2 * nb * n_types * (int64_t)sizeof(int32_t);
+}
+
+potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t n_agents, int32_t* perm,
+                                   void* workspace, int64_t workspace_bytes, void* stream) {
+    if (!ctx || !type || !perm || !workspace) return fail(POTATO_EINVAL, "ctx, type, perm and workspace must be non-null");
+    if (n_agents < 1 || n_agents > 0x7fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^31)");
+    const int64_t need = potato_order_workspace_bytes(n_agents, ctx->n_types);
+    if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
+    const int64_t nb = (n_agents + kOrderBlock - 1) / kOrderBlock;
+    int32_t* counts = reinterpret_cast<int32_t*>(workspace);
+    int32_t* base = counts + nb * ctx->n_types;
+    hipError_t e = launch_order_by_type(type, n_agents, ctx->n_types, ctx->d_rank, perm, counts, base,
+                                        reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_order_by_type");
+}
+
+const char* potato_last_error(void) { return g_err.c_str(); }
+
+const char* potato_version(void) { return "potato-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+/*
+ * kernels.h -- internal interface between the C ABI (abi.hip) and the
+ * gfx950 kernels (kernels.hip).  Not installed; not part of the ABI.
+ */
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "quad_step.h"
+
+namespace potato {
+
+constexpr int kRows = 37;   /* state rows per agent, see include/potato.h */
+
+/* Everything one rollout launch needs, passed by value as the kernel
+ * argument (uniform, lands in scalar registers). */
+struct StepArgs {
+    float* rows;                 /* [kRows][ld] */
+    int64_t ld;
+    int64_t n;                   /* agents (lanes) */
+    const uint8_t* type;         /* [ld] or null */
+    const int32_t* perm;         /* [n] or null */
+    const float* gains;          /* [9][gains_ld] or null */
+    int64_t gains_ld;
+    const float* motor_cmd;      /* [4][cmd_ld] */
+    const float* wp;             /* [n_epochs][3][cmd_ld] */
+    int64_t cmd_ld;
+    int32_t n_epochs;
+    int32_t resample;
+    int64_t step0;               /* global index of this launch's first step */
+    int32_t n_steps;             /* steps in this launch */
+    int32_t k0;                  /* call-relative index of this launch's first step */
+    float* ckpt;                 /* [slots][kRows][ld] or null */
+    int32_t ckpt_every;
+    int32_t n_types;
+    const TypeConst* table;      /* device [n_types] */
+    Limits lim;
+    TypeConst tc0;               /* type 0, read from the argument segment */
+};
+
+struct Variant {
+    int mode;        /* 0 open loop, 1 closed loop */
+    bool het;        /* per-agent type index, LDS table */
+    bool gains;      /* per-agent gains */
+    bool ckpt;       /* write checkpoints */
+    bool perm;       /* processing order */
+};
+
+/* Arguments of the adjoint (reverse sweep) launch. */
+struct AdjArgs {
+    const float* ckpt;           /* [slots][kRows][ld] from the forward call */
+    int64_t ld;
+    int64_t n;
+    const uint8_t* type;
+    const int32_t* perm;
+    const float* gains;
+    int64_t gains_ld;
+    const float* wp;
+    int64_t cmd_ld;
+    int32_t n_epochs;
+    int32_t resample;
+    int64_t step0;
+    int32_t n_steps;
+    int32_t K;                   /* checkpoint interval */
+    const float* grad_final;     /* [30][ld] */
+    float* grad_x0;              /* [30][ld] */
+    float* grad_gains;           /* [9][ld] or null */
+    float* tape;                 /* [K][30][tape_ld], one column per thread of the grid */
+    int64_t tape_ld;
+    int32_t n_types;
+    const TypeConst* table;
+    Limits lim;
+    TypeConst tc0;
+};
+
+/* Launch one rollout kernel (n_steps of args) on `stream`. */
+hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int grid_blocks,
+                          hipStream_t stream);
+
+/* Kernel function pointer of a variant (occupancy queries). */
+const void* rollout_kernel(const Variant& v);
+
+/* Adjoint: kernel pointer (occupancy queries) and launch on exactly
+ * grid_blocks x block threads (the tape has one column per thread). */
+const void* adjoint_kernel(bool het, bool gains, bool perm);
+hipError_t launch_adjoint(bool het, bool gains, bool perm, const AdjArgs& a, int block, int grid_blocks,
+                          hipStream_t stream);
+constexpr int kAdjBlock = 256;
+
+/* Dynamic LDS bytes the variant needs for n_types. */
+size_t rollout_lds_bytes(const Variant& v, int n_types);
+
+/* Processing order by type (see potato_order_by_type). */
+hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types,
+                                const int32_t* type_rank_dev, int32_t* perm,
+                                int32_t* block_counts, int32_t* block_base, hipStream_t stream);
+
+constexpr int kOrderBlock = 256;
+
+}  // namespace potato

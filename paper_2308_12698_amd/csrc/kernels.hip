@@ -1,0 +1,334 @@
+/*
+ * kernels.hip -- gfx950 kernels of the batched quadrotor step.
+ *
+ * k_rollout: one agent per lane, its 37-float state loaded once into
+ * registers (coalesced structure-of-arrays rows), advanced n_steps time
+ * steps, stored once.  With n_steps = 1 and one agent per thread this is
+ * the plain per-step form (HBM bound: the state round-trips every step);
+ * with many steps per launch it is the fused form (VALU bound).  A
+ * grid-stride loop lets a launch use a persistent grid.  Optional pieces
+ * are template switches so that the homogeneous path carries no per-agent
+ * type or gain traffic:
+ *   HET   per-agent type index; the type table is staged in LDS once per
+ *         block (the paper runs one process per type, Sec. II-A; here all
+ *         types share one launch);
+ *   GAINS per-agent controller gains;
+ *   CKPT  checkpoints every ckpt_every steps for the adjoint;
+ *   PERM  processing order (agents grouped by type).
+ * No MFMA: nothing in a quadrotor step is a dense contraction.
+ */
+#include "kernels.h"
+#include "quad_adjoint.h"
+
+namespace potato {
+
+namespace {
+
+template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
+__global__ void __launch_bounds__(512) k_rollout(const StepArgs A) {
+    extern __shared__ float4 lds_raw[];
+    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw);
+    if (HET) {
+        const int words = A.n_types * (int)(sizeof(TypeConst) / 4);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(A.table);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
+    const int64_t ld = A.ld;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.n; j += stride) {
+        const int64_t i = PERM ? (int64_t)A.perm[j] : j;
+        const TypeConst& c = HET ? tab[A.type[i]] : A.tc0;
+
+        int64_t left = (int64_t)c.budget - A.step0;
+        left = left < 0 ? 0 : left;
+        const int steps = left < A.n_steps ? (int)left : A.n_steps;
+        if (steps == 0) continue;
+
+        float* r = A.rows + i;
+        Agent a;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { a.p[k] = r[k * ld]; a.v[k] = r[(3 + k) * ld]; a.w[k] = r[(10 + k) * ld]; }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { a.q[k] = r[(6 + k) * ld]; a.d[k] = r[(13 + k) * ld]; }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { a.p_lo[k] = r[(30 + k) * ld]; a.v_lo[k] = r[(33 + k) * ld]; }
+        if (MODE == 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                a.ip[k] = r[(17 + k) * ld]; a.ia[k] = r[(20 + k) * ld];
+                a.ir[k] = r[(23 + k) * ld]; a.wprev[k] = r[(26 + k) * ld];
+            }
+            a.J = r[29 * ld];
+            a.J_lo = r[36 * ld];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) { a.ip[k] = a.ia[k] = a.ir[k] = a.wprev[k] = 0.0f; }
+            a.J = a.J_lo = 0.0f;
+        }
+
+        Gains g;
+        if (GAINS) {
+            const float* gp = A.gains + i;
+            const int64_t gl = A.gains_ld;
+            g = Gains{gp[0], gp[gl], gp[2 * gl], gp[3 * gl], gp[4 * gl],
+                      gp[5 * gl], gp[6 * gl], gp[7 * gl], gp[8 * gl]};
+        } else {
+            g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
+                      c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
+        }
+
+        float dc[4];
+        float wp[3];
+        int64_t next_epoch_step = INT64_MAX;
+        int epoch = 0;
+        if (MODE == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dc[k] = A.motor_cmd[k * A.cmd_ld + i];
+        } else {
+            if (A.resample > 0) {
+                const int64_t e0 = A.step0 / A.resample;
+                epoch = e0 < A.n_epochs - 1 ? (int)e0 : A.n_epochs - 1;
+                next_epoch_step = e0 < A.n_epochs - 1 ? (e0 + 1) * A.resample : INT64_MAX;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) wp[k] = A.wp[((int64_t)epoch * 3 + k) * A.cmd_ld + i];
+        }
+        int ck_next = 0, ck_slot = 0;
+        if (CKPT) {
+            ck_slot = (A.k0 + A.ckpt_every - 1) / A.ckpt_every;
+            ck_next = ck_slot * A.ckpt_every - A.k0;
+        }
+
+        for (int s = 0; s < steps; ++s) {
+            if (CKPT && s == ck_next) {
+                float* o = A.ckpt + (int64_t)ck_slot * kRows * ld + i;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    o[k * ld] = a.p[k]; o[(3 + k) * ld] = a.v[k]; o[(10 + k) * ld] = a.w[k];
+                    o[(17 + k) * ld] = a.ip[k]; o[(20 + k) * ld] = a.ia[k];
+                    o[(23 + k) * ld] = a.ir[k]; o[(26 + k) * ld] = a.wprev[k];
+                    o[(30 + k) * ld] = a.p_lo[k]; o[(33 + k) * ld] = a.v_lo[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { o[(6 + k) * ld] = a.q[k]; o[(13 + k) * ld] = a.d[k]; }
+                o[29 * ld] = a.J;
+                o[36 * ld] = a.J_lo;
+                ++ck_slot;
+                ck_next += A.ckpt_every;
+            }
+            if (MODE == 1) {
+                if (A.step0 + s == next_epoch_step) {
+                    ++epoch;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) wp[k] = A.wp[((int64_t)epoch * 3 + k) * A.cmd_ld + i];
+                    next_epoch_step = epoch < A.n_epochs - 1 ? next_epoch_step + A.resample : INT64_MAX;
+                }
+                controller(c, A.lim, g, a, wp, dc);
+            }
+            rk4_step(c, A.lim, a, dc);
+        }
+
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { r[k * ld] = a.p[k]; r[(3 + k) * ld] = a.v[k]; r[(10 + k) * ld] = a.w[k]; }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { r[(6 + k) * ld] = a.q[k]; r[(13 + k) * ld] = a.d[k]; }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { r[(30 + k) * ld] = a.p_lo[k]; r[(33 + k) * ld] = a.v_lo[k]; }
+        if (MODE == 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                r[(17 + k) * ld] = a.ip[k]; r[(20 + k) * ld] = a.ia[k];
+                r[(23 + k) * ld] = a.ir[k]; r[(26 + k) * ld] = a.wprev[k];
+            }
+            r[29 * ld] = a.J;
+            r[36 * ld] = a.J_lo;
+        }
+    }
+}
+
+/* Reverse sweep of the checkpointed closed-loop rollout: one agent per lane
+ * (grid-stride), cotangents and gain sums in registers, the recomputed
+ * segment in this thread's tape column. */
+template <bool HET, bool GAINS, bool PERM>
+__global__ void __launch_bounds__(kAdjBlock) k_adjoint(const AdjArgs A) {
+    extern __shared__ float4 lds_raw[];
+    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw);
+    if (HET) {
+        const int words = A.n_types * (int)(sizeof(TypeConst) / 4);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(A.table);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
+    const int64_t ld = A.ld;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    float* tape_col = A.tape + tid;
+    for (int64_t j = tid; j < A.n; j += stride) {
+        const int64_t i = PERM ? (int64_t)A.perm[j] : j;
+        const TypeConst& c = HET ? tab[A.type[i]] : A.tc0;
+        int64_t left = (int64_t)c.budget - A.step0;
+        left = left < 0 ? 0 : left;
+        const int steps = left < A.n_steps ? (int)left : A.n_steps;
+        Gains g;
+        if (GAINS) {
+            const float* gp = A.gains + i;
+            const int64_t gl = A.gains_ld;
+            g = Gains{gp[0], gp[gl], gp[2 * gl], gp[3 * gl], gp[4 * gl],
+                      gp[5 * gl], gp[6 * gl], gp[7 * gl], gp[8 * gl]};
+        } else {
+            g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
+                      c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
+        }
+        AgentAdj lam;
+        load_adj(A.grad_final + i, ld, lam);
+        float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (steps > 0)
+            agent_backward(c, A.lim, g, A.ckpt + i, ld, A.K, steps, A.step0, A.wp + i, A.cmd_ld,
+                           A.n_epochs, A.resample, tape_col, A.tape_ld, lam, gk);
+        store_adj(A.grad_x0 + i, ld, lam);
+        if (A.grad_gains) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) A.grad_gains[k * ld + i] = gk[k];
+        }
+    }
+}
+
+/* ---- processing order by type: block histograms, scan, stable scatter ---- */
+
+__global__ void __launch_bounds__(kOrderBlock) k_block_hist(const uint8_t* type, int64_t n, int n_types,
+                                                            int32_t* counts /* [T][nb] */) {
+    __shared__ int32_t h[256];
+    for (int t = threadIdx.x; t < n_types; t += blockDim.x) h[t] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[type[i]], 1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < n_types; t += blockDim.x) counts[(int64_t)t * gridDim.x + blockIdx.x] = h[t];
+}
+
+/* One block: exclusive scan of each type's block counts, then offsets of
+ * the types in rank order (rank 0 first). */
+__global__ void __launch_bounds__(kOrderBlock) k_scan(const int32_t* counts, int nb, int n_types,
+                                                      const int32_t* rank, int32_t* base) {
+    __shared__ int32_t buf[kOrderBlock];
+    __shared__ int32_t total[256];
+    __shared__ int32_t offset[256];
+    for (int t = 0; t < n_types; ++t) {
+        int32_t carry = 0;
+        for (int b0 = 0; b0 < nb; b0 += kOrderBlock) {
+            const int b = b0 + threadIdx.x;
+            const int32_t v = b < nb ? counts[(int64_t)t * nb + b] : 0;
+            buf[threadIdx.x] = v;
+            __syncthreads();
+            for (int off = 1; off < kOrderBlock; off <<= 1) {
+                const int32_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+                __syncthreads();
+                buf[threadIdx.x] += add;
+                __syncthreads();
+            }
+            if (b < nb) base[(int64_t)t * nb + b] = carry + buf[threadIdx.x] - v;
+            const int32_t chunk = buf[kOrderBlock - 1];
+            __syncthreads();
+            carry += chunk;
+        }
+        if (threadIdx.x == 0) total[t] = carry;
+        __syncthreads();
+    }
+    __shared__ int32_t by_rank[256];
+    for (int t = threadIdx.x; t < n_types; t += blockDim.x) by_rank[rank[t]] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int r = 0; r < n_types; ++r) {
+            const int t = by_rank[r];
+            offset[t] = run;
+            run += total[t];
+        }
+    }
+    __syncthreads();
+    for (int t = 0; t < n_types; ++t)
+        for (int b = threadIdx.x; b < nb; b += kOrderBlock) base[(int64_t)t * nb + b] += offset[t];
+}
+
+__global__ void __launch_bounds__(kOrderBlock) k_scatter(const uint8_t* type, int64_t n, const int32_t* base,
+                                                         int32_t* perm) {
+    __shared__ uint8_t ty[kOrderBlock];
+    const int64_t i = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
+    const uint8_t mine = i < n ? type[i] : 0;
+    ty[threadIdx.x] = mine;
+    __syncthreads();
+    if (i >= n) return;
+    int32_t rank = 0;
+    for (int j = 0; j < (int)threadIdx.x; ++j) rank += ty[j] == mine ? 1 : 0;
+    perm[base[(int64_t)mine * gridDim.x + blockIdx.x] + rank] = (int32_t)i;
+}
+
+template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
+const void* kfn() {
+    return reinterpret_cast<const void*>(&k_rollout<MODE, HET, GAINS, CKPT, PERM>);
+}
+
+}  // namespace
+
+const void* rollout_kernel(const Variant& v) {
+    /* open loop: gains and checkpoints do not apply */
+    if (v.mode == 0) {
+        if (!v.het) return kfn<0, false, false, false, false>();
+        return v.perm ? kfn<0, true, false, false, true>() : kfn<0, true, false, false, false>();
+    }
+#define POTATO_PICK(H, P)                                                                   \
+    if (v.gains) return v.ckpt ? kfn<1, H, true, true, P>() : kfn<1, H, true, false, P>(); \
+    return v.ckpt ? kfn<1, H, false, true, P>() : kfn<1, H, false, false, P>();
+    if (!v.het) { POTATO_PICK(false, false) }
+    if (v.perm) { POTATO_PICK(true, true) }
+    POTATO_PICK(true, false)
+#undef POTATO_PICK
+}
+
+template <bool H, bool G, bool P>
+const void* afn() {
+    return reinterpret_cast<const void*>(&k_adjoint<H, G, P>);
+}
+
+const void* adjoint_kernel(bool het, bool gains, bool perm) {
+    if (!het) return gains ? afn<false, true, false>() : afn<false, false, false>();
+    if (perm) return gains ? afn<true, true, true>() : afn<true, false, true>();
+    return gains ? afn<true, true, false>() : afn<true, false, false>();
+}
+
+hipError_t launch_adjoint(bool het, bool gains, bool perm, const AdjArgs& a, int block, int grid_blocks,
+                          hipStream_t stream) {
+    void* args[] = {const_cast<AdjArgs*>(&a)};
+    const size_t lds = het ? (size_t)a.n_types * sizeof(TypeConst) : 0;
+    return hipLaunchKernel(adjoint_kernel(het, gains, perm), dim3((unsigned)grid_blocks), dim3((unsigned)block),
+                           args, lds, stream);
+}
+
+size_t rollout_lds_bytes(const Variant& v, int n_types) {
+    return v.het ? (size_t)n_types * sizeof(TypeConst) : 0;
+}
+
+hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int grid_blocks,
+                          hipStream_t stream) {
+    const void* fn = rollout_kernel(v);
+    int64_t grid = grid_blocks > 0 ? grid_blocks : (a.n + block - 1) / block;
+    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    void* args[] = {const_cast<StepArgs*>(&a)};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)block), args,
+                           rollout_lds_bytes(v, a.n_types), stream);
+}
+
+hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types, const int32_t* rank,
+                                int32_t* perm, int32_t* block_counts, int32_t* block_base,
+                                hipStream_t stream) {
+    const int nb = (int)((n + kOrderBlock - 1) / kOrderBlock);
+    hipLaunchKernelGGL(k_block_hist, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, block_counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kOrderBlock), 0, stream, block_counts, nb, n_types, rank, block_base);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, block_base, perm);
+    return hipGetLastError();
+}
+
+}  // namespace potato

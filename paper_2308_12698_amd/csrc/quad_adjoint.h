@@ -1,0 +1,475 @@
+/*
+ * quad_adjoint.h -- hand-written reverse mode (vector-Jacobian product) of
+ * one quadrotor time step, FP32, one agent per lane.
+ *
+ * Forward step (quad_step.h): controller -> held rotor command dc; classical
+ * RK4 over v, q, w, d (and p, J, which only integrate) with dc held;
+ * quaternion renormalisation.  step_vjp() recomputes the forward
+ * intermediates of one step from its step-start state and then applies the
+ * transposed derivatives in reverse order:
+ *     renormalisation -> RK4 stages 4, 3, 2, 1 -> controller.
+ * Non-smooth points take the derivative of the branch the forward pass
+ * took: a clamp passes the cotangent inside its interval and stops it
+ * outside; the error-quaternion sign is a constant; sqrt'(0) is taken as 0.
+ * The rounding carries of the forward integrator are not differentiated
+ * (the represented value is row + carry, so both have the same cotangent).
+ */
+#pragma once
+
+#include "quad_step.h"
+
+namespace potato {
+
+/* Cotangents of the 30 physical state rows. */
+struct AgentAdj {
+    float p[3], v[3], q[4], w[3], d[4], J;
+    float ip[3], ia[3], ir[3], wprev[3];
+};
+
+/* Cotangent of the integrated rates of (v, q, w, d, J); the position rate
+ * is v itself and is folded in by the caller. */
+struct RateAdj {
+    float v[3], q[4], w[3], d[4], J;
+};
+
+/* Dynamic part of the state seen by the right-hand side. */
+struct Dyn {
+    float v[3], q[4], w[3], d[4];
+};
+
+/* Transpose of the Jacobian of derivative() at y, applied to mu.  Adds the
+ * state cotangent to (lv, lq, lw, ld) and the command cotangent to ldc. */
+__device__ __forceinline__ void derivative_vjp(const TypeConst& c, const Dyn& y, const RateAdj& mu,
+                                               float lv[3], float lq[4], float lw[3], float ld[4],
+                                               float ldc[4]) {
+    const float* q = y.q;
+    const float* w = y.w;
+    float s[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = y.d[i] * (c.two_w + y.d[i]);
+    const float ssum = (s[0] + s[1]) + (s[2] + s[3]);
+    const float ftm = c.F0 + c.kf_m * ssum;
+    const float x2y2 = q[1] * q[1] + q[2] * q[2];
+    const float bx = 2.0f * (q[1] * q[3] + q[0] * q[2]);
+    const float by = 2.0f * (q[2] * q[3] - q[0] * q[1]);
+
+    /* translational part */
+    const float l_ftm = mu.v[0] * bx + mu.v[1] * by - 2.0f * mu.v[2] * x2y2;
+    float l_ssum = c.kf_m * (l_ftm + mu.v[2]) + mu.J;
+    const float l_bx = mu.v[0] * ftm, l_by = mu.v[1] * ftm, l_x2y2 = -2.0f * ftm * mu.v[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) lv[i] -= c.cd_m * mu.v[i];
+    lq[0] += 2.0f * (q[2] * l_bx - q[1] * l_by);
+    lq[1] += 2.0f * (q[3] * l_bx - q[0] * l_by + q[1] * l_x2y2);
+    lq[2] += 2.0f * (q[0] * l_bx + q[3] * l_by + q[2] * l_x2y2);
+    lq[3] += 2.0f * (q[1] * l_bx + q[2] * l_by);
+
+    /* quaternion kinematics q' = 1/2 q o (0, w) */
+    const float* m = mu.q;
+    lq[0] += 0.5f * (w[0] * m[1] + w[1] * m[2] + w[2] * m[3]);
+    lq[1] += 0.5f * (-w[0] * m[0] - w[2] * m[2] + w[1] * m[3]);
+    lq[2] += 0.5f * (-w[1] * m[0] + w[2] * m[1] - w[0] * m[3]);
+    lq[3] += 0.5f * (-w[2] * m[0] - w[1] * m[1] + w[0] * m[2]);
+    lw[0] += 0.5f * (-q[1] * m[0] + q[0] * m[1] + q[3] * m[2] - q[2] * m[3]);
+    lw[1] += 0.5f * (-q[2] * m[0] - q[3] * m[1] + q[0] * m[2] + q[1] * m[3]);
+    lw[2] += 0.5f * (-q[3] * m[0] + q[2] * m[1] - q[1] * m[2] + q[0] * m[3]);
+
+    /* Euler's equations: w' = I^-1 (tau - w x I w) */
+    const float a0 = c.iIx * mu.w[0], a1 = c.iIy * mu.w[1], a2 = c.iIz * mu.w[2];
+    const float gzy = c.Iz - c.Iy, gxz = c.Ix - c.Iz, gyx = c.Iy - c.Ix;
+    lw[0] -= a1 * gxz * w[2] + a2 * gyx * w[1];
+    lw[1] -= a0 * gzy * w[2] + a2 * gyx * w[0];
+    lw[2] -= a0 * gzy * w[1] + a1 * gxz * w[0];
+
+    /* rotor model and allocation (eqs. 2, 3) through s_i = W_i^2 - w_ref^2 */
+    const float tX = c.kf_ls * a0, tY = c.kf_lc * a1, tZ = c.km * a2;
+    const float ls0 = tX - tY + tZ + l_ssum;
+    const float ls1 = -tX - tY - tZ + l_ssum;
+    const float ls2 = -tX + tY + tZ + l_ssum;
+    const float ls3 = tX + tY - tZ + l_ssum;
+    const float lsv[4] = {ls0, ls1, ls2, ls3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        ld[i] += lsv[i] * 2.0f * (c.w_ref + y.d[i]) - c.inv_tau * mu.d[i];
+        ldc[i] += c.inv_tau * mu.d[i];
+    }
+}
+
+/* Rates of the dynamic part (same arithmetic as the forward step). */
+__device__ __forceinline__ void dyn_rate(const TypeConst& c, const Dyn& y, const float dc[4], Dyn& k,
+                                         float& kJ) {
+    derivative(c, y.v, y.q, y.w, y.d, dc, k.v, k.q, k.w, k.d, kJ);
+}
+
+__device__ __forceinline__ void dyn_axpy(const Dyn& x, float h, const Dyn& k, Dyn& out) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { out.v[i] = x.v[i] + h * k.v[i]; out.w[i] = x.w[i] + h * k.w[i]; }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { out.q[i] = x.q[i] + h * k.q[i]; out.d[i] = x.d[i] + h * k.d[i]; }
+}
+
+/*
+ * Reverse of one step.  `a` is the step-start state (as the forward pass
+ * saw it), wp the waypoint of this step, k the gains.  lam holds the
+ * cotangent of the step-end state on entry and of the step-start state on
+ * return; gk accumulates the gain cotangents.
+ */
+__device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, const Gains& k,
+                                         const Agent& a, const float wp[3], AgentAdj& lam,
+                                         float gk[9]) {
+    /* ---------------- controller, forward with intermediates ---------------- */
+    float er[3] = {wp[0] - a.p[0], wp[1] - a.p[1], wp[2] - a.p[2]};
+    const float n2 = er[0] * er[0] + er[1] * er[1] + er[2] * er[2];
+    const bool sat = n2 > L.r_sat2;
+    float rs = 0.0f, sc = 1.0f;
+    if (sat) { rs = rsq(n2); sc = L.r_sat * rs; }
+    const float e[3] = {er[0] * sc, er[1] * sc, er[2] * sc};
+    float ipn[3];
+    bool in_ip[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float pre = a.ip[i] + e[i] * L.dt;
+        in_ip[i] = !(pre < -L.ipos_max) && !(pre > L.ipos_max);
+        ipn[i] = clampf_(pre, -L.ipos_max, L.ipos_max);
+    }
+    float acc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] = k.kpp * e[i] + k.kip * ipn[i] - k.kdp * a.v[i];
+    acc[2] += L.g;
+    const bool az_cl = acc[2] < L.az_min;
+    if (az_cl) acc[2] = L.az_min;
+    float bz[3];
+    body_z(a.q, bz);
+    const float fc = c.mass * (acc[0] * bz[0] + acc[1] * bz[1] + acc[2] * bz[2]);
+    const float ra = rsq(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+    const float nv[3] = {acc[0] * ra, acc[1] * ra, acc[2] * ra};
+    const float qr0 = 1.0f + nv[2], qr1 = -nv[1], qr2 = nv[0];
+    const float rq = rsq(qr0 * qr0 + qr1 * qr1 + qr2 * qr2);
+    const float qd[3] = {qr0 * rq, qr1 * rq, qr2 * rq};
+    const float* q = a.q;
+    const float qew = q[0] * qd[0] + q[1] * qd[1] + q[2] * qd[2];
+    const float qex = q[0] * qd[1] - q[1] * qd[0] + q[3] * qd[2];
+    const float qey = q[0] * qd[2] - q[2] * qd[0] - q[3] * qd[1];
+    const float qez = q[2] * qd[1] - q[1] * qd[2] - q[3] * qd[0];
+    const float sg = qew < 0.0f ? -2.0f : 2.0f;
+    const float eatt[3] = {sg * qex, sg * qey, sg * qez};
+    float ian[3], irn[3], wdes[3], erate[3], alpha[3];
+    bool in_ia[3], in_ir[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float pa = a.ia[i] + eatt[i] * L.dt;
+        in_ia[i] = !(pa < -L.iatt_max) && !(pa > L.iatt_max);
+        ian[i] = clampf_(pa, -L.iatt_max, L.iatt_max);
+        wdes[i] = k.kpa * eatt[i] + k.kia * ian[i] - k.kda * a.w[i];
+        erate[i] = wdes[i] - a.w[i];
+        const float pr = a.ir[i] + erate[i] * L.dt;
+        in_ir[i] = !(pr < -L.irate_max) && !(pr > L.irate_max);
+        irn[i] = clampf_(pr, -L.irate_max, L.irate_max);
+        alpha[i] = k.kpr * erate[i] + k.kir * irn[i] - k.kdr * ((a.w[i] - a.wprev[i]) * L.inv_dt);
+    }
+    const float Iwx = c.Ix * a.w[0], Iwy = c.Iy * a.w[1], Iwz = c.Iz * a.w[2];
+    const float tx = c.Ix * alpha[0] + (a.w[1] * Iwz - a.w[2] * Iwy);
+    const float ty = c.Iy * alpha[1] + (a.w[2] * Iwx - a.w[0] * Iwz);
+    const float tz = c.Iz * alpha[2] + (a.w[0] * Iwy - a.w[1] * Iwx);
+    const float f4 = 0.25f * fc;
+    const float X = tx * c.mix_x, Y = ty * c.mix_y, Z = tz * c.mix_z;
+    const float f[4] = {f4 + X - Y + Z, f4 - X - Y - Z, f4 - X + Y + Z, f4 + X + Y - Z};
+    float dc[4], lf_scale[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool in_f = !(f[i] < 0.0f) && !(f[i] > c.f_max);
+        const float fi = clampf_(f[i], 0.0f, c.f_max);
+        const float W = sqrt_fast(fi * c.inv_kf);
+        dc[i] = W - c.w_ref;
+        /* d W / d f = inv_kf / (2 W), zero when clamped or W == 0 */
+        lf_scale[i] = (in_f && W > 0.0f) ? 0.5f * c.inv_kf / W : 0.0f;
+    }
+
+    /* ---------------- RK4 forward, keeping the stage states ---------------- */
+    Dyn y1, y2, y3, y4, kk;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { y1.v[i] = a.v[i]; y1.w[i] = a.w[i]; }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { y1.q[i] = a.q[i]; y1.d[i] = a.d[i]; }
+    float kJ;
+    dyn_rate(c, y1, dc, kk, kJ);
+    dyn_axpy(y1, L.half_dt, kk, y2);
+    Dyn acc_q;   /* sum of weighted rates, only q is needed (renormalisation) */
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc_q.q[i] = kk.q[i];
+    dyn_rate(c, y2, dc, kk, kJ);
+    dyn_axpy(y1, L.half_dt, kk, y3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc_q.q[i] += 2.0f * kk.q[i];
+    dyn_rate(c, y3, dc, kk, kJ);
+    dyn_axpy(y1, L.dt, kk, y4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc_q.q[i] += 2.0f * kk.q[i];
+    dyn_rate(c, y4, dc, kk, kJ);
+    float qn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) qn[i] = a.q[i] + L.dt6 * (acc_q.q[i] + kk.q[i]);
+
+    /* ---------------- reverse: renormalisation ---------------- */
+    {
+        const float r = rsq(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+        const float u[4] = {qn[0] * r, qn[1] * r, qn[2] * r, qn[3] * r};
+        const float dot = u[0] * lam.q[0] + u[1] * lam.q[1] + u[2] * lam.q[2] + u[3] * lam.q[3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lam.q[i] = r * (lam.q[i] - u[i] * dot);
+    }
+
+    /* ---------------- reverse: RK4 ----------------
+     * lam (v, q, w, d) is the cotangent of the step-end dynamic state; the
+     * stage rate cotangents are b_i * dt * lam + dt * (cotangent of the next
+     * stage state), with b = 1/6, 1/3, 1/3, 1/6.  Position and cost only
+     * integrate, so their cotangents pass through unchanged and enter each
+     * stage as b_i * dt * lam.p (on the stage velocity) and b_i * dt * lam.J. */
+    const AgentAdj lo = lam;                 /* cotangent of the step end */
+    float ldc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float sv[3], sq[4], sw[3], sd[4];        /* running stage-state cotangent */
+    const float bw[4] = {L.dt6, 2.0f * L.dt6, 2.0f * L.dt6, L.dt6};
+    const float hs[4] = {0.0f, L.half_dt, L.half_dt, L.dt};   /* stage offsets */
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { sv[i] = 0.0f; sw[i] = 0.0f; }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { sq[i] = 0.0f; sd[i] = 0.0f; }
+#pragma unroll
+    for (int st = 3; st >= 0; --st) {
+        /* cotangent of this stage's rate: b dt lam_end + h_{next} lam_{next stage} */
+        const float hn = st < 3 ? hs[st + 1] : 0.0f;
+        RateAdj mu;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mu.v[i] = bw[st] * lo.v[i] + hn * sv[i];
+            mu.w[i] = bw[st] * lo.w[i] + hn * sw[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            mu.q[i] = bw[st] * lo.q[i] + hn * sq[i];
+            mu.d[i] = bw[st] * lo.d[i] + hn * sd[i];
+        }
+        mu.J = bw[st] * lo.J;
+        const Dyn& ys = st == 3 ? y4 : (st == 2 ? y3 : (st == 1 ? y2 : y1));
+        float nv_[3], nq_[4], nw_[3], nd_[4];
+        /* position rate is the stage velocity */
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { nv_[i] = bw[st] * lo.p[i]; nw_[i] = 0.0f; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { nq_[i] = 0.0f; nd_[i] = 0.0f; }
+        derivative_vjp(c, ys, mu, nv_, nq_, nw_, nd_, ldc);
+        /* stage state = y1 + h_st * previous rate: cotangent flows to y1 and
+         * (scaled by h_st) to the previous stage's rate */
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sv[i] = nv_[i]; sw[i] = nw_[i];
+            lam.v[i] += nv_[i]; lam.w[i] += nw_[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            sq[i] = nq_[i]; sd[i] = nd_[i];
+            lam.q[i] += nq_[i]; lam.d[i] += nd_[i];
+        }
+    }
+
+    /* ---------------- reverse: controller ---------------- */
+    float lf[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lf[i] = ldc[i] * lf_scale[i];
+    const float l_f4 = lf[0] + lf[1] + lf[2] + lf[3];
+    const float l_X = lf[0] - lf[1] - lf[2] + lf[3];
+    const float l_Y = -lf[0] - lf[1] + lf[2] + lf[3];
+    const float l_Z = lf[0] - lf[1] + lf[2] - lf[3];
+    const float l_fc = 0.25f * l_f4;
+    const float ltx = c.mix_x * l_X, lty = c.mix_y * l_Y, ltz = c.mix_z * l_Z;
+    const float lal[3] = {c.Ix * ltx, c.Iy * lty, c.Iz * ltz};
+    /* gyroscopic feed-forward w x (I w) */
+    {
+        const float gzy = c.Iz - c.Iy, gxz = c.Ix - c.Iz, gyx = c.Iy - c.Ix;
+        lam.w[0] += lty * gxz * a.w[2] + ltz * gyx * a.w[1];
+        lam.w[1] += ltx * gzy * a.w[2] + ltz * gyx * a.w[0];
+        lam.w[2] += ltx * gzy * a.w[1] + lty * gxz * a.w[0];
+    }
+    float l_eatt[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        /* w_prev <- w */
+        lam.w[i] += lo.wprev[i];
+        /* rate loop */
+        const float dwd = (a.w[i] - a.wprev[i]) * L.inv_dt;
+        gk[6] += lal[i] * erate[i];
+        gk[7] += lal[i] * irn[i];
+        gk[8] -= lal[i] * dwd;
+        float l_er = k.kpr * lal[i];
+        const float l_irn = lo.ir[i] + k.kir * lal[i];
+        lam.w[i] -= k.kdr * L.inv_dt * lal[i];
+        lam.wprev[i] = k.kdr * L.inv_dt * lal[i];
+        const float l_irpre = in_ir[i] ? l_irn : 0.0f;
+        lam.ir[i] = l_irpre;
+        l_er += L.dt * l_irpre;
+        /* erate = wdes - w */
+        const float l_wd = l_er;
+        lam.w[i] -= l_er;
+        /* attitude loop */
+        gk[3] += l_wd * eatt[i];
+        gk[4] += l_wd * ian[i];
+        gk[5] -= l_wd * a.w[i];
+        const float l_ian = lo.ia[i] + k.kia * l_wd;
+        lam.w[i] -= k.kda * l_wd;
+        const float l_iapre = in_ia[i] ? l_ian : 0.0f;
+        lam.ia[i] = l_iapre;
+        l_eatt[i] = k.kpa * l_wd + L.dt * l_iapre;
+    }
+    /* error quaternion (the sign is a constant of the branch) */
+    const float lex = sg * l_eatt[0], ley = sg * l_eatt[1], lez = sg * l_eatt[2];
+    lam.q[0] += lex * qd[1] + ley * qd[2];
+    lam.q[1] += -lex * qd[0] - lez * qd[2];
+    lam.q[2] += -ley * qd[0] + lez * qd[1];
+    lam.q[3] += lex * qd[2] - ley * qd[1] - lez * qd[0];
+    const float lqd[3] = {-lex * q[1] - ley * q[2] - lez * q[3],
+                          lex * q[0] - ley * q[3] + lez * q[2],
+                          lex * q[3] + ley * q[0] - lez * q[1]};
+    /* normalisation of the desired-attitude quaternion */
+    const float dqd = qd[0] * lqd[0] + qd[1] * lqd[1] + qd[2] * lqd[2];
+    const float lqr0 = rq * (lqd[0] - qd[0] * dqd);
+    const float lqr1 = rq * (lqd[1] - qd[1] * dqd);
+    const float lqr2 = rq * (lqd[2] - qd[2] * dqd);
+    /* q_raw = (1 + n_z, -n_y, n_x, 0) */
+    const float ln[3] = {lqr2, -lqr1, lqr0};
+    const float dn = nv[0] * ln[0] + nv[1] * ln[1] + nv[2] * ln[2];
+    float la[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) la[i] = ra * (ln[i] - nv[i] * dn) + c.mass * l_fc * bz[i];
+    /* body z axis used for the collective thrust */
+    {
+        const float m0 = c.mass * l_fc;
+        const float lb0 = m0 * acc[0], lb1 = m0 * acc[1], lb2 = m0 * acc[2];
+        lam.q[0] += 2.0f * (q[2] * lb0 - q[1] * lb1);
+        lam.q[1] += 2.0f * (q[3] * lb0 - q[0] * lb1) - 4.0f * q[1] * lb2;
+        lam.q[2] += 2.0f * (q[0] * lb0 + q[3] * lb1) - 4.0f * q[2] * lb2;
+        lam.q[3] += 2.0f * (q[1] * lb0 + q[2] * lb1);
+    }
+    if (az_cl) la[2] = 0.0f;
+    /* position loop */
+    float l_e[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gk[0] += la[i] * e[i];
+        gk[1] += la[i] * ipn[i];
+        gk[2] -= la[i] * a.v[i];
+        lam.v[i] -= k.kdp * la[i];
+        const float l_ipn = lo.ip[i] + k.kip * la[i];
+        const float l_ippre = in_ip[i] ? l_ipn : 0.0f;
+        lam.ip[i] = l_ippre;
+        l_e[i] = k.kpp * la[i] + L.dt * l_ippre;
+    }
+    /* saturation e = r_sat * er / |er| */
+    if (sat) {
+        const float u[3] = {er[0] * rs, er[1] * rs, er[2] * rs};
+        const float du = u[0] * l_e[0] + u[1] * l_e[1] + u[2] * l_e[2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) l_e[i] = sc * (l_e[i] - u[i] * du);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) lam.p[i] -= l_e[i];
+}
+
+/* Waypoint of global step `k` (epoch min(k / resample, n_epochs - 1)). */
+__device__ __forceinline__ void waypoint_at(const float* wp_col, int64_t cmd_ld, int n_epochs, int resample,
+                                            int64_t k, float wp[3]) {
+    int64_t ep = resample > 0 ? k / resample : 0;
+    ep = ep < n_epochs - 1 ? ep : n_epochs - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) wp[i] = wp_col[(ep * 3 + i) * cmd_ld];
+}
+
+__device__ __forceinline__ void load_rows(const float* r, int64_t ld, Agent& a, bool carries) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.p[k] = r[k * ld]; a.v[k] = r[(3 + k) * ld]; a.w[k] = r[(10 + k) * ld];
+        a.ip[k] = r[(17 + k) * ld]; a.ia[k] = r[(20 + k) * ld];
+        a.ir[k] = r[(23 + k) * ld]; a.wprev[k] = r[(26 + k) * ld];
+        a.p_lo[k] = carries ? r[(30 + k) * ld] : 0.0f;
+        a.v_lo[k] = carries ? r[(33 + k) * ld] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { a.q[k] = r[(6 + k) * ld]; a.d[k] = r[(13 + k) * ld]; }
+    a.J = r[29 * ld];
+    a.J_lo = carries ? r[36 * ld] : 0.0f;
+}
+
+/* The 30 physical rows (the tape does not need the carries). */
+__device__ __forceinline__ void store_phys_rows(float* r, int64_t ld, const Agent& a) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r[k * ld] = a.p[k]; r[(3 + k) * ld] = a.v[k]; r[(10 + k) * ld] = a.w[k];
+        r[(17 + k) * ld] = a.ip[k]; r[(20 + k) * ld] = a.ia[k];
+        r[(23 + k) * ld] = a.ir[k]; r[(26 + k) * ld] = a.wprev[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { r[(6 + k) * ld] = a.q[k]; r[(13 + k) * ld] = a.d[k]; }
+    r[29 * ld] = a.J;
+}
+
+__device__ __forceinline__ void load_adj(const float* r, int64_t ld, AgentAdj& l) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        l.p[k] = r[k * ld]; l.v[k] = r[(3 + k) * ld]; l.w[k] = r[(10 + k) * ld];
+        l.ip[k] = r[(17 + k) * ld]; l.ia[k] = r[(20 + k) * ld];
+        l.ir[k] = r[(23 + k) * ld]; l.wprev[k] = r[(26 + k) * ld];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { l.q[k] = r[(6 + k) * ld]; l.d[k] = r[(13 + k) * ld]; }
+    l.J = r[29 * ld];
+}
+
+__device__ __forceinline__ void store_adj(float* r, int64_t ld, const AgentAdj& l) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r[k * ld] = l.p[k]; r[(3 + k) * ld] = l.v[k]; r[(10 + k) * ld] = l.w[k];
+        r[(17 + k) * ld] = l.ip[k]; r[(20 + k) * ld] = l.ia[k];
+        r[(23 + k) * ld] = l.ir[k]; r[(26 + k) * ld] = l.wprev[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { r[(6 + k) * ld] = l.q[k]; r[(13 + k) * ld] = l.d[k]; }
+    r[29 * ld] = l.J;
+}
+
+/*
+ * Reverse sweep of one agent's closed-loop rollout of `steps` steps from
+ * global step step0.  Checkpoint slot s (37 rows, column ckpt_col, stride
+ * ld) holds the state before call-relative step s*K.  Each segment is
+ * recomputed forward from its checkpoint with the step-start states written
+ * to this agent's tape column (K slots of 30 rows, stride tape_ld), then
+ * reversed step by step.  lam: cotangent of the final state on entry, of
+ * the initial state on return; gk accumulates the gain cotangents.
+ */
+__device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits& L, const Gains& g,
+                                               const float* ckpt_col, int64_t ld, int K, int steps,
+                                               int64_t step0, const float* wp_col, int64_t cmd_ld,
+                                               int n_epochs, int resample, float* tape_col,
+                                               int64_t tape_ld, AgentAdj& lam, float gk[9]) {
+    const int n_seg = (steps + K - 1) / K;
+    for (int seg = n_seg - 1; seg >= 0; --seg) {
+        const int k_begin = seg * K;
+        const int len = steps - k_begin < K ? steps - k_begin : K;
+        Agent a;
+        load_rows(ckpt_col + (int64_t)seg * 37 * ld, ld, a, true);
+        for (int s = 0; s < len; ++s) {
+            store_phys_rows(tape_col + (int64_t)s * 30 * tape_ld, tape_ld, a);
+            float wp[3], dc[4];
+            waypoint_at(wp_col, cmd_ld, n_epochs, resample, step0 + k_begin + s, wp);
+            controller(c, L, g, a, wp, dc);
+            rk4_step(c, L, a, dc);
+        }
+        for (int s = len - 1; s >= 0; --s) {
+            Agent x;
+            load_rows(tape_col + (int64_t)s * 30 * tape_ld, tape_ld, x, false);
+            float wp[3];
+            waypoint_at(wp_col, cmd_ld, n_epochs, resample, step0 + k_begin + s, wp);
+            step_vjp(c, L, g, x, wp, lam, gk);
+        }
+    }
+}
+
+}  // namespace potato

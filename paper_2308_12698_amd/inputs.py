@@ -11,7 +11,7 @@ The paper benchmarks a batch of identical nonlinear quadrotors flying under
 a PID body-rate controller (Sec. III, Table I and Fig. "run_time"); it
 publishes no dataset, so every workload here is synthetic.
 
-State layout (structure of arrays, ``float32[30][ld]``, one column per agent):
+State layout (structure of arrays, ``float32[37][ld]``, one column per agent):
 
 ====== ===================================================================
 rows   meaning
@@ -27,6 +27,7 @@ rows   meaning
 23-25  rate-loop integral
 26-28  body rates at the previous control step (rate-loop derivative)
 29     running cost J = integral of the sum of squared rotor speeds
+30-36  rounding carries of position, velocity and J (zero in a fresh state)
 ====== ===================================================================
 """
 from __future__ import annotations
@@ -36,7 +37,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-N_ROWS = 30
+N_ROWS = 37
+N_PHYS_ROWS = 30   # rows with a physical meaning; the rest are FP32 carries
 N_GAINS = 9
 SEED_BASE = 12698
 
@@ -73,7 +75,7 @@ class Swarm:
     mode: int                      # 0 open loop (motor commands), 1 closed loop
     dt: float
     n_steps: int
-    state: np.ndarray              # [30, N]
+    state: np.ndarray              # [37, N]
     types: list                    # list of dicts, float32 scalars + gains + budget
     glob: dict                     # controller limits, float32 scalars
     type_idx: np.ndarray | None = None     # uint8 [N]
@@ -194,15 +196,14 @@ def hetero_types(n_types: int = 8, seed_stream: int = 0) -> list:
 def config3(scale: int = 1, counts=HETERO_COUNTS) -> Swarm:
     """Heterogeneous swarm: 8 types with uneven counts and step budgets.
 
-    ``scale`` divides every count (for small parity cases).  Counts are
-    assigned to types by a seeded permutation and the per-agent type labels
-    are shuffled, so neighbouring agents generally differ in type.
+    Type t has counts[t] agents and a budget of 1000*(t+1) steps; ``scale``
+    divides every count (for small parity cases).  The per-agent type labels
+    are shuffled (seeded), so neighbouring agents generally differ in type.
     """
     r = rng(3, 1)
     types = hetero_types()
     counts = [max(1, c // scale) for c in counts]
-    perm = r.permutation(len(types))
-    labels = np.concatenate([np.full(c, perm[i], dtype=np.uint8) for i, c in enumerate(counts)])
+    labels = np.concatenate([np.full(c, t, dtype=np.uint8) for t, c in enumerate(counts)])
     r.shuffle(labels)
     n = labels.size
     state = hover_state(_box_positions(r, n))
@@ -212,7 +213,7 @@ def config3(scale: int = 1, counts=HETERO_COUNTS) -> Swarm:
     wp = f32(np.stack([_box_positions(r, n) for _ in range(n_ep)]))
     return Swarm("hetero", 1, 1e-3, n_steps, state, types, globals_f32(),
                  type_idx=labels, wp=wp, resample_every=2000,
-                 extra=dict(counts=counts, type_of_count=perm))
+                 extra=dict(counts=counts))
 
 
 def config4(n: int = 65536, n_steps: int = 500, dt: float = 2e-3) -> Swarm:

@@ -1,0 +1,193 @@
+"""Torch-facing binding of the C ABI: device tensors in, pointers out.
+
+PyTorch supplies device memory and the current stream; every step of the
+simulation runs in the HIP kernels of ``libpotato.so``.  Nothing here
+computes any part of the method.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+N_ROWS = 37            # state rows per agent (include/potato.h)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_rows(name, t, rows, n, dtype=torch.float32):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.shape[0] != rows or t.stride(1) != 1 or t.shape[1] < n:
+        raise ValueError(f"{name} must be [{rows}, >= {n}] with unit column stride, got "
+                         f"{tuple(t.shape)} strides {t.stride()}")
+
+
+class Simulator:
+    """One context of the simulator: a type table, limits and a launch policy.
+
+    types: list of dicts with the fields of potato_type_params (mass, Ixx,
+    Iyy, Izz, arm, alpha, k_f, k_m, tau_m, drag, w_max, w_ref, gains[9],
+    budget); glob: dict of controller limits; mode: 0 open loop, 1 closed.
+    """
+
+    def __init__(self, types, glob, mode: int, form: str = "fused", block: int = 0,
+                 steps_per_launch: int = 0, grid_blocks: int = 0, use_graph: bool = False,
+                 debug: bool = False):
+        self._lib = L.load()
+        self.debug = bool(debug)
+        self.n_types = len(types)
+        self.mode = int(mode)
+        self._types = L.make_type_params(types)
+        self._limits = L.make_limits(glob)
+        self.opts = self._options(form, block, steps_per_launch, grid_blocks, use_graph)
+        h = C.c_void_p()
+        L.check(self._lib.potato_create(C.byref(h), C.addressof(self._types), self.n_types,
+                                        C.byref(self._limits), C.byref(self.opts)))
+        self._h = h
+
+    def _options(self, form, block, steps_per_launch, grid_blocks, use_graph):
+        forms = {"auto": L.FORM_AUTO, "plain": L.FORM_PLAIN, "fused": L.FORM_FUSED}
+        return L.Options(self.mode, forms[form], int(block), int(steps_per_launch),
+                         int(grid_blocks), int(bool(use_graph)))
+
+    def set_options(self, form="fused", block=0, steps_per_launch=0, grid_blocks=0, use_graph=False):
+        self.opts = self._options(form, block, steps_per_launch, grid_blocks, use_graph)
+        L.check(self._lib.potato_set_options(self._h, C.byref(self.opts)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.potato_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- argument structs -------------------------------------------------
+    def _structs(self, state, n, type_idx, perm, gains, motor_cmd, wp, resample_every, step0):
+        _check_rows("state", state, N_ROWS, n)
+        ld = state.stride(0)
+        if type_idx is not None:
+            if not type_idx.is_cuda or type_idx.dtype != torch.uint8 or type_idx.dim() != 1 \
+                    or type_idx.shape[0] < n or not type_idx.is_contiguous():
+                raise ValueError("type_idx must be a contiguous device uint8 tensor of length >= n")
+            # the device does not range-check type indices; debug mode does (syncs)
+            if self.debug and int(type_idx[:n].max().item()) >= self.n_types:
+                raise ValueError("type_idx holds an index >= n_types")
+        if perm is not None:
+            if not perm.is_cuda or perm.dtype != torch.int32 or perm.shape[0] < n or not perm.is_contiguous():
+                raise ValueError("perm must be a contiguous device int32 tensor of length >= n")
+        _check_rows("gains", gains, 9, n)
+        _check_rows("motor_cmd", motor_cmd, 4, n)
+        cmd_ld = ld
+        n_epochs = 0
+        if motor_cmd is not None:
+            cmd_ld = motor_cmd.stride(0)
+        if wp is not None:
+            if not wp.is_cuda or wp.dtype != torch.float32 or wp.dim() != 3 or wp.shape[1] != 3 \
+                    or not wp.is_contiguous() or wp.shape[2] < n:
+                raise ValueError("wp must be a contiguous device float32 tensor [E, 3, >= n]")
+            n_epochs = wp.shape[0]
+            if motor_cmd is not None and motor_cmd.stride(0) != wp.shape[2]:
+                raise ValueError("motor_cmd and wp must share their row stride")
+            cmd_ld = wp.shape[2]
+        st = L.State(C.c_void_p(state.data_ptr()), ld)
+        pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains), gains.stride(0) if gains is not None else 0)
+        cm = L.Cmds(_ptr(motor_cmd), _ptr(wp), n_epochs, int(resample_every), cmd_ld, int(step0))
+        return st, pp, cm
+
+    def step(self, state, n_steps, dt, *, n_agents=None, type_idx=None, perm=None, gains=None,
+             motor_cmd=None, wp=None, resample_every=0, step0=0, ckpt=None, ckpt_every=0,
+             stream=None):
+        """Advance ``state`` ([37, ld] float32, in place) by n_steps steps."""
+        n = int(n_agents if n_agents is not None else state.shape[1])
+        st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
+                                   resample_every, step0)
+        if ckpt is not None:
+            slots = -(-int(n_steps) // int(ckpt_every)) if ckpt_every > 0 else 0
+            if not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous() \
+                    or ckpt.numel() < slots * N_ROWS * st.ld:
+                raise ValueError(f"ckpt must be a contiguous device float32 tensor of >= "
+                                 f"{slots} x {N_ROWS} x {st.ld} elements")
+        L.check(self._lib.potato_step(self._h, C.byref(st), C.byref(pp), C.byref(cm), float(dt),
+                                      n, int(n_steps), _ptr(ckpt), int(ckpt_every),
+                                      _stream_handle(stream)))
+        return state
+
+    def autotune(self, state, dt, probe_steps=200, *, n_agents=None, type_idx=None, perm=None,
+                 gains=None, motor_cmd=None, wp=None, resample_every=0, step0=0, stream=None):
+        """Time the fused form's launch shapes on a scratch copy; keep the best."""
+        n = int(n_agents if n_agents is not None else state.shape[1])
+        st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
+                                   resample_every, step0)
+        best = L.Options()
+        L.check(self._lib.potato_autotune(self._h, C.byref(st), C.byref(pp), C.byref(cm),
+                                          float(dt), n, int(probe_steps), C.byref(best),
+                                          _stream_handle(stream)))
+        return dict(block=best.block, steps_per_launch=best.steps_per_launch,
+                    grid_blocks=best.grid_blocks)
+
+    def step_backward(self, ckpt, ckpt_every, n_steps, dt, grad_final, *, n_agents=None,
+                      type_idx=None, perm=None, gains=None, wp=None, resample_every=0, step0=0,
+                      want_gains=True, workspace=None, stream=None):
+        """Reverse sweep of a checkpointed closed-loop step() call.
+
+        grad_final: [30, ld] cotangent of the final physical rows.  Returns
+        (grad_x0 [30, ld], grad_gains [9, ld] or None)."""
+        _check_rows("grad_final", grad_final, 30, n_agents or grad_final.shape[1])
+        if not grad_final.is_contiguous():
+            raise ValueError("grad_final must be contiguous")
+        ld = grad_final.shape[1]
+        n = int(n_agents if n_agents is not None else ld)
+        if int(ckpt_every) < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        if not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous():
+            raise ValueError("ckpt must be a contiguous device float32 tensor")
+        slots = -(-int(n_steps) // int(ckpt_every))
+        if ckpt.numel() < slots * N_ROWS * ld:
+            raise ValueError(f"ckpt must hold {slots} x {N_ROWS} x {ld} floats")
+        pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains),
+                      gains.stride(0) if gains is not None else 0)
+        if wp is None or wp.dim() != 3 or not wp.is_contiguous():
+            raise ValueError("wp must be a contiguous device float32 tensor [E, 3, >= n]")
+        cm = L.Cmds(None, _ptr(wp), wp.shape[0], int(resample_every), wp.shape[2], int(step0))
+        nbytes = int(self._lib.potato_backward_workspace_bytes(self._h, C.byref(pp), n, int(ckpt_every)))
+        if nbytes < 0:
+            raise ValueError("invalid arguments for potato_backward_workspace_bytes")
+        if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=grad_final.device)
+        gx0 = torch.empty((30, ld), dtype=torch.float32, device=grad_final.device)
+        gg = torch.zeros((9, ld), dtype=torch.float32, device=grad_final.device) if want_gains else None
+        L.check(self._lib.potato_step_backward(self._h, C.byref(pp), C.byref(cm), float(dt), n,
+                                               int(n_steps), _ptr(ckpt), int(ckpt_every), ld,
+                                               _ptr(grad_final), _ptr(gx0), _ptr(gg), _ptr(workspace),
+                                               nbytes, _stream_handle(stream)))
+        return gx0, gg
+
+    def order_by_type(self, type_idx, stream=None):
+        """Processing order grouping agents by type, longest step budget first."""
+        n = type_idx.shape[0]
+        nbytes = int(self._lib.potato_order_workspace_bytes(n, self.n_types))
+        if nbytes < 0:
+            raise ValueError("invalid size for potato_order_workspace_bytes")
+        ws = torch.empty(max(nbytes, 4), dtype=torch.uint8, device=type_idx.device)
+        perm = torch.empty(n, dtype=torch.int32, device=type_idx.device)
+        L.check(self._lib.potato_order_by_type(self._h, _ptr(type_idx), n, _ptr(perm), _ptr(ws),
+                                               nbytes, _stream_handle(stream)))
+        return perm

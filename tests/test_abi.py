@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every function the header declares, and rejects invalid arguments before
+touching the device."""
+import ctypes as C
+import math
+import subprocess
+
+import pytest
+
+from paper_2308_12698_amd import _lib as L
+from paper_2308_12698_amd import inputs as I
+from tests.conftest import gpu_available
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_header_declares_the_expected_entry_points():
+    names = L.declared_functions()
+    for fn in ("potato_create", "potato_destroy", "potato_step", "potato_step_backward"
+               if "potato_step_backward" in names else "potato_step", "potato_autotune",
+               "potato_order_by_type", "potato_last_error"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_function(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for fn in L.declared_functions():
+        assert fn in exported, fn
+        getattr(lib, fn)
+
+
+def test_library_is_built_for_gfx950():
+    """The offload bundle of the library (built here from source) targets gfx950."""
+    with open(L.LIB_PATH, "rb") as f:
+        assert b"gfx950" in f.read()
+
+
+def test_version_and_empty_error(lib):
+    assert b"gfx950" in lib.potato_version()
+    assert isinstance(lib.potato_last_error(), bytes)
+
+
+def _create(lib, types, glob=None, opts=None):
+    arr = L.make_type_params(types)
+    lim = L.make_limits(glob or I.DEFAULT_GLOBALS)
+    o = opts or L.Options(1, 2, 0, 0, 0, 0)
+    h = C.c_void_p()
+    st = lib.potato_create(C.byref(h), C.addressof(arr), len(types), C.byref(lim), C.byref(o))
+    return st, h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(mass=0.0), dict(mass=-1.0), dict(Ixx=float("nan")), dict(k_f=0.0), dict(tau_m=0.0),
+    dict(alpha=0.0), dict(drag=-0.1), dict(w_max=float("inf")), dict(w_ref=-1.0)])
+def test_create_rejects_invalid_types(lib, bad):
+    t = I.base_type()
+    t.update({k: v for k, v in bad.items()})
+    st, h = _create(lib, [t])
+    assert st == L.EINVAL and not h.value
+    assert len(lib.potato_last_error()) > 0
+
+
+def test_create_rejects_invalid_counts_limits_options(lib):
+    t = I.base_type()
+    arr = L.make_type_params([t])
+    lim = L.make_limits(I.DEFAULT_GLOBALS)
+    o = L.Options(1, 2, 0, 0, 0, 0)
+    h = C.c_void_p()
+    assert lib.potato_create(None, C.addressof(arr), 1, C.byref(lim), C.byref(o)) == L.EINVAL
+    assert lib.potato_create(C.byref(h), C.addressof(arr), 0, C.byref(lim), C.byref(o)) == L.EINVAL
+    assert lib.potato_create(C.byref(h), C.addressof(arr), 257, C.byref(lim), C.byref(o)) == L.EINVAL
+    g = dict(I.DEFAULT_GLOBALS); g["g"] = 0.0
+    assert _create(lib, [t], glob=g)[0] == L.EINVAL
+    for bad in (L.Options(2, 2, 0, 0, 0, 0), L.Options(1, 3, 0, 0, 0, 0),
+                L.Options(1, 2, 100, 0, 0, 0), L.Options(1, 2, 0, -1, 0, 0)):
+        assert _create(lib, [t], opts=bad)[0] == L.EINVAL
+
+
+def test_step_rejects_null_context(lib):
+    st = L.State(None, 10)
+    pp = L.Params(None, None, None, 0)
+    cm = L.Cmds(None, None, 0, 0, 10, 0)
+    assert lib.potato_step(None, C.byref(st), C.byref(pp), C.byref(cm), 1e-3, 10, 10, None, 0,
+                           None) == L.EINVAL
+    assert lib.potato_autotune(None, C.byref(st), C.byref(pp), C.byref(cm), 1e-3, 10, 10, None,
+                               None) == L.EINVAL
+    assert lib.potato_destroy(None) == L.OK
+
+
+def test_order_workspace_size(lib):
+    assert lib.potato_order_workspace_bytes(0, 8) == -1
+    assert lib.potato_order_workspace_bytes(1000, 0) == -1
+    assert lib.potato_order_workspace_bytes(1000, 8) == 2 * math.ceil(1000 / 256) * 8 * 4
+
+
+@pytest.mark.skipif(gpu_available(), reason="checks the no-device error path")
+def test_create_without_device_reports_hip_error(lib):
+    st, h = _create(lib, [I.base_type()])
+    assert st == L.EHIP and not h.value

@@ -14,7 +14,7 @@ def test_generators_are_seeded_and_float32():
     a, b = I.config1(n=100), I.config1(n=100)
     assert np.array_equal(a.state, b.state) and np.array_equal(a.wp, b.wp)
     assert a.state.dtype == np.float32 and a.wp.dtype == np.float32
-    assert a.state.shape == (30, 100) and a.wp.shape == (1, 3, 100)
+    assert a.state.shape == (I.N_ROWS, 100) and a.wp.shape == (1, 3, 100)
     assert np.all(a.state[6] == 1.0) and np.all(a.state[13:] == 0.0)
     lo, hi = a.state[0:3].min(axis=1), a.state[0:3].max(axis=1)
     assert np.all(lo >= 0) and np.all(hi <= np.array(I.BOX))
@@ -65,10 +65,10 @@ def test_oracle_matches_its_regression_fixture(oracle):
     idx = np.array(g["open_loop_1000"]["agents"])
     c0 = I.subset(I.config0(), idx)
     s = oracle.rollout(c0.state, c0.types, c0.glob, 0, c0.dt, 1000, motor_cmd=c0.motor_cmd, threads=1)
-    assert np.allclose(s, np.array(g["open_loop_1000"]["final"]), rtol=1e-12, atol=1e-12)
+    assert np.allclose(s[:30], np.array(g["open_loop_1000"]["final"])[:30], rtol=1e-12, atol=1e-12)
     c1 = I.subset(I.config1(), idx)
     s = oracle.rollout(c1.state, c1.types, c1.glob, 1, c1.dt, 1000, wp=c1.wp, threads=1)
-    assert np.allclose(s, np.array(g["closed_loop_1000"]["final"]), rtol=1e-12, atol=1e-12)
+    assert np.allclose(s[:30], np.array(g["closed_loop_1000"]["final"])[:30], rtol=1e-12, atol=1e-12)
 
 
 def test_paper_table_fixture_is_readable():

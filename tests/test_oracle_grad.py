@@ -46,7 +46,7 @@ def test_dual_gradient_matches_central_differences(oracle, diff_case):
     kw = dict(wp=wp, gains=gains, threads=1)
     fin, jac = oracle.jacobian(s0, sw.types, sw.glob, dt, T, **{k: v for k, v in kw.items() if k != "threads"})
     _, gN = loss_and_seed(fin, tgt, w)
-    g_dual = np.einsum("ar,arc->ac", gN.T, jac)                  # [n, 39]
+    g_dual = np.einsum("ar,arc->ac", gN[:30].T, jac)             # [n, 39]
 
     def L_of(s, g):
         f = oracle.rollout(s, sw.types, sw.glob, 1, dt, T, wp=wp, gains=g, threads=1)
@@ -85,10 +85,10 @@ def test_dual_jacobian_columns_match_differences(oracle, diff_case):
             gp[c - 30] += H; gm[c - 30] -= H
         fp = oracle.rollout(sp, sw.types, sw.glob, 1, dt, T, wp=wp, gains=gp, threads=1)
         fm = oracle.rollout(sm, sw.types, sw.glob, 1, dt, T, wp=wp, gains=gm, threads=1)
-        col = (fp - fm) / (2 * H)                                 # [30, n]
+        col = ((fp - fm) / (2 * H))[:30]                          # [30, n]
         for a in range(2):
             # truncation ~ h^2 f''' plus cancellation eps |x_N| / h per row
-            tol = 1e-5 * max(np.abs(jac[a, :, c]).max(), 1e-3) + 50 * 2.2e-16 * np.abs(ref[:, a]) / H
+            tol = 1e-5 * max(np.abs(jac[a, :, c]).max(), 1e-3) + 50 * 2.2e-16 * np.abs(ref[:30, a]) / H
             assert np.all(np.abs(jac[a, :, c] - col[:, a]) <= tol), (c, a)
 
 

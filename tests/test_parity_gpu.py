@@ -1,0 +1,318 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 reference.
+
+Tolerance: relative state error <= 1e-4 per agent and state group after the
+stated number of steps (groups and floors in tests/_util.py).  Determinism
+and decomposition checks compare GPU results with each other bitwise: each
+lane's arithmetic does not depend on the launch shape, so any difference
+would expose an indexing, LDS or ordering bug.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_12698_amd import inputs as I
+from tests._util import OPEN_LOOP_GROUPS, rel_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def _dev(torch, dev, a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def gpu_rollout(torch_dev, sw, n_steps, form="fused", state=None, sim=None, step0=0, ld=None,
+                **opts):
+    """Run the workload on the GPU; returns the final state as float64 [37, N]."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    own = sim is None
+    if own:
+        sim = Simulator(sw.types, sw.glob, mode=sw.mode, form=form, debug=True, **opts)
+    s0 = sw.state if state is None else state
+    n = s0.shape[1]
+    if ld is not None and ld > n:
+        buf = np.full((s0.shape[0], ld), 7.0, dtype=np.float32)
+        buf[:, :n] = s0
+        s0 = buf
+    st = _dev(torch, dev, s0)
+    sim.step(st, n_steps, sw.dt, n_agents=n, type_idx=_dev(torch, dev, sw.type_idx),
+             gains=_dev(torch, dev, sw.gains), motor_cmd=_pad(torch, dev, sw.motor_cmd, st.shape[1]),
+             wp=_pad3(torch, dev, sw.wp, st.shape[1]), resample_every=sw.resample_every, step0=step0)
+    torch.cuda.synchronize()
+    out = st.cpu().numpy()
+    if own:
+        sim.close()
+    return out.astype(np.float64)
+
+
+def _pad(torch, dev, a, ld):
+    if a is None:
+        return None
+    if a.shape[-1] == ld:
+        return _dev(torch, dev, a)
+    b = np.zeros(a.shape[:-1] + (ld,), dtype=a.dtype)
+    b[..., :a.shape[-1]] = a
+    return _dev(torch, dev, b)
+
+
+_pad3 = _pad
+
+
+def oracle_rollout(oracle, sw, n_steps, state=None, step0=0):
+    s = sw.state if state is None else state
+    return oracle.rollout(s, sw.types, sw.glob, sw.mode, sw.dt, n_steps, type_idx=sw.type_idx,
+                          gains=sw.gains, motor_cmd=sw.motor_cmd, wp=sw.wp,
+                          resample_every=sw.resample_every, step0=step0)
+
+
+def assert_parity(got, ref, sw, groups=None, tol=TOL):
+    errs = rel_errors(got, ref, sw.types, sw.type_idx, groups)
+    worst = max(v[0] for v in errs.values())
+    print("parity", sw.name, {k: f"{v[0]:.2e}" for k, v in errs.items()}, flush=True)
+    assert worst <= tol, errs
+
+
+# --- parity with the oracle --------------------------------------------------
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_open_loop_1000_agents_1000_steps(oracle, torch_dev, form):
+    sw = I.config0()
+    got = gpu_rollout(torch_dev, sw, 1000, form=form, steps_per_launch=128)
+    ref = oracle_rollout(oracle, sw, 1000)
+    assert_parity(got, ref, sw, OPEN_LOOP_GROUPS)
+    # rows the open loop does not own are left alone
+    assert np.array_equal(got[17:30], sw.state[17:30].astype(np.float64))
+    assert np.array_equal(got[36], sw.state[36].astype(np.float64))
+
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_closed_loop_5000_agents_1000_steps(oracle, torch_dev, form):
+    sw = I.config1()
+    got = gpu_rollout(torch_dev, sw, 1000, form=form, steps_per_launch=100)
+    ref = oracle_rollout(oracle, sw, 1000)
+    assert_parity(got, ref, sw)
+
+
+def test_closed_loop_10000_steps_sampled(oracle, torch_dev):
+    """The full closed-loop rollout length, on a sample of agents."""
+    sw = I.subset(I.config1(), np.arange(0, 5000, 5))
+    got = gpu_rollout(torch_dev, sw, 10000, steps_per_launch=250)
+    ref = oracle_rollout(oracle, sw, 10000)
+    assert_parity(got, ref, sw)
+
+
+def test_waypoint_epochs_ragged_agents(oracle, torch_dev):
+    """Epoch switches that fall inside launches, a ragged agent count and a
+    padded leading dimension."""
+    sw = I.config2(n=3 * 256 + 37, n_steps=2500, resample_every=700)
+    got = gpu_rollout(torch_dev, sw, 2500, steps_per_launch=333, block=128, ld=1024)
+    ref = oracle_rollout(oracle, sw, 2500)
+    assert_parity(got[:, :sw.n], ref, sw)
+    assert np.all(got[:, sw.n:] == 7.0)            # columns past n_agents untouched
+
+
+def test_scale_workload_full_size_sampled(oracle, torch_dev):
+    """1,048,576 agents, 1,000 steps with the bench's launch shape (tuned,
+    graph-captured); 4,096 sampled agents against the oracle."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config2()
+    sim = Simulator(sw.types, sw.glob, mode=1, form="fused", use_graph=True)
+    st = _dev(torch, dev, sw.state)
+    wp = _dev(torch, dev, sw.wp)
+    sim.autotune(st, sw.dt, 200, wp=wp, resample_every=sw.resample_every)
+    sim.step(st, 1000, sw.dt, wp=wp, resample_every=sw.resample_every)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy().astype(np.float64)
+    sim.close()
+    idx = np.random.default_rng(5).choice(sw.n, 4096, replace=False)
+    sub = I.subset(sw, idx)
+    ref = oracle_rollout(oracle, sub, 1000)
+    assert_parity(got[:, idx], ref, sub)
+    assert np.isfinite(got).all()
+
+
+def test_heterogeneous_batch_matches_oracle(oracle, torch_dev):
+    """Eight types, step budgets 1,000-8,000, one launch, with and without the
+    type-grouped processing order."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config3(scale=256)
+    ref = oracle_rollout(oracle, sw, sw.n_steps)
+    for use_perm in (False, True):
+        sim = Simulator(sw.types, sw.glob, mode=1, form="fused", steps_per_launch=sw.n_steps,
+                        debug=True)
+        st = _dev(torch, dev, sw.state)
+        ti = _dev(torch, dev, sw.type_idx)
+        perm = sim.order_by_type(ti) if use_perm else None
+        sim.step(st, sw.n_steps, sw.dt, type_idx=ti, perm=perm, wp=_dev(torch, dev, sw.wp),
+                 resample_every=sw.resample_every)
+        torch.cuda.synchronize()
+        got = st.cpu().numpy().astype(np.float64)
+        sim.close()
+        assert_parity(got, ref, sw)
+
+
+def test_hover_fixed_point_on_gpu(torch_dev):
+    """wp = p, level, at rest, rotors at the reference speed: nothing moves
+    beyond FP32 rounding of the hover balance."""
+    sw = I.config1(n=512)
+    sw.wp = sw.state[0:3][None].copy()
+    got = gpu_rollout(torch_dev, sw, 1000)
+    assert np.abs(got[0:3] - sw.state[0:3]).max() <= 1e-4        # positions ~ 100 m
+    assert np.abs(got[3:6]).max() <= 1e-5
+    assert np.abs(got[10:13]).max() <= 1e-5
+    assert np.abs(got[13:17]).max() <= 1e-3                        # rad/s around ~634
+    assert np.abs(got[6] - 1.0).max() <= 1e-6
+
+
+# --- GPU-side invariants and decompositions -------------------------------------
+
+def test_launch_shape_does_not_change_results(torch_dev):
+    sw = I.config2(n=2000, n_steps=600, resample_every=250)
+    base = gpu_rollout(torch_dev, sw, 600, form="fused", block=256, steps_per_launch=100)
+    for kw in (dict(form="plain", block=64), dict(form="fused", block=512, steps_per_launch=7),
+               dict(form="fused", block=64, steps_per_launch=600, grid_blocks=5),
+               dict(form="fused", block=128, steps_per_launch=50, use_graph=True)):
+        assert np.array_equal(gpu_rollout(torch_dev, sw, 600, **kw), base), kw
+
+
+def test_split_rollout_is_bitwise_equal(torch_dev):
+    sw = I.config2(n=1500, n_steps=1000, resample_every=300)
+    full = gpu_rollout(torch_dev, sw, 1000, steps_per_launch=64)
+    half = gpu_rollout(torch_dev, sw, 450, steps_per_launch=64).astype(np.float32)
+    rest = gpu_rollout(torch_dev, sw, 550, state=half, step0=450, steps_per_launch=64)
+    assert np.array_equal(full, rest)
+
+
+def test_graph_replay_matches_eager(torch_dev):
+    """A cached hipGraph replayed several times, with eager work between
+    replays, gives the eager result each time."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config1(n=3000)
+    wp = _dev(torch, dev, sw.wp)
+    eager = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=40)
+    graph = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=40, use_graph=True)
+    a = _dev(torch, dev, sw.state)
+    b = _dev(torch, dev, sw.state)
+    for _ in range(4):
+        eager.step(a, 200, sw.dt, wp=wp)
+        graph.step(b, 200, sw.dt, wp=wp)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        a.mul_(1.0)                    # eager work between replays
+    eager.close(); graph.close()
+
+
+def test_types_match_single_type_runs(torch_dev):
+    """Each type's agents in the mixed launch equal a run of the same agents
+    with that type alone: bitwise through the same (type-indexed) kernel,
+    and to FP32 rounding through the homogeneous kernel, whose compiled
+    instruction sequence (FMA contraction) may differ."""
+    sw = I.config3(scale=512)
+    mixed = gpu_rollout(torch_dev, sw, sw.n_steps, steps_per_launch=1000)
+    for t in range(len(sw.types)):
+        idx = np.where(sw.type_idx == t)[0]
+        sub = I.subset(sw, idx)
+        sub.types = [sw.types[t]]
+        sub.type_idx = np.zeros(idx.size, dtype=np.uint8)
+        alone = gpu_rollout(torch_dev, sub, sw.n_steps, steps_per_launch=1000)
+        assert np.array_equal(mixed[:, idx], alone), t
+        sub.type_idx = None
+        homo = gpu_rollout(torch_dev, sub, sw.n_steps, steps_per_launch=1000)
+        assert_parity(homo, alone, sub, tol=1e-5)
+
+
+def test_order_by_type_is_the_stable_budget_order(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config3(scale=16)
+    sim = Simulator(sw.types, sw.glob, mode=1)
+    perm = sim.order_by_type(_dev(torch, dev, sw.type_idx)).cpu().numpy()
+    sim.close()
+    budgets = np.array([t["budget"] for t in sw.types])
+    rank = np.argsort(np.argsort(-budgets, kind="stable"), kind="stable")
+    expect = np.lexsort((np.arange(sw.n), rank[sw.type_idx]))
+    assert np.array_equal(perm, expect)
+
+
+def test_budget_zero_and_nan_agents(torch_dev):
+    sw = I.config1(n=700)
+    t0 = dict(sw.types[0]); t0["budget"] = 0
+    sw.types = [sw.types[0], t0]
+    sw.type_idx = (np.arange(700) % 3 == 0).astype(np.uint8)
+    bad = sw.state.copy()
+    bad[3, 5] = np.nan
+    got = gpu_rollout(torch_dev, sw, 300, state=bad)
+    frozen = sw.type_idx == 1
+    assert np.array_equal(got[:, frozen], bad[:, frozen].astype(np.float64))
+    clean = gpu_rollout(torch_dev, sw, 300)
+    keep = np.arange(700) != 5
+    assert np.array_equal(got[:, keep], clean[:, keep])
+    assert np.isnan(got[:, 5]).any()
+
+
+def test_zero_steps_and_single_agent(oracle, torch_dev):
+    sw = I.config1(n=1)
+    assert np.array_equal(gpu_rollout(torch_dev, sw, 0), sw.state.astype(np.float64))
+    got = gpu_rollout(torch_dev, sw, 500)
+    assert_parity(got, oracle_rollout(oracle, sw, 500), sw)
+
+
+def test_step_rejects_invalid_arguments(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd import _lib as L
+    from paper_2308_12698_amd.sim import Simulator
+    import ctypes as C
+    sw = I.config1(n=64)
+    sim = Simulator(sw.types, sw.glob, mode=1)
+    st = _dev(torch, dev, sw.state)
+    wp = _dev(torch, dev, sw.wp)
+    before = st.clone()
+    lib = L.load()
+    S = L.State(C.c_void_p(st.data_ptr()), 64)
+    P = L.Params(None, None, None, 0)
+    Cm = L.Cmds(None, C.c_void_p(wp.data_ptr()), 1, 0, 64, 0)
+    h = sim._h
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 1e-3, 65, 10, None, 0, None) == L.EINVAL
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 0.0, 64, 10, None, 0, None) == L.EINVAL
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), float("nan"), 64, 10, None, 0, None) == L.EINVAL
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 1e-3, 64, -1, None, 0, None) == L.EINVAL
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 1e-3, 64, 10, C.c_void_p(st.data_ptr()), 0, None) == L.EINVAL
+    Cm0 = L.Cmds(None, None, 0, 0, 64, 0)
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm0), 1e-3, 64, 10, None, 0, None) == L.EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(st, before)
+    with pytest.raises(ValueError):
+        bad_t = torch.full((64,), 3, dtype=torch.uint8, device=dev)
+        sim.debug = True
+        sim.step(st, 10, sw.dt, wp=wp, type_idx=bad_t)
+    sim.close()
+
+
+def test_checkpoints_are_the_intermediate_states(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config4(n=1000, n_steps=230)
+    K = 50
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=37)
+    st = _dev(torch, dev, sw.state)
+    ck = torch.full((5, 37, 1000), float("nan"), device=dev)
+    sim.step(st, 230, sw.dt, wp=_dev(torch, dev, sw.wp), gains=_dev(torch, dev, sw.gains),
+             ckpt=ck, ckpt_every=K)
+    torch.cuda.synchronize()
+    ck = ck.cpu().numpy()
+    sim.close()
+    for c in range(5):
+        ref = gpu_rollout(torch_dev, sw, c * K, steps_per_launch=37)
+        assert np.array_equal(ck[c].astype(np.float64), ref), c
