@@ -73,7 +73,13 @@ def main():
     ap.add_argument("--sim-steps", type=int, default=10000)
     ap.add_argument("--no-extra", action="store_true", help="skip the other forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device-to-device copy of known size (for scaling "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the quadrotor step has no cross-agent coupling, "
               "so a multi-GPU run is N independent copies of this one (see DESIGN.md).",
@@ -177,7 +183,7 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
     plain = Simulator(sw.types, sw.glob, mode=1, form="plain", use_graph=True)
     ms = timed(lambda: plain.step(state, steps_plain, sw.dt, wp=wp, resample_every=sw.resample_every))
     plain.close()
-    bytes_step = (37 + 37 + 3) * 4      # state rows in and out + waypoint
+    bytes_step = (40 + 40 + 3) * 4      # state rows in and out + waypoint
     launch_ms = ms / steps_plain
     gbs = bytes_step * N / (launch_ms * 1e-3) / 1e9
     res["plain"] = {"agent_steps_per_s": N * steps_plain / (ms * 1e-3), "steps_timed": steps_plain,
@@ -223,7 +229,7 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
         gains = torch.from_numpy(dw.gains).to(dev)
         dwp = torch.from_numpy(dw.wp).to(dev)
         tgt = torch.from_numpy(dw.extra["target"]).to(dev)
-        ckpt = torch.empty((dw.n_steps // K, 37, dw.n), device=dev)
+        ckpt = torch.empty((dw.n_steps // K, 40, dw.n), device=dev)
         gfin = torch.empty((30, dw.n), device=dev)
         ws = None
 
@@ -251,6 +257,19 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
         dsim.close()
         del ckpt, x, x0
     return res
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain copy of `nbytes` bytes, `reps` times: each dispatch moves
+    exactly nbytes in and nbytes out of HBM, which calibrates the FETCH_SIZE
+    and WRITE_SIZE counters of a profiler run."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000):

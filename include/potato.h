@@ -28,7 +28,7 @@
  *     last failure on the calling thread is potato_last_error().
  *   - No C++ exception crosses this interface.
  *
- * State layout: float32 rows[37][ld], one column per agent (ld >= n_agents):
+ * State layout: float32 rows[40][ld], one column per agent (ld >= n_agents):
  *   0-2 position (ENU inertial, m)      3-5 velocity (m/s)
  *   6-9 quaternion w,x,y,z (body FLU -> inertial, Hamilton product)
  *   10-12 body rates (rad/s)
@@ -38,10 +38,11 @@
  *   17-19 position-loop integral   20-22 attitude-loop integral
  *   23-25 rate-loop integral       26-28 body rates at the previous step
  *   29 running cost J = time integral of the sum of squared rotor speeds
- *   30-32, 33-35, 36: rounding carries of position, velocity and J.  The
- *         integrator keeps the low-order bits that an FP32 update drops
- *         (compensated summation); the represented value is row + carry.
- *         Set them to 0 when writing a state; they are < 1 ulp of the row.
+ *   30-32, 33-35, 36, 37-39: rounding carries of position, velocity, J and
+ *         the position-loop integral.  The integrator keeps the low-order
+ *         bits that an FP32 update drops (compensated summation); the
+ *         represented value is row + carry.  Set them to 0 when writing a
+ *         state; they are below 1 ulp of their row.
  * Open-loop mode reads and writes rows 0-16 and 30-35 only.
  */
 #ifndef POTATO_H
@@ -65,7 +66,7 @@ typedef enum {
 
 enum { POTATO_OPEN_LOOP = 0, POTATO_CLOSED_LOOP = 1 };
 enum { POTATO_FORM_AUTO = 0, POTATO_FORM_PLAIN = 1, POTATO_FORM_FUSED = 2 };
-enum { POTATO_ROWS = 37, POTATO_GAINS = 9, POTATO_MAX_TYPES = 256 };
+enum { POTATO_ROWS = 40, POTATO_GAINS = 9, POTATO_MAX_TYPES = 256 };
 
 /* One airframe type (all FP32, SI units).  alpha is the rotor-arm angle of
  * the allocation matrix of eq. (3) (pi/4 for an X frame); k_f, k_m are the
@@ -105,7 +106,7 @@ typedef struct {
     int32_t use_graph;
 } potato_options;
 
-/* Device state rows[37][ld] (in place). */
+/* Device state rows[40][ld] (in place). */
 typedef struct {
     float* rows;
     int64_t ld;
@@ -165,7 +166,7 @@ potato_status potato_set_options(potato_ctx* ctx, const potato_options* opts);
  * motor_cmd (open loop) or wp / n_epochs < 1 (closed loop), cmds->ld <
  * n_agents, gains_ld < n_agents when gains are given, ckpt set with
  * ckpt_every < 1.  n_steps == 0 is a no-op.
- * ckpt (optional, device float[ceil(n_steps/ckpt_every)][37][ld]): slot c
+ * ckpt (optional, device float[ceil(n_steps/ckpt_every)][40][ld]): slot c
  * receives the state at call-relative step c*ckpt_every, before that step;
  * it is what potato_step_backward consumes.  Requires the fused form.
  */
@@ -211,7 +212,7 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
  * exactly, not the continuous adjoint).  A carry row has the cotangent of
  * its row.
  *   params, cmds, dt, n_agents, n_steps: exactly as in the forward call;
- *   ckpt, ckpt_every: the checkpoints that call wrote (37 rows per slot);
+ *   ckpt, ckpt_every: the checkpoints that call wrote (40 rows per slot);
  *   workspace: device scratch of potato_backward_workspace_bytes() bytes
  *   (per-thread recomputation tape of ckpt_every steps).
  * Each segment of ckpt_every steps is recomputed from its checkpoint, then

@@ -1,7 +1,7 @@
 """``torch.autograd.Function`` around the fused forward rollout (with
 checkpoints) and the hand-written adjoint of libpotato.so.
 
-Inputs that carry gradients: the initial state x0 [37, N] (rows 30-36 are
+Inputs that carry gradients: the initial state x0 [40, N] (rows 30-39 are
 rounding carries; a carry row receives the cotangent of its row because the
 represented value is row + carry) and per-agent gains [9, N].  The loss is
 any torch expression of the returned final state; only the cotangent of the
@@ -48,12 +48,13 @@ class Rollout(torch.autograd.Function):
         full[30:33] = gx0[0:3]
         full[33:36] = gx0[3:6]
         full[36] = gx0[29]
+        full[37:40] = gx0[17:20]
         return (full, gg if ctx.needs_input_grad[1] else None, None, None, None, None, None, None,
                 None, None, None)
 
 
 def rollout(x0, gains, sim, wp, dt, n_steps, ckpt_every, resample_every=0, step0=0,
             type_idx=None, perm=None):
-    """Differentiable closed-loop rollout: returns the final state [37, N]."""
+    """Differentiable closed-loop rollout: returns the final state [40, N]."""
     return Rollout.apply(x0, gains, sim, wp, dt, n_steps, ckpt_every, resample_every, step0,
                          type_idx, perm)

@@ -81,6 +81,7 @@ TypeConst derive(const potato_type_params& p, const potato_limits& L) {
     c.mass = p.mass;
     c.inv_m = (float)(1.0 / m);
     c.cd_m = (float)(p.drag / m);
+    c.ncd_m = -c.cd_m;
     c.Ix = p.Ixx; c.Iy = p.Iyy; c.Iz = p.Izz;
     c.iIx = (float)(1.0 / p.Ixx); c.iIy = (float)(1.0 / p.Iyy); c.iIz = (float)(1.0 / p.Izz);
     c.F0 = (float)F0;
@@ -89,6 +90,12 @@ TypeConst derive(const potato_type_params& p, const potato_limits& L) {
     c.kf_ls = (float)(kf * ls);
     c.kf_lc = (float)(kf * lc);
     c.km = p.k_m;
+    c.ax = (float)(kf * ls / p.Ixx);
+    c.ay = (float)(kf * lc / p.Iyy);
+    c.az = (float)(km / p.Izz);
+    c.gx = (float)(((double)p.Izz - p.Iyy) / p.Ixx);
+    c.gy = (float)(((double)p.Ixx - p.Izz) / p.Iyy);
+    c.gz = (float)(((double)p.Iyy - p.Ixx) / p.Izz);
     c.w_ref = p.w_ref;
     c.two_w = (float)(2.0 * w);
     c.four_w2 = (float)(4.0 * w * w);
@@ -116,6 +123,7 @@ Limits make_limits(const potato_limits& L, float dt) {
     r.half_dt = 0.5f * dt;
     r.dt6 = dt / 6.0f;
     r.inv_dt = 1.0f / dt;
+    r.dt2_6 = dt * dt / 6.0f;
     return r;
 }
 

@@ -11,7 +11,7 @@
 
 namespace potato {
 
-constexpr int kRows = 37;   /* state rows per agent, see include/potato.h */
+constexpr int kRows = 40;   /* state rows per agent, see include/potato.h */
 
 /* Everything one rollout launch needs, passed by value as the kernel
  * argument (uniform, lands in scalar registers). */

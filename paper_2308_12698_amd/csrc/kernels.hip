@@ -1,7 +1,7 @@
 /*
  * kernels.hip -- gfx950 kernels of the batched quadrotor step.
  *
- * k_rollout: one agent per lane, its 37-float state loaded once into
+ * k_rollout: one agent per lane, its 40-float state loaded once into
  * registers (coalesced structure-of-arrays rows), advanced n_steps time
  * steps, stored once.  With n_steps = 1 and one agent per thread this is
  * the plain per-step form (HBM bound: the state round-trips every step);
@@ -24,8 +24,20 @@ namespace potato {
 
 namespace {
 
+/* Occupancy target of the rollout kernel in waves per SIMD (0 = compiler's
+ * choice).  Fewer registers per lane buy more resident waves to hide the
+ * latency of dependent FP32 chains and transcendental ops. */
+#ifndef POTATO_ROLLOUT_WAVES
+#define POTATO_ROLLOUT_WAVES 3
+#endif
+#if POTATO_ROLLOUT_WAVES > 0
+#define POTATO_ROLLOUT_ATTR __attribute__((amdgpu_waves_per_eu(POTATO_ROLLOUT_WAVES, POTATO_ROLLOUT_WAVES)))
+#else
+#define POTATO_ROLLOUT_ATTR
+#endif
+
 template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
-__global__ void __launch_bounds__(512) k_rollout(const StepArgs A) {
+__global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
     extern __shared__ float4 lds_raw[];
     TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw);
     if (HET) {
@@ -62,9 +74,11 @@ __global__ void __launch_bounds__(512) k_rollout(const StepArgs A) {
             }
             a.J = r[29 * ld];
             a.J_lo = r[36 * ld];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a.ip_lo[k] = r[(37 + k) * ld];
         } else {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) { a.ip[k] = a.ia[k] = a.ir[k] = a.wprev[k] = 0.0f; }
+            for (int k = 0; k < 3; ++k) { a.ip[k] = a.ia[k] = a.ir[k] = a.wprev[k] = a.ip_lo[k] = 0.0f; }
             a.J = a.J_lo = 0.0f;
         }
 
@@ -110,6 +124,7 @@ __global__ void __launch_bounds__(512) k_rollout(const StepArgs A) {
                     o[(17 + k) * ld] = a.ip[k]; o[(20 + k) * ld] = a.ia[k];
                     o[(23 + k) * ld] = a.ir[k]; o[(26 + k) * ld] = a.wprev[k];
                     o[(30 + k) * ld] = a.p_lo[k]; o[(33 + k) * ld] = a.v_lo[k];
+                    o[(37 + k) * ld] = a.ip_lo[k];
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { o[(6 + k) * ld] = a.q[k]; o[(13 + k) * ld] = a.d[k]; }
@@ -144,6 +159,8 @@ __global__ void __launch_bounds__(512) k_rollout(const StepArgs A) {
             }
             r[29 * ld] = a.J;
             r[36 * ld] = a.J_lo;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r[(37 + k) * ld] = a.ip_lo[k];
         }
     }
 }

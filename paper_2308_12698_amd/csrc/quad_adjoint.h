@@ -391,6 +391,7 @@ __device__ __forceinline__ void load_rows(const float* r, int64_t ld, Agent& a, 
         a.ir[k] = r[(23 + k) * ld]; a.wprev[k] = r[(26 + k) * ld];
         a.p_lo[k] = carries ? r[(30 + k) * ld] : 0.0f;
         a.v_lo[k] = carries ? r[(33 + k) * ld] : 0.0f;
+        a.ip_lo[k] = carries ? r[(37 + k) * ld] : 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) { a.q[k] = r[(6 + k) * ld]; a.d[k] = r[(13 + k) * ld]; }
@@ -437,7 +438,7 @@ __device__ __forceinline__ void store_adj(float* r, int64_t ld, const AgentAdj& 
 
 /*
  * Reverse sweep of one agent's closed-loop rollout of `steps` steps from
- * global step step0.  Checkpoint slot s (37 rows, column ckpt_col, stride
+ * global step step0.  Checkpoint slot s (40 rows, column ckpt_col, stride
  * ld) holds the state before call-relative step s*K.  Each segment is
  * recomputed forward from its checkpoint with the step-start states written
  * to this agent's tape column (K slots of 30 rows, stride tape_ld), then
@@ -454,7 +455,7 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         const int k_begin = seg * K;
         const int len = steps - k_begin < K ? steps - k_begin : K;
         Agent a;
-        load_rows(ckpt_col + (int64_t)seg * 37 * ld, ld, a, true);
+        load_rows(ckpt_col + (int64_t)seg * 40 * ld, ld, a, true);
         for (int s = 0; s < len; ++s) {
             store_phys_rows(tape_col + (int64_t)s * 30 * tape_ld, tape_ld, a);
             float wp[3], dc[4];

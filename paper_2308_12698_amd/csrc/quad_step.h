@@ -5,20 +5,30 @@
  * The physics follows Sec. II-B of the paper: eqs. (qd1)-(qd4) for the rigid
  * body, eq. (2) for rotor thrust/torque, eq. (3) for the allocation matrix,
  * classical RK4 for the discretisation, and a PID cascade ending in the
- * body-rate loop.  Differences from a literal transcription, all exact
- * algebraic rewrites chosen for FP32 accuracy or speed:
+ * body-rate loop.  Differences from a literal transcription, all exact in
+ * real arithmetic and chosen for FP32 accuracy or instruction count:
  *   - rotor speeds are carried as d = W - w_ref, and squared speeds as
  *     s = W^2 - w_ref^2 = d (2 w_ref + d), so the small speed differences
  *     that make the torques are not lost against a large W;
- *   - collective thrust over mass is F0 + (k_f/m) sum(s), F0 = 4 k_f w_ref^2 / m,
+ *   - collective thrust over mass is F0 + (k_f/m) sum(s), F0 = 4 k_f w_ref^2/m,
  *     and the vertical acceleration is assembled as (F0 - g) + ... so that
  *     the hover cancellation thrust/m - g happens once, on the host;
  *   - the mixer uses the closed-form inverse G^-1 = G^T diag(1/|row|^2),
  *     exact because the rows of G are mutually orthogonal;
+ *   - the rotor lag d' = (dc - d)/tau is linear with the command held, so the
+ *     four RK4 stage values of d are dc + (d - dc) c_i with the RK4 stage
+ *     polynomials c_i(z), z = -dt/tau, and the step ends at dc + (d - dc) R(z),
+ *     R the RK4 stability polynomial (the numbers RK4 produces);
+ *   - position obeys p' = v, so RK4 gives p + dt v + dt^2/6 (a1 + a2 + a3);
  *   - divisions by mass, inertia, tau_m and dt are multiplications by
  *     reciprocals precomputed per type.
- * The reference FP64 implementation performs the literal operations; the
- * two agree to the tolerance the tests state.
+ * p, v, J and the position-loop integral are updated with a carried rounding
+ * error (Fast2Sum), so long runs of nearly equal increments do not drift.
+ *
+ * Every forward function below turns floating-point contraction off and
+ * places its fused multiply-adds explicitly: each kernel that inlines them
+ * (plain, fused, type-indexed, adjoint recomputation) then executes the
+ * same operations and produces the same bits.
  */
 #pragma once
 
@@ -30,10 +40,12 @@ namespace potato {
 /* Per-type constants, derived once on the host from potato_type_params and
  * rounded to FP32. */
 struct TypeConst {
-    float mass, inv_m, cd_m;              /* m, 1/m, c_d/m */
+    float mass, inv_m, cd_m, ncd_m;       /* m, 1/m, c_d/m, -c_d/m */
     float Ix, Iy, Iz, iIx, iIy, iIz;      /* inertia and its inverse */
     float F0, F0_g, kf_m;                 /* 4 k_f w_ref^2/m, F0 - g, k_f/m */
     float kf_ls, kf_lc, km;               /* k_f L sin(a), k_f L cos(a), k_m */
+    float ax, ay, az;                     /* k_f L sin(a)/Ixx, k_f L cos(a)/Iyy, k_m/Izz */
+    float gx, gy, gz;                     /* (Izz-Iyy)/Ixx, (Ixx-Izz)/Iyy, (Iyy-Ixx)/Izz */
     float w_ref, two_w, four_w2;          /* w_ref, 2 w_ref, 4 w_ref^2 */
     float inv_tau;                        /* 1 / tau_m */
     float mix_x, mix_y, mix_z;            /* 1/(4 L sin a), 1/(4 L cos a), k_f/(4 k_m) */
@@ -46,33 +58,37 @@ struct TypeConst {
 /* Controller limits and the time step, shared by all agents of a launch. */
 struct Limits {
     float g, r_sat, r_sat2, ipos_max, iatt_max, irate_max, az_min;
-    float dt, half_dt, dt6, inv_dt;
+    float dt, half_dt, dt6, inv_dt, dt2_6;   /* dt, dt/2, dt/6, 1/dt, dt^2/6 */
 };
 
 struct Gains {
     float kpp, kip, kdp, kpa, kia, kda, kpr, kir, kdr;
 };
 
-/* 17 integrated rows + running cost, plus the controller memory. */
+/* 17 integrated rows + running cost, the controller memory, and the
+ * rounding carries of p, v, J and the position-loop integral. */
 struct Agent {
     float p[3], v[3], q[4], w[3], d[4];   /* d = rotor speed - w_ref */
     float J;
     float ip[3], ia[3], ir[3], wprev[3];
-    float p_lo[3], v_lo[3], J_lo;         /* rounding carries of p, v, J */
+    float p_lo[3], v_lo[3], J_lo, ip_lo[3];
 };
 
+#define POTATO_FMA(a, b, c) __builtin_fmaf((a), (b), (c))
+
 /* x += inc with the rounding error carried in lo (Fast2Sum, Dekker 1971):
- * the carried low part is added back into the next increment, so a long
- * run of nearly equal increments does not drift by half an ulp per step. */
+ * the low part is added back into the next increment. */
 __device__ __forceinline__ void add_carry(float& x, float& lo, float inc) {
+#pragma clang fp contract(off)
     const float y = inc + lo;
     const float s = x + y;
     lo = y - (s - x);
     x = s;
 }
 
+/* clamp(x, lo, hi) for lo <= hi (one v_med3_f32). */
 __device__ __forceinline__ float clampf_(float x, float lo, float hi) {
-    return x < lo ? lo : (x > hi ? hi : x);
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -81,46 +97,54 @@ __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sq
 /* Body z axis in the inertial frame: third column of R(q), unit-norm form
  * (eq. qd2 with thrust along body z). */
 __device__ __forceinline__ void body_z(const float q[4], float bz[3]) {
-    bz[0] = 2.0f * (q[1] * q[3] + q[0] * q[2]);
-    bz[1] = 2.0f * (q[2] * q[3] - q[0] * q[1]);
-    bz[2] = 1.0f - 2.0f * (q[1] * q[1] + q[2] * q[2]);
+#pragma clang fp contract(off)
+    bz[0] = 2.0f * POTATO_FMA(q[0], q[2], q[1] * q[3]);
+    bz[1] = 2.0f * POTATO_FMA(q[2], q[3], -(q[0] * q[1]));
+    bz[2] = POTATO_FMA(-2.0f, POTATO_FMA(q[1], q[1], q[2] * q[2]), 1.0f);
 }
 
-/* Rate of the integrated rows for held rotor command dc (relative to w_ref).
- * Position is not an input: only its derivative (= v) is needed.  Outputs
- * dv, dq, dw, dd and the cost rate dJ. */
+/* Rates of v, q, w at rotor deviations d (eqs. 2, 3, qd2-qd4).  Returns
+ * sum_i s_i (collective thrust and cost rate follow from it). */
+__device__ __forceinline__ float rates(const TypeConst& c, const float v[3], const float q[4],
+                                       const float w[3], const float d[4], float dv[3], float dq[4],
+                                       float dw[3]) {
+#pragma clang fp contract(off)
+    /* eq. (2) with s_i = W_i^2 - w_ref^2 */
+    float s[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = POTATO_FMA(d[i], d[i], c.two_w * d[i]);
+    const float A = s[0] - s[1], B = s[3] - s[2];
+    const float P01 = s[0] + s[1], P23 = s[2] + s[3];
+    const float ssum = P01 + P23;
+    /* eq. (qd2) + drag: (f_c/m) R(q) z - (c_d/m) v - g z */
+    const float ftm2 = 2.0f * POTATO_FMA(c.kf_m, ssum, c.F0);
+    const float bx2 = POTATO_FMA(q[0], q[2], q[1] * q[3]);
+    const float by2 = POTATO_FMA(q[2], q[3], -(q[0] * q[1]));
+    const float x2y2 = POTATO_FMA(q[1], q[1], q[2] * q[2]);
+    dv[0] = POTATO_FMA(ftm2, bx2, c.ncd_m * v[0]);
+    dv[1] = POTATO_FMA(ftm2, by2, c.ncd_m * v[1]);
+    dv[2] = POTATO_FMA(c.ncd_m, v[2], POTATO_FMA(-ftm2, x2y2, POTATO_FMA(c.kf_m, ssum, c.F0_g)));
+    /* eq. (qd3): q' = 1/2 q o (0, w) */
+    const float h0 = 0.5f * w[0], h1 = 0.5f * w[1], h2 = 0.5f * w[2];
+    dq[0] = -POTATO_FMA(q[3], h2, POTATO_FMA(q[2], h1, q[1] * h0));
+    dq[1] = POTATO_FMA(-q[3], h1, POTATO_FMA(q[2], h2, q[0] * h0));
+    dq[2] = POTATO_FMA(-q[1], h2, POTATO_FMA(q[3], h0, q[0] * h1));
+    dq[3] = POTATO_FMA(-q[2], h0, POTATO_FMA(q[1], h1, q[0] * h2));
+    /* eq. (3) torques and eq. (qd4): w' = I^-1 (tau - w x I w) */
+    dw[0] = POTATO_FMA(-c.gx, w[1] * w[2], c.ax * (A + B));
+    dw[1] = POTATO_FMA(-c.gy, w[2] * w[0], c.ay * (P23 - P01));
+    dw[2] = POTATO_FMA(-c.gz, w[0] * w[1], c.az * (A - B));
+    return ssum;
+}
+
+/* Rate of the integrated rows for held rotor command dc (relative to
+ * w_ref): the general form, used where a single derivative is needed. */
 __device__ __forceinline__ void derivative(const TypeConst& c, const float v[3], const float q[4],
                                            const float w[3], const float d[4], const float dc[4],
                                            float dv[3], float dq[4], float dw[3], float dd[4],
                                            float& dJ) {
-    /* eq. (2) with s_i = W_i^2 - w_ref^2 */
-    float s[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s[i] = d[i] * (c.two_w + d[i]);
-    const float ssum = (s[0] + s[1]) + (s[2] + s[3]);
-    /* eq. (3): body torques from the rotor thrusts */
-    const float tx = c.kf_ls * ((s[0] - s[1]) + (s[3] - s[2]));
-    const float ty = c.kf_lc * ((s[2] - s[0]) + (s[3] - s[1]));
-    const float tz = c.km * ((s[0] - s[1]) + (s[2] - s[3]));
-    /* eq. (qd2) + drag: (f_c/m) R(q) z - (c_d/m) v - g z */
-    const float ftm = c.F0 + c.kf_m * ssum;
-    const float x2y2 = q[1] * q[1] + q[2] * q[2];
-    const float bx = 2.0f * (q[1] * q[3] + q[0] * q[2]);
-    const float by = 2.0f * (q[2] * q[3] - q[0] * q[1]);
-    dv[0] = ftm * bx - c.cd_m * v[0];
-    dv[1] = ftm * by - c.cd_m * v[1];
-    dv[2] = (c.F0_g + c.kf_m * ssum) - 2.0f * ftm * x2y2 - c.cd_m * v[2];
-    /* eq. (qd3): q' = 1/2 q o (0, w) */
-    dq[0] = -0.5f * (q[1] * w[0] + q[2] * w[1] + q[3] * w[2]);
-    dq[1] = 0.5f * (q[0] * w[0] + q[2] * w[2] - q[3] * w[1]);
-    dq[2] = 0.5f * (q[0] * w[1] + q[3] * w[0] - q[1] * w[2]);
-    dq[3] = 0.5f * (q[0] * w[2] + q[1] * w[1] - q[2] * w[0]);
-    /* eq. (qd4): w' = I^-1 (tau - w x I w) */
-    const float Iwx = c.Ix * w[0], Iwy = c.Iy * w[1], Iwz = c.Iz * w[2];
-    dw[0] = c.iIx * (tx - (w[1] * Iwz - w[2] * Iwy));
-    dw[1] = c.iIy * (ty - (w[2] * Iwx - w[0] * Iwz));
-    dw[2] = c.iIz * (tz - (w[0] * Iwy - w[1] * Iwx));
-    /* first-order rotor lag */
+#pragma clang fp contract(off)
+    const float ssum = rates(c, v, q, w, d, dv, dq, dw);
 #pragma unroll
     for (int i = 0; i < 4; ++i) dd[i] = (dc[i] - d[i]) * c.inv_tau;
     dJ = c.four_w2 + ssum;
@@ -131,67 +155,70 @@ __device__ __forceinline__ void derivative(const TypeConst& c, const float v[3],
  * w_ref and updates the controller memory. */
 __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, const Gains& k,
                                            Agent& a, const float wp[3], float dc[4]) {
+#pragma clang fp contract(off)
     /* position loop: error saturated to radius r_sat */
     float e[3] = {wp[0] - a.p[0], wp[1] - a.p[1], wp[2] - a.p[2]};
-    const float n2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
-    if (n2 > L.r_sat2) {
-        const float sc = L.r_sat * rsq(n2);
-        e[0] *= sc; e[1] *= sc; e[2] *= sc;
-    }
+    const float n2 = POTATO_FMA(e[2], e[2], POTATO_FMA(e[1], e[1], e[0] * e[0]));
+    const float sc = n2 > L.r_sat2 ? L.r_sat * rsq(n2) : 1.0f;
     float acc[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        a.ip[i] = clampf_(a.ip[i] + e[i] * L.dt, -L.ipos_max, L.ipos_max);
-        acc[i] = k.kpp * e[i] + k.kip * a.ip[i] - k.kdp * a.v[i];
+        e[i] *= sc;
+        /* integral with carried rounding error, clamped (carry cleared at a bound) */
+        const float y = POTATO_FMA(e[i], L.dt, a.ip_lo[i]);
+        const float s = a.ip[i] + y;
+        const float lo = y - (s - a.ip[i]);
+        const float cl = clampf_(s, -L.ipos_max, L.ipos_max);
+        a.ip_lo[i] = cl == s ? lo : 0.0f;
+        a.ip[i] = cl;
+        acc[i] = POTATO_FMA(-k.kdp, a.v[i], POTATO_FMA(k.kip, cl, k.kpp * e[i]));
     }
-    acc[2] += L.g;
-    acc[2] = acc[2] < L.az_min ? L.az_min : acc[2];
+    acc[2] = fmaxf(acc[2] + L.g, L.az_min);
 
     /* collective thrust: commanded acceleration along the current body z */
     float bz[3];
     body_z(a.q, bz);
-    const float fc = c.mass * (acc[0] * bz[0] + acc[1] * bz[1] + acc[2] * bz[2]);
+    const float fc = c.mass * POTATO_FMA(acc[2], bz[2], POTATO_FMA(acc[1], bz[1], acc[0] * bz[0]));
 
-    /* desired attitude: shortest rotation of z onto the thrust direction */
-    const float ra = rsq(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+    /* desired attitude: shortest rotation of z onto the thrust direction,
+     * q_des ~ (1 + n_z, -n_y, n_x, 0), whose squared norm is 2 (1 + n_z) */
+    const float ra = rsq(POTATO_FMA(acc[2], acc[2], POTATO_FMA(acc[1], acc[1], acc[0] * acc[0])));
     const float nx = acc[0] * ra, ny = acc[1] * ra, nz = acc[2] * ra;
-    float qd0 = 1.0f + nz, qd1 = -ny, qd2 = nx;
-    const float rq = rsq(qd0 * qd0 + qd1 * qd1 + qd2 * qd2);
-    qd0 *= rq; qd1 *= rq; qd2 *= rq;
+    const float qr0 = 1.0f + nz;
+    const float rq = rsq(qr0 + qr0);
+    const float qd0 = qr0 * rq, qd1 = -(ny * rq), qd2 = nx * rq;
 
     /* attitude loop on conj(q) o q_des (short arc) */
     const float* q = a.q;
-    float ew = q[0] * qd0 + q[1] * qd1 + q[2] * qd2;
-    float ex = q[0] * qd1 - q[1] * qd0 + q[3] * qd2;
-    float ey = q[0] * qd2 - q[2] * qd0 - q[3] * qd1;
-    float ez = q[2] * qd1 - q[1] * qd2 - q[3] * qd0;
+    const float ew = POTATO_FMA(q[2], qd2, POTATO_FMA(q[1], qd1, q[0] * qd0));
+    const float ex = POTATO_FMA(q[3], qd2, POTATO_FMA(-q[1], qd0, q[0] * qd1));
+    const float ey = POTATO_FMA(-q[3], qd1, POTATO_FMA(-q[2], qd0, q[0] * qd2));
+    const float ez = POTATO_FMA(-q[3], qd0, POTATO_FMA(-q[1], qd2, q[2] * qd1));
     const float sg = ew < 0.0f ? -2.0f : 2.0f;
     const float eatt[3] = {sg * ex, sg * ey, sg * ez};
     float alpha[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        a.ia[i] = clampf_(a.ia[i] + eatt[i] * L.dt, -L.iatt_max, L.iatt_max);
-        const float wdes = k.kpa * eatt[i] + k.kia * a.ia[i] - k.kda * a.w[i];
+        a.ia[i] = clampf_(POTATO_FMA(eatt[i], L.dt, a.ia[i]), -L.iatt_max, L.iatt_max);
+        const float wdes = POTATO_FMA(-k.kda, a.w[i], POTATO_FMA(k.kia, a.ia[i], k.kpa * eatt[i]));
         /* body-rate loop, derivative on the measured rate */
         const float erate = wdes - a.w[i];
-        a.ir[i] = clampf_(a.ir[i] + erate * L.dt, -L.irate_max, L.irate_max);
-        alpha[i] = k.kpr * erate + k.kir * a.ir[i] - k.kdr * ((a.w[i] - a.wprev[i]) * L.inv_dt);
+        a.ir[i] = clampf_(POTATO_FMA(erate, L.dt, a.ir[i]), -L.irate_max, L.irate_max);
+        const float dwr = (a.w[i] - a.wprev[i]) * L.inv_dt;
+        alpha[i] = POTATO_FMA(-k.kdr, dwr, POTATO_FMA(k.kir, a.ir[i], k.kpr * erate));
         a.wprev[i] = a.w[i];
     }
     /* torque for the desired angular acceleration, eq. (qd4) inverted */
     const float Iwx = c.Ix * a.w[0], Iwy = c.Iy * a.w[1], Iwz = c.Iz * a.w[2];
-    const float tx = c.Ix * alpha[0] + (a.w[1] * Iwz - a.w[2] * Iwy);
-    const float ty = c.Iy * alpha[1] + (a.w[2] * Iwx - a.w[0] * Iwz);
-    const float tz = c.Iz * alpha[2] + (a.w[0] * Iwy - a.w[1] * Iwx);
+    const float tx = POTATO_FMA(c.Ix, alpha[0], POTATO_FMA(a.w[1], Iwz, -(a.w[2] * Iwy)));
+    const float ty = POTATO_FMA(c.Iy, alpha[1], POTATO_FMA(a.w[2], Iwx, -(a.w[0] * Iwz)));
+    const float tz = POTATO_FMA(c.Iz, alpha[2], POTATO_FMA(a.w[0], Iwy, -(a.w[1] * Iwx)));
 
     /* mixer: f = G^-1 [fc, tau], saturate, invert eq. (2) */
     const float f4 = 0.25f * fc;
     const float X = tx * c.mix_x, Y = ty * c.mix_y, Z = tz * c.mix_z;
-    float f[4];
-    f[0] = f4 + X - Y + Z;
-    f[1] = f4 - X - Y - Z;
-    f[2] = f4 - X + Y + Z;
-    f[3] = f4 + X + Y - Z;
+    const float fpz = f4 + Z, fmz = f4 - Z, xmy = X - Y, xpy = X + Y;
+    const float f[4] = {fpz + xmy, fmz - xpy, fpz - xmy, fmz + xpy};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float fi = clampf_(f[i], 0.0f, c.f_max);
@@ -202,61 +229,93 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
 /* Classical RK4 with the command held, then quaternion renormalisation. */
 __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Agent& a,
                                          const float dc[4]) {
-    float sv[3], sq[4], sw[3], sd[4];      /* stage state */
-    float kv[3], kq[4], kw[3], kd[4], kJ;  /* stage rate */
-    float av[3], aq[4], aw[3], ad[4], ap[3], aJ;  /* weighted sum of rates */
+#pragma clang fp contract(off)
+    /* RK4 stage polynomials of the linear rotor lag, z = -dt / tau */
+    const float z = -(L.dt * c.inv_tau);
+    const float hz = 0.5f * z;
+    const float c2 = 1.0f + hz;
+    const float c3 = POTATO_FMA(hz, c2, 1.0f);
+    const float c4 = POTATO_FMA(z, c3, 1.0f);
+    const float cR = POTATO_FMA(z * (1.0f / 6.0f), ((1.0f + (c2 + c2)) + (c3 + c3)) + c4, 1.0f);
+    float e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = a.d[i] - dc[i];
 
-    derivative(c, a.v, a.q, a.w, a.d, dc, kv, kq, kw, kd, kJ);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { ap[i] = a.v[i]; av[i] = kv[i]; aw[i] = kw[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { aq[i] = kq[i]; ad[i] = kd[i]; }
-    aJ = kJ;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { sv[i] = a.v[i] + L.half_dt * kv[i]; sw[i] = a.w[i] + L.half_dt * kw[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { sq[i] = a.q[i] + L.half_dt * kq[i]; sd[i] = a.d[i] + L.half_dt * kd[i]; }
+    float kv[3], kq[4], kw[3];            /* stage rates */
+    float av[3], aq[4], aw[3], A3[3];     /* weighted sums; A3 = a1 + a2 + a3 */
+    float sv[3], sq[4], sw[3], sd[4];     /* stage state */
+    float ss, ass;
 
-    derivative(c, sv, sq, sw, sd, dc, kv, kq, kw, kd, kJ);
+    /* stage 1 */
+    ss = rates(c, a.v, a.q, a.w, a.d, kv, kq, kw);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { ap[i] += 2.0f * sv[i]; av[i] += 2.0f * kv[i]; aw[i] += 2.0f * kw[i]; }
+    for (int i = 0; i < 3; ++i) { av[i] = kv[i]; aw[i] = kw[i]; A3[i] = kv[i]; }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { aq[i] += 2.0f * kq[i]; ad[i] += 2.0f * kd[i]; }
-    aJ += 2.0f * kJ;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { sv[i] = a.v[i] + L.half_dt * kv[i]; sw[i] = a.w[i] + L.half_dt * kw[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { sq[i] = a.q[i] + L.half_dt * kq[i]; sd[i] = a.d[i] + L.half_dt * kd[i]; }
-
-    derivative(c, sv, sq, sw, sd, dc, kv, kq, kw, kd, kJ);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { ap[i] += 2.0f * sv[i]; av[i] += 2.0f * kv[i]; aw[i] += 2.0f * kw[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { aq[i] += 2.0f * kq[i]; ad[i] += 2.0f * kd[i]; }
-    aJ += 2.0f * kJ;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { sv[i] = a.v[i] + L.dt * kv[i]; sw[i] = a.w[i] + L.dt * kw[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { sq[i] = a.q[i] + L.dt * kq[i]; sd[i] = a.d[i] + L.dt * kd[i]; }
-
-    derivative(c, sv, sq, sw, sd, dc, kv, kq, kw, kd, kJ);
+    for (int i = 0; i < 4; ++i) aq[i] = kq[i];
+    ass = ss;
+    /* stage 2 */
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        ap[i] += sv[i]; av[i] += kv[i]; aw[i] += kw[i];
-        add_carry(a.p[i], a.p_lo[i], L.dt6 * ap[i]);
-        add_carry(a.v[i], a.v_lo[i], L.dt6 * av[i]);
-        a.w[i] += L.dt6 * aw[i];
+        sv[i] = POTATO_FMA(L.half_dt, kv[i], a.v[i]);
+        sw[i] = POTATO_FMA(L.half_dt, kw[i], a.w[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.half_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c2, dc[i]); }
+    ss = rates(c, sv, sq, sw, sd, kv, kq, kw);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        av[i] = POTATO_FMA(2.0f, kv[i], av[i]);
+        aw[i] = POTATO_FMA(2.0f, kw[i], aw[i]);
+        A3[i] += kv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) aq[i] = POTATO_FMA(2.0f, kq[i], aq[i]);
+    ass = POTATO_FMA(2.0f, ss, ass);
+    /* stage 3 */
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        sv[i] = POTATO_FMA(L.half_dt, kv[i], a.v[i]);
+        sw[i] = POTATO_FMA(L.half_dt, kw[i], a.w[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.half_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c3, dc[i]); }
+    ss = rates(c, sv, sq, sw, sd, kv, kq, kw);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        av[i] = POTATO_FMA(2.0f, kv[i], av[i]);
+        aw[i] = POTATO_FMA(2.0f, kw[i], aw[i]);
+        A3[i] += kv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) aq[i] = POTATO_FMA(2.0f, kq[i], aq[i]);
+    ass = POTATO_FMA(2.0f, ss, ass);
+    /* stage 4 */
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        sv[i] = POTATO_FMA(L.dt, kv[i], a.v[i]);
+        sw[i] = POTATO_FMA(L.dt, kw[i], a.w[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c4, dc[i]); }
+    ss = rates(c, sv, sq, sw, sd, kv, kq, kw);
+    ass += ss;
+
+    /* combine: p with dt v + dt^2/6 (a1 + a2 + a3), the rest dt/6 (k1 + 2k2 + 2k3 + k4) */
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        add_carry(a.p[i], a.p_lo[i], POTATO_FMA(L.dt2_6, A3[i], L.dt * a.v[i]));
+        add_carry(a.v[i], a.v_lo[i], L.dt6 * (av[i] + kv[i]));
+        a.w[i] = POTATO_FMA(L.dt6, aw[i] + kw[i], a.w[i]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        aq[i] += kq[i]; ad[i] += kd[i];
-        a.q[i] += L.dt6 * aq[i];
-        a.d[i] += L.dt6 * ad[i];
+        a.q[i] = POTATO_FMA(L.dt6, aq[i] + kq[i], a.q[i]);
+        a.d[i] = POTATO_FMA(e[i], cR, dc[i]);
     }
-    aJ += kJ;
-    add_carry(a.J, a.J_lo, L.dt6 * aJ);
+    add_carry(a.J, a.J_lo, POTATO_FMA(L.dt6, ass, L.dt * c.four_w2));
 
-    const float r = rsq(a.q[0] * a.q[0] + a.q[1] * a.q[1] + a.q[2] * a.q[2] + a.q[3] * a.q[3]);
+    const float r = rsq(POTATO_FMA(a.q[3], a.q[3],
+                        POTATO_FMA(a.q[2], a.q[2], POTATO_FMA(a.q[1], a.q[1], a.q[0] * a.q[0]))));
 #pragma unroll
     for (int i = 0; i < 4; ++i) a.q[i] *= r;
 }

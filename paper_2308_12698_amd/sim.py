@@ -12,7 +12,7 @@ import torch
 
 from . import _lib as L
 
-N_ROWS = 37            # state rows per agent (include/potato.h)
+N_ROWS = 40            # state rows per agent (include/potato.h)
 
 
 def _ptr(t):
@@ -115,7 +115,7 @@ class Simulator:
     def step(self, state, n_steps, dt, *, n_agents=None, type_idx=None, perm=None, gains=None,
              motor_cmd=None, wp=None, resample_every=0, step0=0, ckpt=None, ckpt_every=0,
              stream=None):
-        """Advance ``state`` ([37, ld] float32, in place) by n_steps steps."""
+        """Advance ``state`` ([40, ld] float32, in place) by n_steps steps."""
         n = int(n_agents if n_agents is not None else state.shape[1])
         st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
                                    resample_every, step0)

@@ -38,7 +38,7 @@ def diff_run(torch_dev):
     x = torch.from_numpy(sw.state).to(dev)
     gains = torch.from_numpy(sw.gains).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
-    ckpt = torch.empty((sw.n_steps // K, 37, sw.n), device=dev)
+    ckpt = torch.empty((sw.n_steps // K, 40, sw.n), device=dev)
     sim.step(x, sw.n_steps, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
     tgt = torch.from_numpy(sw.extra["target"]).to(dev)
     gfin = torch.zeros((30, sw.n), device=dev)
@@ -120,7 +120,7 @@ def test_adjoint_random_cotangent_all_rows(oracle, torch_dev):
     x = torch.from_numpy(sw.state).to(dev)
     gains = torch.from_numpy(sw.gains).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
-    ckpt = torch.empty((3, 37, sw.n), device=dev)
+    ckpt = torch.empty((3, 40, sw.n), device=dev)
     sim.step(x, 120, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
     lam = np.random.default_rng(3).normal(size=(30, sw.n)).astype(np.float32)
     gx0, gg = sim.step_backward(ckpt, K, 120, sw.dt, torch.from_numpy(lam).to(dev), gains=gains, wp=wp)
@@ -150,7 +150,7 @@ def test_checkpoint_interval_does_not_change_the_gradient(torch_dev):
     for K in (10, 50, 200):
         sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
         x = torch.from_numpy(sw.state).to(dev)
-        ckpt = torch.empty((200 // K, 37, sw.n), device=dev)
+        ckpt = torch.empty((200 // K, 40, sw.n), device=dev)
         sim.step(x, 200, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
         gx0, gg = sim.step_backward(ckpt, K, 200, sw.dt, lam, gains=gains, wp=wp)
         torch.cuda.synchronize()
@@ -193,7 +193,7 @@ def test_adjoint_heterogeneous_budgets(oracle, torch_dev):
     gains = torch.from_numpy(sw.gains).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
     tid = torch.from_numpy(ti).to(dev)
-    ckpt = torch.empty((3, 37, sw.n), device=dev)
+    ckpt = torch.empty((3, 40, sw.n), device=dev)
     sim.step(x, 150, sw.dt, gains=gains, wp=wp, type_idx=tid, ckpt=ckpt, ckpt_every=50)
     lam = np.random.default_rng(2).normal(size=(30, sw.n)).astype(np.float32)
     gx0, gg = sim.step_backward(ckpt, 50, 150, sw.dt, torch.from_numpy(lam).to(dev), gains=gains,
