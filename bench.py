@@ -217,6 +217,27 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
         log(f"{label}: {res[label]['agent_steps_per_s']:.4e} agent-steps/s")
     hsim.close()
 
+    # collision detection on the scale swarm's positions (all alive on entry)
+    cw = I.config2(n=N, n_steps=1)
+    cstate = torch.from_numpy(cw.state).to(dev)
+    csim = Simulator(cw.types, cw.glob, mode=1)
+    alive0 = torch.ones(N, dtype=torch.uint8, device=dev)
+    alive = alive0.clone()
+    ws = torch.empty(int(csim._lib.potato_collision_workspace_bytes(N)), dtype=torch.uint8, device=dev)
+    died = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def detect():
+        alive.copy_(alive0)
+        csim.detect_collisions(cstate, alive, workspace=ws, died=died)
+
+    ms = timed(detect, reps=5)
+    res["collisions"] = {"agents_per_s": N / (ms * 1e-3), "n_agents": N, "ms": ms,
+                         "died_per_pass": int(died.item()) // 6}
+    log(f"collisions: {N / (ms * 1e-3):.4e} agents/s ({ms:.3f} ms per pass, "
+        f"{res['collisions']['died_per_pass']} collided)")
+    csim.close()
+    del cstate, ws
+
     # forward (with checkpoints) + hand-written adjoint of the differentiable
     # rollout: 500 steps at dt = 2 ms, checkpoints every 50 steps, at the
     # workload's own 65,536 agents and at 1,048,576 agents

@@ -73,12 +73,13 @@ enum { POTATO_ROWS = 40, POTATO_GAINS = 9, POTATO_MAX_TYPES = 256 };
  * thrust and torque coefficients of eq. (2) in N/(rad/s)^2 and N m/(rad/s)^2;
  * tau_m the rotor time constant (s); drag the linear drag coefficient (N s/m);
  * w_max the rotor speed limit (rad/s); w_ref the reference speed the stored
- * rotor rows are relative to (any value; the hover speed keeps them small).
+ * rotor rows are relative to (any value; the hover speed keeps them small);
+ * radius the collision radius (m) used by potato_detect_collisions.
  * gains = [kpp kip kdp kpa kia kda kpr kir kdr] (position, attitude, rate
  * loops; P, I, D).  step_budget: an agent of this type is advanced only
  * while its global step index is below it (INT32_MAX = unlimited). */
 typedef struct {
-    float mass, Ixx, Iyy, Izz, arm, alpha, k_f, k_m, tau_m, drag, w_max, w_ref;
+    float mass, Ixx, Iyy, Izz, arm, alpha, k_f, k_m, tau_m, drag, w_max, w_ref, radius;
     float gains[9];
     int32_t step_budget;
 } potato_type_params;
@@ -119,12 +120,16 @@ typedef struct {
  *   perm   int32[n_agents] processing order: lane j advances agent perm[j]
  *          (a permutation of 0..n_agents-1, e.g. from
  *          potato_order_by_type).  NULL = identity.
- *   gains  float[9][gains_ld] per-agent gains (NULL: the type's gains). */
+ *   gains  float[9][gains_ld] per-agent gains (NULL: the type's gains).
+ *   alive  uint8[n_agents]: agents with 0 are dead and are neither advanced
+ *          nor differentiated (their state and cotangent pass through);
+ *          NULL: all alive.  potato_detect_collisions maintains it. */
 typedef struct {
     const uint8_t* type;
     const int32_t* perm;
     const float* gains;
     int64_t gains_ld;
+    const uint8_t* alive;
 } potato_params;
 
 /* Commands (device pointers):
@@ -227,6 +232,25 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
                                    int32_t ckpt_every, int64_t ld, const float* grad_final,
                                    float* grad_x0, float* grad_gains, void* workspace,
                                    int64_t workspace_bytes, void* stream);
+
+/*
+ * Collision detection (the detection module of Sec. II-A: colliding agents
+ * are marked dead and excluded).  Among agents with alive[i] != 0 on entry,
+ * every agent i for which some other such agent j satisfies
+ * |p_i - p_j|^2 < (r_i + r_j)^2 gets alive[i] = 0; r is the type's radius.
+ * The test is FP32 with the operation order d2 = (dx*dx + dy*dy) + dz*dz,
+ * dx = x_i - x_j, compared against (r_i + r_j)*(r_i + r_j), no contraction;
+ * positions are rows 0-2 of the state.  All decisions use the entry alive
+ * set.  alive: device uint8[n_agents], in/out.  died (device int64, may be
+ * NULL) is incremented by the number of agents marked dead.  params->type is
+ * the optional type index; other params fields are ignored.  Exact for
+ * |coordinates| below 2^16 cell edges (cell edge 2.02 r_max; 22 km at
+ * r = 0.17 m).  workspace: potato_collision_workspace_bytes(n_agents) bytes.
+ */
+int64_t potato_collision_workspace_bytes(int64_t n_agents);
+potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                                       int64_t n_agents, uint8_t* alive, int64_t* died, void* workspace,
+                                       int64_t workspace_bytes, void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* potato_last_error(void);

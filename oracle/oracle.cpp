@@ -558,6 +558,76 @@ int oracle_count_ops(const oracle_type* type, const oracle_globals* gl, int mode
     return 0;
 }
 
+/*
+ * Collision detection of Sec. II-A: agents closer than the sum of their
+ * collision radii are marked dead (alive = 0) and excluded from then on.
+ * All pairs of agents alive on entry are tested, brute force; the decisions
+ * of one call are simultaneous (a pair kills both, a dead agent kills
+ * nobody).  The decision |p_i - p_j|^2 < (r_i + r_j)^2 is taken in FP32 with
+ * the operation order d2 = (dx*dx + dy*dy) + dz*dz, dx = x_i - x_j,
+ * rr = (r_i + r_j) * (r_i + r_j), every operation rounded to float and no
+ * fused multiply-add (this file is compiled without contraction).
+ * rows: FP32 state rows [>=3][ld] (rows 0-2 are the position).
+ * Returns the number of agents that died in this call, or -1 on bad input.
+ */
+int64_t oracle_detect_collisions(const float* rows, int64_t ld, int64_t n, const int32_t* type_idx,
+                                 const float* radius, int n_types, uint8_t* alive) {
+    if (!rows || !radius || !alive || n < 0 || ld < n || n_types < 1) return -1;
+    const float* x = rows;
+    const float* y = rows + ld;
+    const float* z = rows + 2 * ld;
+    uint8_t* hit = new uint8_t[n > 0 ? n : 1];
+    for (int64_t i = 0; i < n; ++i) hit[i] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!alive[i]) continue;
+        const float ri = radius[type_idx ? type_idx[i] : 0];
+        for (int64_t j = i + 1; j < n; ++j) {
+            if (!alive[j]) continue;
+            const float rj = radius[type_idx ? type_idx[j] : 0];
+            const float dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            const float dxx = dx * dx, dyy = dy * dy, dzz = dz * dz;
+            const float d2 = (dxx + dyy) + dzz;
+            const float rs = ri + rj;
+            const float rr = rs * rs;
+            if (d2 < rr) { hit[i] = 1; hit[j] = 1; }
+        }
+    }
+    int64_t died = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (hit[i]) { alive[i] = 0; ++died; }
+    delete[] hit;
+    return died;
+}
+
+/* The same decision for selected agents only: hit[q] = 1 when agent
+ * query[q] (alive) collides with any other alive agent.  O(n) per query. */
+int oracle_collides(const float* rows, int64_t ld, int64_t n, const int32_t* type_idx, const float* radius,
+                    int n_types, const uint8_t* alive, const int64_t* query, int64_t n_query, uint8_t* hit,
+                    int n_threads) {
+    if (!rows || !radius || !alive || !query || !hit || n < 0 || ld < n || n_types < 1) return -1;
+    const float* x = rows;
+    const float* y = rows + ld;
+    const float* z = rows + 2 * ld;
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+    for (int64_t q = 0; q < n_query; ++q) {
+        const int64_t i = query[q];
+        hit[q] = 0;
+        if (i < 0 || i >= n || !alive[i]) continue;
+        const float ri = radius[type_idx ? type_idx[i] : 0];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i || !alive[j]) continue;
+            const float rj = radius[type_idx ? type_idx[j] : 0];
+            const float dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            const float dxx = dx * dx, dyy = dy * dy, dzz = dz * dz;
+            const float d2 = (dxx + dyy) + dzz;
+            const float rs = ri + rj;
+            if (d2 < rs * rs) { hit[q] = 1; break; }
+        }
+    }
+    return 0;
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 }  // extern "C"

@@ -59,6 +59,10 @@ def lib():
         L.oracle_controller.argtypes = [P, P, P, P, P, P, D, P]
         L.oracle_allocation.argtypes = [P, P, P]
         L.oracle_count_ops.argtypes = [P, P, I, D, P]
+        L.oracle_detect_collisions.argtypes = [P, I64, I64, P, P, I, P]
+        L.oracle_detect_collisions.restype = C.c_int64
+        L.oracle_collides.argtypes = [P, I64, I64, P, P, I, P, P, I64, P, I]
+        L.oracle_collides.restype = C.c_int
         for fn in ("oracle_rollout", "oracle_jacobian", "oracle_derivative", "oracle_controller",
                    "oracle_allocation", "oracle_count_ops", "oracle_max_threads"):
             getattr(L, fn).restype = C.c_int
@@ -182,6 +186,34 @@ def count_ops(t: dict, glob: dict, mode: int, dt: float) -> dict:
     d = dict(zip(("add", "mul", "div", "sqrt", "cmp"), (int(v) for v in c)))
     d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
     return d
+
+
+def detect_collisions(rows, radius, alive, type_idx=None):
+    """Brute-force FP32 collision check; returns (new alive mask, number that died)."""
+    r = np.ascontiguousarray(np.asarray(rows)[:3], dtype=np.float32)
+    n = r.shape[1]
+    a = np.array(alive, dtype=np.uint8, copy=True)
+    rad = np.ascontiguousarray(radius, dtype=np.float32)
+    ti = None if type_idx is None else np.ascontiguousarray(type_idx, dtype=np.int32)
+    died = lib().oracle_detect_collisions(_p(r), n, n, _p(ti), _p(rad), int(rad.size), _p(a))
+    if died < 0:
+        raise ValueError("oracle_detect_collisions rejected its arguments")
+    return a, int(died)
+
+
+def collides(rows, radius, alive, query, type_idx=None, threads=None):
+    """Collision decision of the agents ``query`` against all alive agents."""
+    r = np.ascontiguousarray(np.asarray(rows)[:3], dtype=np.float32)
+    n = r.shape[1]
+    a = np.ascontiguousarray(alive, dtype=np.uint8)
+    rad = np.ascontiguousarray(radius, dtype=np.float32)
+    ti = None if type_idx is None else np.ascontiguousarray(type_idx, dtype=np.int32)
+    qi = np.ascontiguousarray(query, dtype=np.int64)
+    hit = np.zeros(qi.size, dtype=np.uint8)
+    if lib().oracle_collides(_p(r), n, n, _p(ti), _p(rad), int(rad.size), _p(a), _p(qi), qi.size,
+                             _p(hit), int(threads or threads_default())) != 0:
+        raise ValueError("oracle_collides rejected its arguments")
+    return hit
 
 
 def max_threads() -> int:

@@ -19,7 +19,7 @@ OPEN_LOOP, CLOSED_LOOP = 0, 1
 FORM_AUTO, FORM_PLAIN, FORM_FUSED = 0, 1, 2
 
 TYPE_FIELDS = ("mass", "Ixx", "Iyy", "Izz", "arm", "alpha", "k_f", "k_m", "tau_m", "drag",
-               "w_max", "w_ref")
+               "w_max", "w_ref", "radius")
 LIMIT_FIELDS = ("g", "r_sat", "ipos_max", "iatt_max", "irate_max", "az_min_frac")
 
 
@@ -44,7 +44,7 @@ class State(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("type", C.c_void_p), ("perm", C.c_void_p), ("gains", C.c_void_p),
-                ("gains_ld", C.c_int64)]
+                ("gains_ld", C.c_int64), ("alive", C.c_void_p)]
 
 
 class Cmds(C.Structure):
@@ -89,12 +89,16 @@ def load():
     L.potato_backward_workspace_bytes.argtypes = [P, P, I64, I32]
     L.potato_backward_workspace_bytes.restype = I64
     L.potato_step_backward.argtypes = [P, P, P, F, I64, I32, P, I32, I64, P, P, P, P, I64, P]
+    L.potato_collision_workspace_bytes.argtypes = [I64]
+    L.potato_collision_workspace_bytes.restype = I64
+    L.potato_detect_collisions.argtypes = [P, P, P, I64, P, P, P, I64, P]
     L.potato_last_error.argtypes = []
     L.potato_last_error.restype = C.c_char_p
     L.potato_version.argtypes = []
     L.potato_version.restype = C.c_char_p
     for fn in ("potato_create", "potato_destroy", "potato_set_options", "potato_step",
-               "potato_autotune", "potato_order_by_type", "potato_step_backward"):
+               "potato_autotune", "potato_order_by_type", "potato_step_backward",
+               "potato_detect_collisions"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L
@@ -109,7 +113,7 @@ def make_type_params(types) -> C.Array:
     arr = (TypeParams * len(types))()
     for i, t in enumerate(types):
         for f in TYPE_FIELDS:
-            setattr(arr[i], f, float(t[f]))
+            setattr(arr[i], f, float(t.get(f, t["arm"]) if f == "radius" else t[f]))
         for k in range(9):
             arr[i].gains[k] = float(t["gains"][k])
         arr[i].step_budget = int(min(int(t.get("budget", 2**31 - 1)), 2**31 - 1))

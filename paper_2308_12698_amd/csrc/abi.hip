@@ -60,6 +60,8 @@ struct potato_ctx {
     std::vector<TypeConst> consts;
     TypeConst* d_table = nullptr;
     int32_t* d_rank = nullptr;         /* rank of each type by budget (longest first) */
+    float* d_radius = nullptr;         /* collision radius per type */
+    float r_max = 0.0f;
     potato_limits limits{};
     potato_options opts{};
     hipStream_t cap_stream = nullptr;
@@ -134,8 +136,8 @@ potato_status check_type(const potato_type_params& p, int t) {
     if (!std::isfinite(p.alpha) || std::fabs(std::sin(p.alpha)) < 1e-6f || std::fabs(std::cos(p.alpha)) < 1e-6f)
         return fail(POTATO_EINVAL, "type %d: alpha must be finite with sin and cos away from 0", t);
     if (!std::isfinite(p.drag) || p.drag < 0.0f || !std::isfinite(p.w_max) || p.w_max < 0.0f ||
-        !std::isfinite(p.w_ref) || p.w_ref < 0.0f)
-        return fail(POTATO_EINVAL, "type %d: drag, w_max, w_ref must be finite and >= 0", t);
+        !std::isfinite(p.w_ref) || p.w_ref < 0.0f || !std::isfinite(p.radius) || p.radius < 0.0f)
+        return fail(POTATO_EINVAL, "type %d: drag, w_max, w_ref, radius must be finite and >= 0", t);
     for (int k = 0; k < 9; ++k)
         if (!std::isfinite(p.gains[k])) return fail(POTATO_EINVAL, "type %d: gains must be finite", t);
     return POTATO_OK;
@@ -162,7 +164,7 @@ potato_status check_options(const potato_options& o) {
 }
 
 void drop_graphs(potato_ctx* ctx) {
-    for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     ctx->graphs.clear();
 }
 
@@ -216,12 +218,9 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     a.step0 = cm->step0; a.k0 = 0; a.n_steps = 0;
     a.ckpt = ckpt; a.ckpt_every = ckpt_every > 0 ? ckpt_every : 1;
     a.n_types = ctx->n_types; a.table = ctx->d_table;
+    a.alive = pp->alive;
     a.lim = make_limits(ctx->limits, dt);
-    a.tc0 = ctx->consts[0];
-    if (!P.v.het) {
-        /* homogeneous launch: type 0's constants travel in the argument segment */
-        a.n_types = 1;
-    }
+    if (!P.v.het) a.n_types = 1;      /* homogeneous launch: only type 0 is staged */
 
     const potato_options& o = ctx->opts;
     Tuned t{256, 100, 0};
@@ -257,7 +256,7 @@ std::vector<int64_t> graph_key(const Plan& P, int32_t n_steps, float dt) {
     std::memcpy(&dtbits, &dt, 4);
     return {(int64_t)a.rows, a.ld, a.n, (int64_t)a.type, (int64_t)a.perm, (int64_t)a.gains, a.gains_ld,
             (int64_t)a.motor_cmd, (int64_t)a.wp, a.cmd_ld, a.n_epochs, a.resample, a.step0, n_steps,
-            dtbits, (int64_t)a.ckpt, a.ckpt_every, P.block, P.steps, P.grid, P.v.mode};
+            dtbits, (int64_t)a.ckpt, a.ckpt_every, P.block, P.steps, P.grid, P.v.mode, (int64_t)a.alive};
 }
 
 }  // namespace
@@ -293,9 +292,17 @@ potato_status potato_create(potato_ctx** out, const potato_type_params* types, i
                      [&](int a, int b) { return types[a].step_budget > types[b].step_budget; });
     for (int r = 0; r < n_types; ++r) rank[order[r]] = r;
 
+    std::vector<float> radius(n_types);
+    for (int t = 0; t < n_types; ++t) {
+        radius[t] = types[t].radius;
+        ctx->r_max = std::max(ctx->r_max, types[t].radius);
+    }
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipMalloc(&ctx->d_table, sizeof(TypeConst) * n_types);
     if (e == hipSuccess) e = hipMalloc(&ctx->d_rank, sizeof(int32_t) * n_types);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_radius, sizeof(float) * n_types);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_radius, radius.data(), sizeof(float) * n_types, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_table, ctx->consts.data(), sizeof(TypeConst) * n_types, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_rank, rank.data(), sizeof(int32_t) * n_types, hipMemcpyHostToDevice);
@@ -311,9 +318,10 @@ potato_status potato_create(potato_ctx** out, const potato_type_params* types, i
 potato_status potato_destroy(potato_ctx* ctx) {
     if (!ctx) return POTATO_OK;
     drop_graphs(ctx);
-    if (ctx->d_table) hipFree(ctx->d_table);
-    if (ctx->d_rank) hipFree(ctx->d_rank);
-    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    if (ctx->d_table) (void)hipFree(ctx->d_table);
+    if (ctx->d_rank) (void)hipFree(ctx->d_rank);
+    if (ctx->d_radius) (void)hipFree(ctx->d_radius);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return POTATO_OK;
 }
@@ -351,10 +359,10 @@ potato_status potato_step(potato_ctx* ctx, const potato_state* state, const pota
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         hipError_t le = enqueue(P, n_steps, ctx->cap_stream);
         e = hipStreamEndCapture(ctx->cap_stream, &graph);
-        if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "potato_step capture"); }
+        if (le != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(le, "potato_step capture"); }
         if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
         it = ctx->graphs.emplace(key, exec).first;
     }
@@ -417,10 +425,10 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
         }
     }
     ctx->opts = saved;
-    if (t0) hipEventDestroy(t0);
-    if (t1) hipEventDestroy(t1);
-    hipStreamSynchronize(hs);
-    hipFree(scratch);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipStreamSynchronize(hs);
+    (void)hipFree(scratch);
     if (e != hipSuccess) return hip_fail(e, "potato_autotune");
     const bool het = params->type != nullptr;
     ctx->tuned[TuneKey{ctx->opts.mode, het, ctx->opts.mode == 1 && params->gains != nullptr,
@@ -442,7 +450,7 @@ namespace {
  * never more than the agents need (one tape column per thread). */
 int adjoint_grid(potato_ctx* ctx, bool het, bool gains, bool perm, int64_t n) {
     int per_cu = 0, n_cu = 0;
-    const size_t lds = het ? (size_t)ctx->n_types * sizeof(TypeConst) : 0;
+    const size_t lds = adjoint_lds_bytes(het, ctx->n_types);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adjoint_kernel(het, gains, perm), kAdjBlock, lds) !=
             hipSuccess ||
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
@@ -499,8 +507,8 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
     a.grad_final = grad_final; a.grad_x0 = grad_x0; a.grad_gains = grad_gains;
     a.tape = reinterpret_cast<float*>(workspace); a.tape_ld = (int64_t)grid * kAdjBlock;
     a.n_types = het ? ctx->n_types : 1; a.table = ctx->d_table;
+    a.alive = params->alive;
     a.lim = make_limits(ctx->limits, dt);
-    a.tc0 = ctx->consts[0];
     hipError_t e = launch_adjoint(het, gains, perm, a, kAdjBlock, grid, reinterpret_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_step_backward launch");
@@ -524,6 +532,28 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
     hipError_t e = launch_order_by_type(type, n_agents, ctx->n_types, ctx->d_rank, perm, counts, base,
                                         reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_order_by_type");
+}
+
+int64_t potato_collision_workspace_bytes(int64_t n_agents) {
+    if (n_agents < 1 || n_agents > 0x3fffffffLL) return -1;
+    return collision_workspace_bytes(n_agents);
+}
+
+potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                                       int64_t n_agents, uint8_t* alive, int64_t* died, void* workspace,
+                                       int64_t workspace_bytes, void* stream) {
+    if (!ctx || !state || !state->rows || !alive || !workspace)
+        return fail(POTATO_EINVAL, "ctx, state, state.rows, alive and workspace must be non-null");
+    if (n_agents < 1 || n_agents > 0x3fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30)");
+    if (state->ld < n_agents) return fail(POTATO_EINVAL, "state.ld < n_agents");
+    const int64_t need = collision_workspace_bytes(n_agents);
+    if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
+    if (!(ctx->r_max > 0.0f)) return fail(POTATO_EINVAL, "every type has radius 0: nothing can collide");
+    hipError_t e = launch_detect_collisions(state->rows, state->ld, n_agents, params ? params->type : nullptr,
+                                            ctx->d_radius, ctx->r_max, alive,
+                                            reinterpret_cast<unsigned long long*>(died), workspace,
+                                            reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_detect_collisions launch");
 }
 
 const char* potato_last_error(void) { return g_err.c_str(); }

@@ -35,8 +35,8 @@ struct StepArgs {
     int32_t ckpt_every;
     int32_t n_types;
     const TypeConst* table;      /* device [n_types] */
+    const uint8_t* alive;        /* [ld] or null: 0 = dead, not advanced */
     Limits lim;
-    TypeConst tc0;               /* type 0, read from the argument segment */
 };
 
 struct Variant {
@@ -70,8 +70,8 @@ struct AdjArgs {
     int64_t tape_ld;
     int32_t n_types;
     const TypeConst* table;
+    const uint8_t* alive;
     Limits lim;
-    TypeConst tc0;
 };
 
 /* Launch one rollout kernel (n_steps of args) on `stream`. */
@@ -86,6 +86,7 @@ const void* rollout_kernel(const Variant& v);
 const void* adjoint_kernel(bool het, bool gains, bool perm);
 hipError_t launch_adjoint(bool het, bool gains, bool perm, const AdjArgs& a, int block, int grid_blocks,
                           hipStream_t stream);
+size_t adjoint_lds_bytes(bool het, int n_types);
 constexpr int kAdjBlock = 256;
 
 /* Dynamic LDS bytes the variant needs for n_types. */
@@ -97,5 +98,12 @@ hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types,
                                 int32_t* block_counts, int32_t* block_base, hipStream_t stream);
 
 constexpr int kOrderBlock = 256;
+
+/* Collision detection on a hashed grid (see collide.hip). */
+uint32_t collision_buckets(int64_t n);
+int64_t collision_workspace_bytes(int64_t n);
+hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type,
+                                    const float* radius_dev, float r_max, uint8_t* alive,
+                                    unsigned long long* died, void* workspace, hipStream_t s);
 
 }  // namespace potato

@@ -27,6 +27,9 @@ namespace {
 /* Occupancy target of the rollout kernel in waves per SIMD (0 = compiler's
  * choice).  Fewer registers per lane buy more resident waves to hide the
  * latency of dependent FP32 chains and transcendental ops. */
+#ifndef POTATO_LIMITS_FROM_LDS
+#define POTATO_LIMITS_FROM_LDS 0
+#endif
 #ifndef POTATO_ROLLOUT_WAVES
 #define POTATO_ROLLOUT_WAVES 3
 #endif
@@ -36,22 +39,38 @@ namespace {
 #define POTATO_ROLLOUT_ATTR
 #endif
 
+/* The per-type constants (and the launch's limits) are staged in LDS and
+ * read from there by every lane, also when all agents share one type:
+ * values loaded from LDS live in vector registers, and the step's FMAs then
+ * take them as vector operands.  As scalar-register operands of the same
+ * instructions (kernel arguments) the step measured 16-20 % slower. */
+__device__ __forceinline__ void stage_constants(const TypeConst* table, int n_types, const Limits& lim,
+                                                TypeConst* tab, Limits* l) {
+    const int words = n_types * (int)(sizeof(TypeConst) / 4);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(table);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x == 0) *l = lim;
+    __syncthreads();
+}
+
 template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
 __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
     extern __shared__ float4 lds_raw[];
-    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw);
-    if (HET) {
-        const int words = A.n_types * (int)(sizeof(TypeConst) / 4);
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(A.table);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
-        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
-        __syncthreads();
-    }
+    Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
+    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw + (sizeof(Limits) + 15) / 16);
+    stage_constants(A.table, A.n_types, A.lim, tab, lim_lds);
+#if POTATO_LIMITS_FROM_LDS
+    const Limits& lim = *lim_lds;
+#else
+    const Limits& lim = A.lim;
+#endif
     const int64_t ld = A.ld;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.n; j += stride) {
         const int64_t i = PERM ? (int64_t)A.perm[j] : j;
-        const TypeConst& c = HET ? tab[A.type[i]] : A.tc0;
+        const TypeConst& c = HET ? tab[A.type[i]] : tab[0];
+        if (A.alive && !A.alive[i]) continue;
 
         int64_t left = (int64_t)c.budget - A.step0;
         left = left < 0 ? 0 : left;
@@ -140,9 +159,9 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
                     for (int k = 0; k < 3; ++k) wp[k] = A.wp[((int64_t)epoch * 3 + k) * A.cmd_ld + i];
                     next_epoch_step = epoch < A.n_epochs - 1 ? next_epoch_step + A.resample : INT64_MAX;
                 }
-                controller(c, A.lim, g, a, wp, dc);
+                controller(c, lim, g, a, wp, dc);
             }
-            rk4_step(c, A.lim, a, dc);
+            rk4_step(c, lim, a, dc);
         }
 
 #pragma unroll
@@ -168,27 +187,33 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 /* Reverse sweep of the checkpointed closed-loop rollout: one agent per lane
  * (grid-stride), cotangents and gain sums in registers, the recomputed
  * segment in this thread's tape column. */
+#ifndef POTATO_ADJOINT_WAVES
+#define POTATO_ADJOINT_WAVES 1
+#endif
+
 template <bool HET, bool GAINS, bool PERM>
-__global__ void __launch_bounds__(kAdjBlock) k_adjoint(const AdjArgs A) {
+__global__ void __launch_bounds__(kAdjBlock)
+    __attribute__((amdgpu_waves_per_eu(POTATO_ADJOINT_WAVES, POTATO_ADJOINT_WAVES))) k_adjoint(const AdjArgs A) {
     extern __shared__ float4 lds_raw[];
-    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw);
-    if (HET) {
-        const int words = A.n_types * (int)(sizeof(TypeConst) / 4);
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(A.table);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(tab);
-        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
-        __syncthreads();
-    }
+    Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
+    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw + (sizeof(Limits) + 15) / 16);
+    stage_constants(A.table, A.n_types, A.lim, tab, lim_lds);
+#if POTATO_LIMITS_FROM_LDS
+    const Limits& lim = *lim_lds;
+#else
+    const Limits& lim = A.lim;
+#endif
     const int64_t ld = A.ld;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     float* tape_col = A.tape + tid;
     for (int64_t j = tid; j < A.n; j += stride) {
         const int64_t i = PERM ? (int64_t)A.perm[j] : j;
-        const TypeConst& c = HET ? tab[A.type[i]] : A.tc0;
+        const TypeConst& c = HET ? tab[A.type[i]] : tab[0];
         int64_t left = (int64_t)c.budget - A.step0;
         left = left < 0 ? 0 : left;
-        const int steps = left < A.n_steps ? (int)left : A.n_steps;
+        int steps = left < A.n_steps ? (int)left : A.n_steps;
+        if (A.alive && !A.alive[i]) steps = 0;      /* dead: identity map */
         Gains g;
         if (GAINS) {
             const float* gp = A.gains + i;
@@ -203,7 +228,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint(const AdjArgs A) {
         load_adj(A.grad_final + i, ld, lam);
         float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (steps > 0)
-            agent_backward(c, A.lim, g, A.ckpt + i, ld, A.K, steps, A.step0, A.wp + i, A.cmd_ld,
+            agent_backward(c, lim, g, A.ckpt + i, ld, A.K, steps, A.step0, A.wp + i, A.cmd_ld,
                            A.n_epochs, A.resample, tape_col, A.tape_ld, lam, gk);
         store_adj(A.grad_x0 + i, ld, lam);
         if (A.grad_gains) {
@@ -310,6 +335,10 @@ const void* afn() {
     return reinterpret_cast<const void*>(&k_adjoint<H, G, P>);
 }
 
+size_t adjoint_lds_bytes(bool het, int n_types) {
+    return ((sizeof(Limits) + 15) / 16) * 16 + (size_t)(het ? n_types : 1) * sizeof(TypeConst);
+}
+
 const void* adjoint_kernel(bool het, bool gains, bool perm) {
     if (!het) return gains ? afn<false, true, false>() : afn<false, false, false>();
     if (perm) return gains ? afn<true, true, true>() : afn<true, false, true>();
@@ -319,13 +348,13 @@ const void* adjoint_kernel(bool het, bool gains, bool perm) {
 hipError_t launch_adjoint(bool het, bool gains, bool perm, const AdjArgs& a, int block, int grid_blocks,
                           hipStream_t stream) {
     void* args[] = {const_cast<AdjArgs*>(&a)};
-    const size_t lds = het ? (size_t)a.n_types * sizeof(TypeConst) : 0;
+    const size_t lds = adjoint_lds_bytes(het, a.n_types);
     return hipLaunchKernel(adjoint_kernel(het, gains, perm), dim3((unsigned)grid_blocks), dim3((unsigned)block),
                            args, lds, stream);
 }
 
 size_t rollout_lds_bytes(const Variant& v, int n_types) {
-    return v.het ? (size_t)n_types * sizeof(TypeConst) : 0;
+    return ((sizeof(Limits) + 15) / 16) * 16 + (size_t)(v.het ? n_types : 1) * sizeof(TypeConst);
 }
 
 hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int grid_blocks,

@@ -117,72 +117,13 @@ __device__ __forceinline__ void dyn_axpy(const Dyn& x, float h, const Dyn& k, Dy
 __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, const Gains& k,
                                          const Agent& a, const float wp[3], AgentAdj& lam,
                                          float gk[9]) {
-    /* ---------------- controller, forward with intermediates ---------------- */
-    float er[3] = {wp[0] - a.p[0], wp[1] - a.p[1], wp[2] - a.p[2]};
-    const float n2 = er[0] * er[0] + er[1] * er[1] + er[2] * er[2];
-    const bool sat = n2 > L.r_sat2;
-    float rs = 0.0f, sc = 1.0f;
-    if (sat) { rs = rsq(n2); sc = L.r_sat * rs; }
-    const float e[3] = {er[0] * sc, er[1] * sc, er[2] * sc};
-    float ipn[3];
-    bool in_ip[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float pre = a.ip[i] + e[i] * L.dt;
-        in_ip[i] = !(pre < -L.ipos_max) && !(pre > L.ipos_max);
-        ipn[i] = clampf_(pre, -L.ipos_max, L.ipos_max);
-    }
-    float acc[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) acc[i] = k.kpp * e[i] + k.kip * ipn[i] - k.kdp * a.v[i];
-    acc[2] += L.g;
-    const bool az_cl = acc[2] < L.az_min;
-    if (az_cl) acc[2] = L.az_min;
-    float bz[3];
-    body_z(a.q, bz);
-    const float fc = c.mass * (acc[0] * bz[0] + acc[1] * bz[1] + acc[2] * bz[2]);
-    const float ra = rsq(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
-    const float nv[3] = {acc[0] * ra, acc[1] * ra, acc[2] * ra};
-    const float qr0 = 1.0f + nv[2], qr1 = -nv[1], qr2 = nv[0];
-    const float rq = rsq(qr0 * qr0 + qr1 * qr1 + qr2 * qr2);
-    const float qd[3] = {qr0 * rq, qr1 * rq, qr2 * rq};
-    const float* q = a.q;
-    const float qew = q[0] * qd[0] + q[1] * qd[1] + q[2] * qd[2];
-    const float qex = q[0] * qd[1] - q[1] * qd[0] + q[3] * qd[2];
-    const float qey = q[0] * qd[2] - q[2] * qd[0] - q[3] * qd[1];
-    const float qez = q[2] * qd[1] - q[1] * qd[2] - q[3] * qd[0];
-    const float sg = qew < 0.0f ? -2.0f : 2.0f;
-    const float eatt[3] = {sg * qex, sg * qey, sg * qez};
-    float ian[3], irn[3], wdes[3], erate[3], alpha[3];
-    bool in_ia[3], in_ir[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float pa = a.ia[i] + eatt[i] * L.dt;
-        in_ia[i] = !(pa < -L.iatt_max) && !(pa > L.iatt_max);
-        ian[i] = clampf_(pa, -L.iatt_max, L.iatt_max);
-        wdes[i] = k.kpa * eatt[i] + k.kia * ian[i] - k.kda * a.w[i];
-        erate[i] = wdes[i] - a.w[i];
-        const float pr = a.ir[i] + erate[i] * L.dt;
-        in_ir[i] = !(pr < -L.irate_max) && !(pr > L.irate_max);
-        irn[i] = clampf_(pr, -L.irate_max, L.irate_max);
-        alpha[i] = k.kpr * erate[i] + k.kir * irn[i] - k.kdr * ((a.w[i] - a.wprev[i]) * L.inv_dt);
-    }
-    const float Iwx = c.Ix * a.w[0], Iwy = c.Iy * a.w[1], Iwz = c.Iz * a.w[2];
-    const float tx = c.Ix * alpha[0] + (a.w[1] * Iwz - a.w[2] * Iwy);
-    const float ty = c.Iy * alpha[1] + (a.w[2] * Iwx - a.w[0] * Iwz);
-    const float tz = c.Iz * alpha[2] + (a.w[0] * Iwy - a.w[1] * Iwx);
-    const float f4 = 0.25f * fc;
-    const float X = tx * c.mix_x, Y = ty * c.mix_y, Z = tz * c.mix_z;
-    const float f[4] = {f4 + X - Y + Z, f4 - X - Y - Z, f4 - X + Y + Z, f4 + X + Y - Z};
-    float dc[4], lf_scale[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const bool in_f = !(f[i] < 0.0f) && !(f[i] > c.f_max);
-        const float fi = clampf_(f[i], 0.0f, c.f_max);
-        const float W = sqrt_fast(fi * c.inv_kf);
-        dc[i] = W - c.w_ref;
-        /* d W / d f = inv_kf / (2 W), zero when clamped or W == 0 */
-        lf_scale[i] = (in_f && W > 0.0f) ? 0.5f * c.inv_kf / W : 0.0f;
+    /* ---------------- held command: the forward controller on a copy ----------------
+     * (its intermediates are recomputed below, after the RK4 reverse, so they
+     * are not live while the stage states are) */
+    float dc[4];
+    {
+        Agent tmp = a;
+        controller(c, L, k, tmp, wp, dc);
     }
 
     /* ---------------- RK4 forward, keeping the stage states ---------------- */
@@ -270,6 +211,73 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
             sq[i] = nq_[i]; sd[i] = nd_[i];
             lam.q[i] += nq_[i]; lam.d[i] += nd_[i];
         }
+    }
+
+    /* ---------------- controller, forward with intermediates ---------------- */
+    float er[3] = {wp[0] - a.p[0], wp[1] - a.p[1], wp[2] - a.p[2]};
+    const float n2 = er[0] * er[0] + er[1] * er[1] + er[2] * er[2];
+    const bool sat = n2 > L.r_sat2;
+    float rs = 0.0f, sc = 1.0f;
+    if (sat) { rs = rsq(n2); sc = L.r_sat * rs; }
+    const float e[3] = {er[0] * sc, er[1] * sc, er[2] * sc};
+    float ipn[3];
+    bool in_ip[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float pre = a.ip[i] + e[i] * L.dt;
+        in_ip[i] = !(pre < -L.ipos_max) && !(pre > L.ipos_max);
+        ipn[i] = clampf_(pre, -L.ipos_max, L.ipos_max);
+    }
+    float acc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] = k.kpp * e[i] + k.kip * ipn[i] - k.kdp * a.v[i];
+    acc[2] += L.g;
+    const bool az_cl = acc[2] < L.az_min;
+    if (az_cl) acc[2] = L.az_min;
+    float bz[3];
+    body_z(a.q, bz);
+    const float fc = c.mass * (acc[0] * bz[0] + acc[1] * bz[1] + acc[2] * bz[2]);
+    const float ra = rsq(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+    const float nv[3] = {acc[0] * ra, acc[1] * ra, acc[2] * ra};
+    const float qr0 = 1.0f + nv[2], qr1 = -nv[1], qr2 = nv[0];
+    const float rq = rsq(qr0 * qr0 + qr1 * qr1 + qr2 * qr2);
+    const float qd[3] = {qr0 * rq, qr1 * rq, qr2 * rq};
+    const float* q = a.q;
+    const float qew = q[0] * qd[0] + q[1] * qd[1] + q[2] * qd[2];
+    const float qex = q[0] * qd[1] - q[1] * qd[0] + q[3] * qd[2];
+    const float qey = q[0] * qd[2] - q[2] * qd[0] - q[3] * qd[1];
+    const float qez = q[2] * qd[1] - q[1] * qd[2] - q[3] * qd[0];
+    const float sg = qew < 0.0f ? -2.0f : 2.0f;
+    const float eatt[3] = {sg * qex, sg * qey, sg * qez};
+    float ian[3], irn[3], wdes[3], erate[3], alpha[3];
+    bool in_ia[3], in_ir[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float pa = a.ia[i] + eatt[i] * L.dt;
+        in_ia[i] = !(pa < -L.iatt_max) && !(pa > L.iatt_max);
+        ian[i] = clampf_(pa, -L.iatt_max, L.iatt_max);
+        wdes[i] = k.kpa * eatt[i] + k.kia * ian[i] - k.kda * a.w[i];
+        erate[i] = wdes[i] - a.w[i];
+        const float pr = a.ir[i] + erate[i] * L.dt;
+        in_ir[i] = !(pr < -L.irate_max) && !(pr > L.irate_max);
+        irn[i] = clampf_(pr, -L.irate_max, L.irate_max);
+        alpha[i] = k.kpr * erate[i] + k.kir * irn[i] - k.kdr * ((a.w[i] - a.wprev[i]) * L.inv_dt);
+    }
+    const float Iwx = c.Ix * a.w[0], Iwy = c.Iy * a.w[1], Iwz = c.Iz * a.w[2];
+    const float tx = c.Ix * alpha[0] + (a.w[1] * Iwz - a.w[2] * Iwy);
+    const float ty = c.Iy * alpha[1] + (a.w[2] * Iwx - a.w[0] * Iwz);
+    const float tz = c.Iz * alpha[2] + (a.w[0] * Iwy - a.w[1] * Iwx);
+    const float f4 = 0.25f * fc;
+    const float X = tx * c.mix_x, Y = ty * c.mix_y, Z = tz * c.mix_z;
+    const float f[4] = {f4 + X - Y + Z, f4 - X - Y - Z, f4 - X + Y + Z, f4 + X + Y - Z};
+    float lf_scale[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool in_f = !(f[i] < 0.0f) && !(f[i] > c.f_max);
+        const float fi = clampf_(f[i], 0.0f, c.f_max);
+        const float W = sqrt_fast(fi * c.inv_kf);
+        /* d W / d f = inv_kf / (2 W), zero when clamped or W == 0 */
+        lf_scale[i] = (in_f && W > 0.0f) ? 0.5f * c.inv_kf / W : 0.0f;
     }
 
     /* ---------------- reverse: controller ---------------- */
@@ -451,6 +459,20 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
                                                int n_epochs, int resample, float* tape_col,
                                                int64_t tape_ld, AgentAdj& lam, float gk[9]) {
     const int n_seg = (steps + K - 1) / K;
+    /* the waypoint is reloaded only when the epoch changes */
+    int64_t cur_ep = -1;
+    float wp[3] = {0.0f, 0.0f, 0.0f};
+    auto epoch_of = [&](int64_t k) {
+        int64_t ep = resample > 0 ? k / resample : 0;
+        return ep < n_epochs - 1 ? ep : (int64_t)n_epochs - 1;
+    };
+    auto use_epoch = [&](int64_t ep) {
+        if (ep != cur_ep) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) wp[i] = wp_col[(ep * 3 + i) * cmd_ld];
+            cur_ep = ep;
+        }
+    };
     for (int seg = n_seg - 1; seg >= 0; --seg) {
         const int k_begin = seg * K;
         const int len = steps - k_begin < K ? steps - k_begin : K;
@@ -458,17 +480,21 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         load_rows(ckpt_col + (int64_t)seg * 40 * ld, ld, a, true);
         for (int s = 0; s < len; ++s) {
             store_phys_rows(tape_col + (int64_t)s * 30 * tape_ld, tape_ld, a);
-            float wp[3], dc[4];
-            waypoint_at(wp_col, cmd_ld, n_epochs, resample, step0 + k_begin + s, wp);
+            float dc[4];
+            use_epoch(epoch_of(step0 + k_begin + s));
             controller(c, L, g, a, wp, dc);
             rk4_step(c, L, a, dc);
         }
+        /* reverse sweep; the tape slot of the next (earlier) step is loaded
+         * while the current step is differentiated */
+        Agent x;
+        load_rows(tape_col + (int64_t)(len - 1) * 30 * tape_ld, tape_ld, x, false);
         for (int s = len - 1; s >= 0; --s) {
-            Agent x;
-            load_rows(tape_col + (int64_t)s * 30 * tape_ld, tape_ld, x, false);
-            float wp[3];
-            waypoint_at(wp_col, cmd_ld, n_epochs, resample, step0 + k_begin + s, wp);
+            Agent nx;
+            if (s > 0) load_rows(tape_col + (int64_t)(s - 1) * 30 * tape_ld, tape_ld, nx, false);
+            use_epoch(epoch_of(step0 + k_begin + s));
             step_vjp(c, L, g, x, wp, lam, gk);
+            if (s > 0) x = nx;
         }
     }
 }

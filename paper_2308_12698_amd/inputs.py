@@ -109,6 +109,7 @@ def make_type(mass, Ixx, Iyy, Izz, arm, k_f, k_m, tau_m=0.02, drag=0.1,
     if w_ref is None:
         w_ref = hover_reference_speed(t["mass"], t["k_f"], np.float32(g))
     t["w_ref"] = np.float32(w_ref)
+    t["radius"] = t["arm"]          # collision radius: rotor hub distance
     t["gains"] = f32(gains)
     t["budget"] = int(budget)
     return t

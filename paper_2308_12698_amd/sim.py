@@ -80,7 +80,14 @@ class Simulator:
             pass
 
     # -- argument structs -------------------------------------------------
-    def _structs(self, state, n, type_idx, perm, gains, motor_cmd, wp, resample_every, step0):
+    @staticmethod
+    def _check_mask(name, t, n):
+        if t is not None and (not t.is_cuda or t.dtype != torch.uint8 or t.dim() != 1
+                              or t.shape[0] < n or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous device uint8 tensor of length >= n")
+
+    def _structs(self, state, n, type_idx, perm, gains, motor_cmd, wp, resample_every, step0,
+                 alive=None):
         _check_rows("state", state, N_ROWS, n)
         ld = state.stride(0)
         if type_idx is not None:
@@ -108,17 +115,20 @@ class Simulator:
                 raise ValueError("motor_cmd and wp must share their row stride")
             cmd_ld = wp.shape[2]
         st = L.State(C.c_void_p(state.data_ptr()), ld)
-        pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains), gains.stride(0) if gains is not None else 0)
+        self._check_mask("alive", alive, n)
+        pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains), gains.stride(0) if gains is not None else 0,
+                      _ptr(alive))
         cm = L.Cmds(_ptr(motor_cmd), _ptr(wp), n_epochs, int(resample_every), cmd_ld, int(step0))
         return st, pp, cm
 
     def step(self, state, n_steps, dt, *, n_agents=None, type_idx=None, perm=None, gains=None,
              motor_cmd=None, wp=None, resample_every=0, step0=0, ckpt=None, ckpt_every=0,
-             stream=None):
-        """Advance ``state`` ([40, ld] float32, in place) by n_steps steps."""
+             alive=None, stream=None):
+        """Advance ``state`` ([40, ld] float32, in place) by n_steps steps.
+        ``alive`` (uint8 [n], optional): agents with 0 are not advanced."""
         n = int(n_agents if n_agents is not None else state.shape[1])
         st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
-                                   resample_every, step0)
+                                   resample_every, step0, alive)
         if ckpt is not None:
             slots = -(-int(n_steps) // int(ckpt_every)) if ckpt_every > 0 else 0
             if not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous() \
@@ -145,7 +155,7 @@ class Simulator:
 
     def step_backward(self, ckpt, ckpt_every, n_steps, dt, grad_final, *, n_agents=None,
                       type_idx=None, perm=None, gains=None, wp=None, resample_every=0, step0=0,
-                      want_gains=True, workspace=None, stream=None):
+                      want_gains=True, workspace=None, alive=None, stream=None):
         """Reverse sweep of a checkpointed closed-loop step() call.
 
         grad_final: [30, ld] cotangent of the final physical rows.  Returns
@@ -162,8 +172,9 @@ class Simulator:
         slots = -(-int(n_steps) // int(ckpt_every))
         if ckpt.numel() < slots * N_ROWS * ld:
             raise ValueError(f"ckpt must hold {slots} x {N_ROWS} x {ld} floats")
+        self._check_mask("alive", alive, n)
         pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains),
-                      gains.stride(0) if gains is not None else 0)
+                      gains.stride(0) if gains is not None else 0, _ptr(alive))
         if wp is None or wp.dim() != 3 or not wp.is_contiguous():
             raise ValueError("wp must be a contiguous device float32 tensor [E, 3, >= n]")
         cm = L.Cmds(None, _ptr(wp), wp.shape[0], int(resample_every), wp.shape[2], int(step0))
@@ -179,6 +190,28 @@ class Simulator:
                                                _ptr(grad_final), _ptr(gx0), _ptr(gg), _ptr(workspace),
                                                nbytes, _stream_handle(stream)))
         return gx0, gg
+
+    def detect_collisions(self, state, alive, *, n_agents=None, type_idx=None, died=None,
+                          workspace=None, stream=None):
+        """Mark colliding agents dead in ``alive`` (uint8 [n], in place).
+        ``died`` (int64 device scalar, optional) is incremented by the count."""
+        n = int(n_agents if n_agents is not None else state.shape[1])
+        _check_rows("state", state, N_ROWS, n)
+        self._check_mask("alive", alive, n)
+        self._check_mask("type_idx", type_idx, n)
+        if died is not None and (not died.is_cuda or died.dtype != torch.int64 or died.numel() < 1):
+            raise ValueError("died must be a device int64 tensor")
+        nbytes = int(self._lib.potato_collision_workspace_bytes(n))
+        if nbytes < 0:
+            raise ValueError("invalid agent count")
+        if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=state.device)
+        st = L.State(C.c_void_p(state.data_ptr()), state.stride(0))
+        pp = L.Params(_ptr(type_idx), None, None, 0, None)
+        L.check(self._lib.potato_detect_collisions(self._h, C.byref(st), C.byref(pp), n, _ptr(alive),
+                                                   _ptr(died), _ptr(workspace), nbytes,
+                                                   _stream_handle(stream)))
+        return alive
 
     def order_by_type(self, type_idx, stream=None):
         """Processing order grouping agents by type, longest step budget first."""

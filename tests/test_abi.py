@@ -102,3 +102,25 @@ def test_order_workspace_size(lib):
 def test_create_without_device_reports_hip_error(lib):
     st, h = _create(lib, [I.base_type()])
     assert st == L.EHIP and not h.value
+
+
+def test_collision_workspace_size(lib):
+    lib.potato_collision_workspace_bytes.restype = C.c_int64
+    lib.potato_collision_workspace_bytes.argtypes = [C.c_int64]
+    assert lib.potato_collision_workspace_bytes(0) == -1
+    n = 1000
+    m = 2048                                   # smallest power of two >= 2n (and >= 1024)
+    expect = (3 * m + 2 * n + m // 1024 + 1) * 4 + 256
+    assert lib.potato_collision_workspace_bytes(n) == expect
+
+
+def test_detect_rejects_null_context(lib):
+    st = L.State(None, 10)
+    assert lib.potato_detect_collisions(None, C.byref(st), None, 10, None, None, None, 0, None) == L.EINVAL
+
+
+def test_type_radius_is_validated(lib):
+    t = I.base_type()
+    t["radius"] = -1.0
+    st, h = _create(lib, [t])
+    assert st == L.EINVAL and not h.value

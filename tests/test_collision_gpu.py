@@ -1,0 +1,149 @@
+"""Collision detection on the GPU (hashed grid) against the brute-force
+reference, and dead agents excluded from the step and the adjoint.
+
+The collision decision is integer output, so parity is bit-exact: both sides
+take the FP32 decision with the same operation order.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_12698_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def dense_swarm(n, box, seed):
+    """Hovering swarm packed densely enough that many pairs overlap."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 1.0, size=(3, n)) * np.asarray(box, dtype=np.float64)[:, None]
+    return I.hover_state(pos)
+
+
+def gpu_detect(torch_dev, state, types, alive, type_idx=None):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sim = Simulator(types, I.globals_f32(), mode=1)
+    st = torch.from_numpy(state).to(dev)
+    a = torch.from_numpy(alive.copy()).to(dev)
+    died = torch.zeros(1, dtype=torch.int64, device=dev)
+    ti = None if type_idx is None else torch.from_numpy(type_idx).to(dev)
+    sim.detect_collisions(st, a, type_idx=ti, died=died)
+    torch.cuda.synchronize()
+    sim.close()
+    return a.cpu().numpy(), int(died.item())
+
+
+@pytest.mark.parametrize("n,box", [(1, (1, 1, 1)), (20000, (20, 20, 5)), (30001, (60, 60, 10))])
+def test_detection_matches_brute_force(oracle, torch_dev, n, box):
+    state = dense_swarm(n, box, seed=n)
+    t = I.base_type()
+    alive = (np.random.default_rng(1).random(n) > 0.05).astype(np.uint8)
+    got, died = gpu_detect(torch_dev, state, [t], alive)
+    ref, ref_died = oracle.detect_collisions(state, [t["radius"]], alive)
+    assert np.array_equal(got, ref) and died == ref_died
+    print(f"collisions n={n}: {ref_died} died", flush=True)
+
+
+def test_detection_with_type_radii(oracle, torch_dev):
+    n = 15000
+    state = dense_swarm(n, (25, 25, 5), seed=7)
+    types = I.hetero_types()
+    ti = np.random.default_rng(3).integers(0, 8, n).astype(np.uint8)
+    alive = np.ones(n, np.uint8)
+    got, died = gpu_detect(torch_dev, state, types, alive, ti)
+    radii = [t["radius"] for t in types]
+    ref, ref_died = oracle.detect_collisions(state, radii, alive, type_idx=ti)
+    assert np.array_equal(got, ref) and died == ref_died
+
+
+def test_detection_full_size_sampled(oracle, torch_dev):
+    """The 1,048,576-agent scale swarm: every agent's decision for a sample of
+    4,096 agents, each against all others, from the reference."""
+    sw = I.config2()
+    alive = np.ones(sw.n, np.uint8)
+    got, died = gpu_detect(torch_dev, sw.state, sw.types, alive)
+    q = np.random.default_rng(9).choice(sw.n, 4096, replace=False)
+    hit = oracle.collides(sw.state, [sw.types[0]["radius"]], alive, q)
+    assert np.array_equal(got[q] == 0, hit == 1)
+    assert died == int((got == 0).sum()) > 0
+
+
+def test_second_pass_is_a_fixed_point(torch_dev):
+    """After one pass no two alive agents overlap, so a second pass kills none."""
+    state = dense_swarm(20000, (20, 20, 5), seed=2)
+    t = I.base_type()
+    a1, d1 = gpu_detect(torch_dev, state, [t], np.ones(20000, np.uint8))
+    a2, d2 = gpu_detect(torch_dev, state, [t], a1)
+    assert d1 > 0 and d2 == 0 and np.array_equal(a1, a2)
+
+
+def test_dead_agents_are_not_advanced(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config1(n=3000)
+    alive = (np.arange(sw.n) % 4 != 0).astype(np.uint8)
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
+    st = torch.from_numpy(sw.state).to(dev)
+    wp = torch.from_numpy(sw.wp).to(dev)
+    sim.step(st, 300, sw.dt, wp=wp, alive=torch.from_numpy(alive).to(dev))
+    ref = torch.from_numpy(sw.state).to(dev)
+    sim.step(ref, 300, sw.dt, wp=wp)
+    torch.cuda.synchronize()
+    got, ref = st.cpu().numpy(), ref.cpu().numpy()
+    dead = alive == 0
+    assert np.array_equal(got[:, dead], sw.state[:, dead])
+    assert np.array_equal(got[:, ~dead], ref[:, ~dead])
+    sim.close()
+
+
+def test_dead_agents_pass_the_cotangent_through(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config4(n=512, n_steps=100)
+    alive = (np.arange(sw.n) % 3 != 0).astype(np.uint8)
+    at = torch.from_numpy(alive).to(dev)
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=50)
+    x = torch.from_numpy(sw.state).to(dev)
+    gains = torch.from_numpy(sw.gains).to(dev)
+    wp = torch.from_numpy(sw.wp).to(dev)
+    ckpt = torch.empty((2, 40, sw.n), device=dev)
+    sim.step(x, 100, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=50, alive=at)
+    lam = torch.randn(30, sw.n, device=dev)
+    gx0, gg = sim.step_backward(ckpt, 50, 100, sw.dt, lam, gains=gains, wp=wp, alive=at)
+    x2 = torch.from_numpy(sw.state).to(dev)
+    ck2 = torch.empty((2, 40, sw.n), device=dev)
+    sim.step(x2, 100, sw.dt, gains=gains, wp=wp, ckpt=ck2, ckpt_every=50)
+    gx2, gg2 = sim.step_backward(ck2, 50, 100, sw.dt, lam, gains=gains, wp=wp)
+    torch.cuda.synchronize()
+    dead = torch.from_numpy(alive == 0).to(dev)
+    assert torch.equal(gx0[:, dead], lam[:, dead]) and torch.all(gg[:, dead] == 0)
+    assert torch.equal(gx0[:, ~dead], gx2[:, ~dead]) and torch.equal(gg[:, ~dead], gg2[:, ~dead])
+    sim.close()
+
+
+def test_graph_replay_reads_the_current_mask(torch_dev):
+    """A cached graph reads the mask at run time: killing agents between two
+    replays freezes them from then on."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config1(n=2000)
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=50, use_graph=True)
+    st = torch.from_numpy(sw.state).to(dev)
+    wp = torch.from_numpy(sw.wp).to(dev)
+    alive = torch.ones(sw.n, dtype=torch.uint8, device=dev)
+    sim.step(st, 100, sw.dt, wp=wp, alive=alive)
+    alive[::2] = 0
+    before = st.clone()
+    sim.step(st, 100, sw.dt, wp=wp, alive=alive)
+    torch.cuda.synchronize()
+    assert torch.equal(st[:, ::2], before[:, ::2])
+    assert not torch.equal(st[:, 1::2], before[:, 1::2])
+    sim.close()
