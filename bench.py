@@ -10,9 +10,11 @@ timed rollouts, inputs resident in HBM.
 
 Also reported, on the same GPU: the plain one-step-per-launch kernel on the
 same swarm, the fused form without the graph, the heterogeneous 8-type batch
-in one launch per rollout, and (when the adjoint is built) forward+backward
-of the differentiable rollout.  cpu_baseline times the FP64 reference on a
-bounded sample of the same workload on the host cores.
+in one launch per rollout, collision detection over the swarm's positions,
+the rollout driven through the command/snapshot pipeline (host decisions
+outside the loop, positions streamed out), and forward+backward of the
+differentiable rollout.  cpu_baseline times the FP64 reference on a bounded
+sample of the same workload on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -72,7 +74,14 @@ def main():
     ap.add_argument("--agents", type=int, default=1 << 20)
     ap.add_argument("--sim-steps", type=int, default=10000)
     ap.add_argument("--no-extra", action="store_true", help="skip the other forms")
+    ap.add_argument("--forms", default="plain,fused_eager,hetero,collisions,pipeline,fwd_bwd",
+                    help="comma-separated subset of the other forms to run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time per round against the number of agents (the paper's protocol: "
+                         "500 warm-up rounds, 2,000 timed rounds, 3 executions), GPU plain and "
+                         "fused forms and the FP64 reference on 1 and all host threads; prints "
+                         "one JSON line per point and exits")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of known size (for scaling "
                          "HBM byte counters) and exit")
@@ -80,9 +89,13 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.sweep:
+        sweep()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the quadrotor step has no cross-agent coupling, "
-              "so a multi-GPU run is N independent copies of this one (see DESIGN.md).",
+              "so a multi-GPU run is N independent copies of this one, each on its share of "
+              "the agents.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -141,7 +154,8 @@ def main():
 
     forms = {"fused_graph": {"agent_steps_per_s": value, "rollout_ms": float(np.mean(ev_ms))}}
     if not args.no_extra:
-        forms.update(extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops))
+        forms.update(extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops,
+                                 set(args.forms.split(","))))
     sim.close()
 
     cpu = None if args.no_cpu else cpu_baseline(O, sw)
@@ -161,9 +175,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
-    from paper_2308_12698_amd import inputs as I
-    from paper_2308_12698_amd.sim import Simulator
+def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops, which):
     res = {}
     N = sw.n
 
@@ -179,6 +191,31 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
         return a.elapsed_time(b) / reps
 
     # plain: one launch per step, state round-trips HBM every step
+    if "plain" in which:
+        res.update(plain_form(timed, sw, state, wp, N))
+    # fused without the graph (host launches)
+    sim.set_options(form="fused", use_graph=False, block=sim.opts.block,
+                    steps_per_launch=sim.opts.steps_per_launch, grid_blocks=sim.opts.grid_blocks)
+    if "fused_eager" in which:
+        ms = timed(lambda: sim.step(state, 2000, sw.dt, wp=wp, resample_every=sw.resample_every))
+        res["fused_eager"] = {"agent_steps_per_s": N * 2000 / (ms * 1e-3), "steps_timed": 2000}
+        log(f"fused eager: {res['fused_eager']['agent_steps_per_s']:.4e} agent-steps/s")
+    if "hetero" in which:
+        res.update(hetero_form(torch, dev, timed))
+    if "collisions" in which:
+        res["collisions"] = collisions_form(torch, dev, timed, N)
+    if "pipeline" in which:
+        res["pipeline"] = pipeline_form(torch, dev, sim, sw, T)
+        log(f"pipeline: {res['pipeline']['agent_steps_per_s']:.4e} agent-steps/s, "
+            f"{res['pipeline']['overhead_vs_resident']:+.3f} vs resident")
+    if "fwd_bwd" in which:
+        res.update(fwd_bwd_form(torch, dev, timed, N))
+    return res
+
+
+def plain_form(timed, sw, state, wp, N):
+    from paper_2308_12698_amd.sim import Simulator
+    res = {}
     steps_plain = 1000
     plain = Simulator(sw.types, sw.glob, mode=1, form="plain", use_graph=True)
     ms = timed(lambda: plain.step(state, steps_plain, sw.dt, wp=wp, resample_every=sw.resample_every))
@@ -193,15 +230,15 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
                                  "bytes_per_agent_step": bytes_step,
                                  "traffic": measured_traffic("plain")}}
     log(f"plain: {res['plain']['agent_steps_per_s']:.4e} agent-steps/s, {gbs:.0f} GB/s")
+    return res
 
-    # fused without the graph (host launches)
-    sim.set_options(form="fused", use_graph=False, block=sim.opts.block,
-                    steps_per_launch=sim.opts.steps_per_launch, grid_blocks=sim.opts.grid_blocks)
-    ms = timed(lambda: sim.step(state, 2000, sw.dt, wp=wp, resample_every=sw.resample_every))
-    res["fused_eager"] = {"agent_steps_per_s": N * 2000 / (ms * 1e-3), "steps_timed": 2000}
-    log(f"fused eager: {res['fused_eager']['agent_steps_per_s']:.4e} agent-steps/s")
 
-    # heterogeneous: 8 types, budgets 1,000..8,000, one launch per rollout
+def hetero_form(torch, dev, timed):
+    """8 types, budgets 1,000..8,000, one launch per rollout, with and
+    without the type-grouped processing order."""
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
+    res = {}
     hw = I.config3()
     hsim = Simulator(hw.types, hw.glob, mode=1, form="fused", steps_per_launch=hw.n_steps)
     hs = torch.from_numpy(hw.state).to(dev)
@@ -216,8 +253,13 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
                       "n_agents": hw.n, "rollout_ms": ms}
         log(f"{label}: {res[label]['agent_steps_per_s']:.4e} agent-steps/s")
     hsim.close()
+    return res
 
-    # collision detection on the scale swarm's positions (all alive on entry)
+
+def collisions_form(torch, dev, timed, N):
+    """Collision detection on the scale swarm's positions (all alive on entry)."""
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
     cw = I.config2(n=N, n_steps=1)
     cstate = torch.from_numpy(cw.state).to(dev)
     csim = Simulator(cw.types, cw.glob, mode=1)
@@ -231,16 +273,21 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
         csim.detect_collisions(cstate, alive, workspace=ws, died=died)
 
     ms = timed(detect, reps=5)
-    res["collisions"] = {"agents_per_s": N / (ms * 1e-3), "n_agents": N, "ms": ms,
-                         "died_per_pass": int(died.item()) // 6}
+    out = {"agents_per_s": N / (ms * 1e-3), "n_agents": N, "ms": ms,
+           "died_per_pass": int(died.item()) // 6}
     log(f"collisions: {N / (ms * 1e-3):.4e} agents/s ({ms:.3f} ms per pass, "
-        f"{res['collisions']['died_per_pass']} collided)")
+        f"{out['died_per_pass']} collided)")
     csim.close()
-    del cstate, ws
+    return out
 
-    # forward (with checkpoints) + hand-written adjoint of the differentiable
-    # rollout: 500 steps at dt = 2 ms, checkpoints every 50 steps, at the
-    # workload's own 65,536 agents and at 1,048,576 agents
+
+def fwd_bwd_form(torch, dev, timed, N):
+    """Forward (with checkpoints) + hand-written adjoint of the differentiable
+    rollout: 500 steps at dt = 2 ms, checkpoints every 50 steps, at the
+    workload's own 65,536 agents and at N agents."""
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
+    res = {}
     for n_agents in (65536, N):
         dw = I.config4(n=n_agents)
         K = dw.extra["ckpt_every"]
@@ -278,6 +325,116 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops):
         dsim.close()
         del ckpt, x, x0
     return res
+
+
+def pipeline_form(torch, dev, sim, sw, T, snap_every=500):
+    """Decision loop outside the simulation: every 2,000-step epoch the host
+    computes the next waypoints from the positions streamed out one epoch
+    earlier and pushes them while the GPU keeps simulating; positions of all
+    agents are downloaded every `snap_every` steps.  Compared by wall clock
+    with the same steps launched eagerly with the waypoints resident."""
+    from paper_2308_12698_amd.sim import Pipe
+    N, es = sw.n, sw.resample_every
+    E = T // es
+    per = es // snap_every
+    x0 = torch.from_numpy(sw.state).to(dev)
+    state = x0.clone()
+    wp = torch.from_numpy(sw.wp).to(dev)
+    pipe = Pipe(sim, N)
+    snaps = torch.empty((E, per, 3, N), dtype=torch.float32, pin_memory=True)
+    offsets = (sw.wp - sw.state[None, 0:3]).astype(np.float32)      # [E, 3, N]
+
+    def pipelined():
+        state.copy_(x0)
+        base = pipe.n_snaps
+        pipe.push(sw.wp[0])
+        for e in range(E):
+            pipe.run(state, es, sw.dt, snap_every=snap_every, snaps=snaps[e])
+            if e + 1 == E:
+                break
+            if e == 0:
+                observed = sw.state[0:3]
+            else:
+                pipe.wait_snapshots(base + e * per)
+                observed = snaps[e - 1, per - 1].numpy()
+            pipe.push(observed + offsets[e + 1])
+        pipe.sync()
+        torch.cuda.synchronize()
+
+    def resident():
+        state.copy_(x0)
+        sim.step(state, E * es, sw.dt, wp=wp, resample_every=es)
+        torch.cuda.synchronize()
+
+    out = {}
+    for label, fn in (("pipelined", pipelined), ("resident", resident)):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            fn()
+        out[label] = (time.perf_counter() - t0) / 2
+    pipe.close()
+    steps = E * es
+    return {"agent_steps_per_s": N * steps / out["pipelined"], "sim_steps": steps, "epochs": E,
+            "snap_every": snap_every, "snapshots": E * per,
+            "snapshot_bytes": E * per * 3 * N * 4, "command_bytes": E * 3 * N * 4,
+            "wall_ms": out["pipelined"] * 1e3, "resident_wall_ms": out["resident"] * 1e3,
+            "overhead_vs_resident": out["pipelined"] / out["resident"] - 1.0}
+
+
+SWEEP_SIZES = (1000, 2048, 4096, 5000, 8192, 10000, 16384, 65536, 262144, 1048576)
+
+
+def sweep(sizes=SWEEP_SIZES, warm=500, rounds=2000, execs=3, cpu_budget_s=4.0):
+    """Closed-loop swarm of each size, hovering with one random waypoint.
+    One round = one time step of every agent.  GPU forms: plain (one launch
+    per round, replayed from a hipGraph) and fused (autotuned, hipGraph);
+    after the warm-up rounds one untimed call of `rounds` rounds captures the
+    graph that the timed executions replay (one waypoint epoch and no step
+    budget, so the step index does not change the work).
+    The reference runs the same swarm for as many rounds as fit in about
+    cpu_budget_s seconds (at least one)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    all_threads = max(1, min(16, os.cpu_count() or 1))
+    cpu_rate = {}
+    for n in sizes:
+        sw = I.config1(n=n)
+        wp = torch.from_numpy(sw.wp).to(dev)
+        for form in ("plain", "fused"):
+            state = torch.from_numpy(sw.state).to(dev)
+            sim = Simulator(sw.types, sw.glob, mode=1, form=form, use_graph=True)
+            if form == "fused":
+                tuned = sim.autotune(state, sw.dt, 200, wp=wp)
+                sim.set_options(form="fused", use_graph=True, **tuned)
+            sim.step(state, warm, sw.dt, wp=wp)
+            sim.step(state, rounds, sw.dt, wp=wp)     # captures the graph that is timed below
+            ms = []
+            for e in range(execs):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                sim.step(state, rounds, sw.dt, wp=wp)
+                b.record(stream)
+                torch.cuda.synchronize()
+                ms.append(a.elapsed_time(b) / rounds)
+            sim.close()
+            print(json.dumps({"sweep": "gpu", "form": form, "n_agents": n, "ms_per_round": float(np.mean(ms)),
+                              "sd_ms": float(np.std(ms)), "agent_steps_per_s": n / (np.mean(ms) * 1e-3),
+                              "warmup_rounds": warm, "rounds": rounds, "executions": execs}), flush=True)
+        for threads in (1, all_threads):
+            # rate from the previous size sets the number of rounds that fit the budget
+            guess = cpu_rate.get(threads, 2e6 * threads)
+            r = int(max(1, min(rounds, cpu_budget_s * guess / n)))
+            t0 = time.perf_counter()
+            O.rollout(sw.state, sw.types, sw.glob, 1, sw.dt, r, wp=sw.wp, threads=threads)
+            dt = time.perf_counter() - t0
+            cpu_rate[threads] = n * r / dt
+            print(json.dumps({"sweep": "oracle", "threads": threads, "n_agents": n, "rounds": r,
+                              "ms_per_round": dt / r * 1e3, "agent_steps_per_s": n * r / dt}), flush=True)
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):

@@ -167,7 +167,7 @@ potato_status potato_set_options(potato_ctx* ctx, const potato_options* opts);
  * Advance agents 0..n_agents-1 by n_steps time steps of length dt in place.
  * An agent of type t takes min(n_steps, max(0, step_budget_t - step0))
  * steps.  Errors (POTATO_EINVAL): ctx/state/params/cmds NULL, rows NULL,
- * n_agents < 1, ld < n_agents, n_steps < 0, dt not finite and > 0, missing
+ * n_agents outside [1, 2^30], ld < n_agents, n_steps < 0, dt not finite and > 0, missing
  * motor_cmd (open loop) or wp / n_epochs < 1 (closed loop), cmds->ld <
  * n_agents, gains_ld < n_agents when gains are given, ckpt set with
  * ckpt_every < 1.  n_steps == 0 is a no-op.
@@ -251,6 +251,57 @@ int64_t potato_collision_workspace_bytes(int64_t n_agents);
 potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                                        int64_t n_agents, uint8_t* alive, int64_t* died, void* workspace,
                                        int64_t workspace_bytes, void* stream);
+
+/*
+ * Command ingress and snapshot egress around a running rollout (Sec. III-A,
+ * Fig. 2: the decision side is kept out of the simulation loop, so the
+ * simulated world keeps running while new commands are produced, and the
+ * states are streamed out to a viewer).  A pipe owns two device command
+ * slots, two device position slots, a pinned host staging copy of each
+ * command slot and two copy streams (ingress and egress), all allocated by
+ * potato_pipe_create, so runs and pushes allocate nothing.
+ *
+ *   potato_pipe_push(pipe, host_cmd): host_cmd is host memory (any kind)
+ *     float[rows][n_agents], rows = 3 (closed loop: waypoint x, y, z) or
+ *     4 (open loop: rotor commands relative to w_ref).  It is copied into
+ *     the pinned staging slot before the call returns (the caller may
+ *     reuse it at once), then to the device slot on the ingress stream,
+ *     after the runs that read that slot's previous contents.  Blocks the
+ *     host only while the same staging slot's previous upload is still in
+ *     flight (two pushes ahead of the GPU).
+ *   potato_pipe_run(pipe, state, params, dt, n_steps, snap_every,
+ *     host_snap, stream): advances state (as potato_step with the
+ *     context's launch options, without graph capture) by n_steps with
+ *     the most recently pushed commands (held for the whole run; the
+ *     stream waits for their upload).  The
+ *     pipe keeps the global step index across runs (step budgets).  With
+ *     snap_every > 0, after every snap_every steps positions (rows 0-2)
+ *     are copied to a device slot and from there, on the egress stream, to
+ *     host_snap[k] (float[n_steps / snap_every][3][n_agents], host memory;
+ *     pinned for the copy to overlap the next steps).  Snapshot k of the
+ *     run holds the positions after step (k+1)*snap_every of the run.
+ *     Every run of a pipe must use the same stream.
+ *   potato_pipe_wait_snapshots(pipe, count): blocks until the first
+ *     `count` snapshots taken by the pipe since its creation (counted over
+ *     all runs) are in host memory.
+ *   potato_pipe_sync(pipe): blocks until all enqueued uploads and
+ *     snapshots are done.
+ *   potato_pipe_destroy(pipe): synchronises the pipe's streams and the run
+ *     stream, then frees the pipe.  NULL is a no-op.
+ * Errors: POTATO_EINVAL for null pointers, n_agents < 1, a run before the
+ * first push, n_steps < 0, snap_every < 0, missing host_snap when a
+ * snapshot is due, a run on another stream than the first run, or a
+ * context whose mode changed since the pipe was created; the errors of
+ * potato_step otherwise.  After a POTATO_EHIP the pipe must be destroyed.
+ */
+typedef struct potato_pipe potato_pipe;
+potato_status potato_pipe_create(potato_ctx* ctx, int64_t n_agents, potato_pipe** out);
+potato_status potato_pipe_push(potato_pipe* pipe, const float* host_cmd);
+potato_status potato_pipe_run(potato_pipe* pipe, const potato_state* state, const potato_params* params,
+                              float dt, int32_t n_steps, int32_t snap_every, float* host_snap, void* stream);
+potato_status potato_pipe_wait_snapshots(potato_pipe* pipe, int64_t count);
+potato_status potato_pipe_sync(potato_pipe* pipe);
+potato_status potato_pipe_destroy(potato_pipe* pipe);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* potato_last_error(void);

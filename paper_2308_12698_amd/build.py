@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpotato.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "collide.hip", "abi.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "collide.hip", "abi.hip", "pipeline.hip")]
 ARCH = os.environ.get("POTATO_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every HIP translation unit; the

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/potato.h"
+#include "internal.h"
 #include "kernels.h"
 
 using namespace potato;
@@ -180,7 +181,7 @@ potato_status validate_step(const potato_ctx* ctx, const potato_state* st, const
     if (!ctx || !st || !pp || !cm) return fail(POTATO_EINVAL, "ctx, state, params and cmds must be non-null");
     if (!st->rows) return fail(POTATO_EINVAL, "state.rows is null");
     if (n < 1) return fail(POTATO_EINVAL, "n_agents must be >= 1");
-    if (n > 0x7fffffffLL) return fail(POTATO_EINVAL, "n_agents must fit in int32");
+    if (n > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be <= 2^30");
     if (st->ld < n) return fail(POTATO_EINVAL, "state.ld (%lld) < n_agents (%lld)", (long long)st->ld, (long long)n);
     if (n_steps < 0) return fail(POTATO_EINVAL, "n_steps must be >= 0");
     if (!std::isfinite(dt) || !(dt > 0.0f)) return fail(POTATO_EINVAL, "dt must be finite and > 0");
@@ -260,6 +261,38 @@ std::vector<int64_t> graph_key(const Plan& P, int32_t n_steps, float dt) {
 }
 
 }  // namespace
+
+namespace potato {
+
+potato_status set_error(potato_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+potato_status set_hip_error(hipError_t e, const char* where) { return hip_fail(e, where); }
+
+int ctx_mode(const potato_ctx* ctx) { return ctx->opts.mode; }
+
+int ctx_device(const potato_ctx* ctx) { return ctx->device; }
+
+potato_status step_eager(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                         const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
+                         hipStream_t stream) {
+    potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, n_steps, nullptr, 0);
+    if (s != POTATO_OK) return s;
+    if (n_steps == 0) return POTATO_OK;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    Plan P = make_plan(ctx, state, params, cmds, dt, n_agents, nullptr, 0);
+    hipError_t e = enqueue(P, n_steps, stream);
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato step launch");
+}
+
+}  // namespace potato
 
 extern "C" {
 
@@ -480,7 +513,7 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
         return fail(POTATO_EUNSUPPORTED, "the adjoint is implemented for closed-loop rollouts");
     if (!ckpt || !grad_final || !grad_x0 || !workspace)
         return fail(POTATO_EINVAL, "ckpt, grad_final, grad_x0 and workspace must be non-null");
-    if (n_agents < 1 || n_agents > 0x7fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^31)");
+    if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");
     if (ld < n_agents) return fail(POTATO_EINVAL, "ld < n_agents");
     if (n_steps < 0) return fail(POTATO_EINVAL, "n_steps must be >= 0");
     if (ckpt_every < 1) return fail(POTATO_EINVAL, "ckpt_every must be >= 1");
@@ -523,7 +556,7 @@ int64_t potato_order_workspace_bytes(int64_t n_agents, int32_t n_types) {
 potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t n_agents, int32_t* perm,
                                    void* workspace, int64_t workspace_bytes, void* stream) {
     if (!ctx || !type || !perm || !workspace) return fail(POTATO_EINVAL, "ctx, type, perm and workspace must be non-null");
-    if (n_agents < 1 || n_agents > 0x7fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^31)");
+    if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");
     const int64_t need = potato_order_workspace_bytes(n_agents, ctx->n_types);
     if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
     const int64_t nb = (n_agents + kOrderBlock - 1) / kOrderBlock;

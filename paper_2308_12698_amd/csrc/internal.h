@@ -1,0 +1,28 @@
+/*
+ * internal.h -- host-side helpers shared by the translation units of the C
+ * ABI (abi.hip, pipeline.hip).  Not installed; not part of the ABI.
+ */
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/potato.h"
+
+namespace potato {
+
+/* Record `fmt` as the calling thread's last error and return `st`. */
+potato_status set_error(potato_status st, const char* fmt, ...);
+potato_status set_hip_error(hipError_t e, const char* where);
+
+/* Mode (open / closed loop) the context was created or last set with. */
+int ctx_mode(const potato_ctx* ctx);
+int ctx_device(const potato_ctx* ctx);
+
+/* potato_step without hipGraph capture: validates, plans with the tuned
+ * launch shape and enqueues the launches on `stream`. */
+potato_status step_eager(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                         const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
+                         hipStream_t stream);
+
+}  // namespace potato

@@ -13,6 +13,10 @@ namespace potato {
 
 constexpr int kRows = 40;   /* state rows per agent, see include/potato.h */
 
+/* Largest agent count: agent index times 4 (a byte offset into a row) must
+ * fit 32 bits, which the kernels' row addressing relies on. */
+constexpr int64_t kMaxAgents = int64_t(1) << 30;
+
 /* Everything one rollout launch needs, passed by value as the kernel
  * argument (uniform, lands in scalar registers). */
 struct StepArgs {

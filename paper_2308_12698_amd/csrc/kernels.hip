@@ -31,7 +31,7 @@ namespace {
 #define POTATO_LIMITS_FROM_LDS 0
 #endif
 #ifndef POTATO_ROLLOUT_WAVES
-#define POTATO_ROLLOUT_WAVES 3
+#define POTATO_ROLLOUT_WAVES 4
 #endif
 #if POTATO_ROLLOUT_WAVES > 0
 #define POTATO_ROLLOUT_ATTR __attribute__((amdgpu_waves_per_eu(POTATO_ROLLOUT_WAVES, POTATO_ROLLOUT_WAVES)))
@@ -68,33 +68,38 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
     const int64_t ld = A.ld;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.n; j += stride) {
-        const int64_t i = PERM ? (int64_t)A.perm[j] : j;
-        const TypeConst& c = HET ? tab[A.type[i]] : tab[0];
-        if (A.alive && !A.alive[i]) continue;
+        /* agent index < 2^30, so byte offsets into rows fit 32 bits.  Row
+         * addresses are uniform: every active lane starts at step 0 and
+         * steps together, so the epoch and checkpoint slot agree too. */
+        const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
+        const uint32_t bo = i << 2;
+        const TypeConst& c = HET ? tab[elem(A.type, i)] : tab[0];
+        if (A.alive && !elem(A.alive, i)) continue;
 
         int64_t left = (int64_t)c.budget - A.step0;
         left = left < 0 ? 0 : left;
         const int steps = left < A.n_steps ? (int)left : A.n_steps;
         if (steps == 0) continue;
 
-        float* r = A.rows + i;
+        float* const R = A.rows;
+        auto row = [&](int k) -> float& { return elem(uniform(R + k * ld), bo); };
         Agent a;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { a.p[k] = r[k * ld]; a.v[k] = r[(3 + k) * ld]; a.w[k] = r[(10 + k) * ld]; }
+        for (int k = 0; k < 3; ++k) { a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k); }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { a.q[k] = r[(6 + k) * ld]; a.d[k] = r[(13 + k) * ld]; }
+        for (int k = 0; k < 4; ++k) { a.q[k] = row(6 + k); a.d[k] = row(13 + k); }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { a.p_lo[k] = r[(30 + k) * ld]; a.v_lo[k] = r[(33 + k) * ld]; }
+        for (int k = 0; k < 3; ++k) { a.p_lo[k] = row(30 + k); a.v_lo[k] = row(33 + k); }
         if (MODE == 1) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                a.ip[k] = r[(17 + k) * ld]; a.ia[k] = r[(20 + k) * ld];
-                a.ir[k] = r[(23 + k) * ld]; a.wprev[k] = r[(26 + k) * ld];
+                a.ip[k] = row(17 + k); a.ia[k] = row(20 + k);
+                a.ir[k] = row(23 + k); a.wprev[k] = row(26 + k);
             }
-            a.J = r[29 * ld];
-            a.J_lo = r[36 * ld];
+            a.J = row(29);
+            a.J_lo = row(36);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) a.ip_lo[k] = r[(37 + k) * ld];
+            for (int k = 0; k < 3; ++k) a.ip_lo[k] = row(37 + k);
         } else {
 #pragma unroll
             for (int k = 0; k < 3; ++k) { a.ip[k] = a.ia[k] = a.ir[k] = a.wprev[k] = a.ip_lo[k] = 0.0f; }
@@ -103,10 +108,10 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 
         Gains g;
         if (GAINS) {
-            const float* gp = A.gains + i;
+            const float* G = A.gains;
             const int64_t gl = A.gains_ld;
-            g = Gains{gp[0], gp[gl], gp[2 * gl], gp[3 * gl], gp[4 * gl],
-                      gp[5 * gl], gp[6 * gl], gp[7 * gl], gp[8 * gl]};
+            auto gain = [&](int k) { return elem(uniform(G + k * gl), bo); };
+            g = Gains{gain(0), gain(1), gain(2), gain(3), gain(4), gain(5), gain(6), gain(7), gain(8)};
         } else {
             g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
                       c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
@@ -118,7 +123,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         int epoch = 0;
         if (MODE == 0) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dc[k] = A.motor_cmd[k * A.cmd_ld + i];
+            for (int k = 0; k < 4; ++k) dc[k] = elem(uniform(A.motor_cmd + k * A.cmd_ld), bo);
         } else {
             if (A.resample > 0) {
                 const int64_t e0 = A.step0 / A.resample;
@@ -126,7 +131,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
                 next_epoch_step = e0 < A.n_epochs - 1 ? (e0 + 1) * A.resample : INT64_MAX;
             }
 #pragma unroll
-            for (int k = 0; k < 3; ++k) wp[k] = A.wp[((int64_t)epoch * 3 + k) * A.cmd_ld + i];
+            for (int k = 0; k < 3; ++k) wp[k] = elem(uniform(A.wp + ((int64_t)epoch * 3 + k) * A.cmd_ld), bo);
         }
         int ck_next = 0, ck_slot = 0;
         if (CKPT) {
@@ -136,19 +141,20 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 
         for (int s = 0; s < steps; ++s) {
             if (CKPT && s == ck_next) {
-                float* o = A.ckpt + (int64_t)ck_slot * kRows * ld + i;
+                float* const O = A.ckpt + (int64_t)ck_slot * kRows * ld;
+                auto out = [&](int k) -> float& { return elem(uniform(O + k * ld), bo); };
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    o[k * ld] = a.p[k]; o[(3 + k) * ld] = a.v[k]; o[(10 + k) * ld] = a.w[k];
-                    o[(17 + k) * ld] = a.ip[k]; o[(20 + k) * ld] = a.ia[k];
-                    o[(23 + k) * ld] = a.ir[k]; o[(26 + k) * ld] = a.wprev[k];
-                    o[(30 + k) * ld] = a.p_lo[k]; o[(33 + k) * ld] = a.v_lo[k];
-                    o[(37 + k) * ld] = a.ip_lo[k];
+                    out(k) = a.p[k]; out(3 + k) = a.v[k]; out(10 + k) = a.w[k];
+                    out(17 + k) = a.ip[k]; out(20 + k) = a.ia[k];
+                    out(23 + k) = a.ir[k]; out(26 + k) = a.wprev[k];
+                    out(30 + k) = a.p_lo[k]; out(33 + k) = a.v_lo[k];
+                    out(37 + k) = a.ip_lo[k];
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) { o[(6 + k) * ld] = a.q[k]; o[(13 + k) * ld] = a.d[k]; }
-                o[29 * ld] = a.J;
-                o[36 * ld] = a.J_lo;
+                for (int k = 0; k < 4; ++k) { out(6 + k) = a.q[k]; out(13 + k) = a.d[k]; }
+                out(29) = a.J;
+                out(36) = a.J_lo;
                 ++ck_slot;
                 ck_next += A.ckpt_every;
             }
@@ -156,7 +162,8 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
                 if (A.step0 + s == next_epoch_step) {
                     ++epoch;
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) wp[k] = A.wp[((int64_t)epoch * 3 + k) * A.cmd_ld + i];
+                    for (int k = 0; k < 3; ++k)
+                        wp[k] = elem(uniform(A.wp + ((int64_t)epoch * 3 + k) * A.cmd_ld), bo);
                     next_epoch_step = epoch < A.n_epochs - 1 ? next_epoch_step + A.resample : INT64_MAX;
                 }
                 controller(c, lim, g, a, wp, dc);
@@ -165,21 +172,21 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         }
 
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { r[k * ld] = a.p[k]; r[(3 + k) * ld] = a.v[k]; r[(10 + k) * ld] = a.w[k]; }
+        for (int k = 0; k < 3; ++k) { row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k]; }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { r[(6 + k) * ld] = a.q[k]; r[(13 + k) * ld] = a.d[k]; }
+        for (int k = 0; k < 4; ++k) { row(6 + k) = a.q[k]; row(13 + k) = a.d[k]; }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { r[(30 + k) * ld] = a.p_lo[k]; r[(33 + k) * ld] = a.v_lo[k]; }
+        for (int k = 0; k < 3; ++k) { row(30 + k) = a.p_lo[k]; row(33 + k) = a.v_lo[k]; }
         if (MODE == 1) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                r[(17 + k) * ld] = a.ip[k]; r[(20 + k) * ld] = a.ia[k];
-                r[(23 + k) * ld] = a.ir[k]; r[(26 + k) * ld] = a.wprev[k];
+                row(17 + k) = a.ip[k]; row(20 + k) = a.ia[k];
+                row(23 + k) = a.ir[k]; row(26 + k) = a.wprev[k];
             }
-            r[29 * ld] = a.J;
-            r[36 * ld] = a.J_lo;
+            row(29) = a.J;
+            row(36) = a.J_lo;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) r[(37 + k) * ld] = a.ip_lo[k];
+            for (int k = 0; k < 3; ++k) row(37 + k) = a.ip_lo[k];
         }
     }
 }
@@ -206,34 +213,35 @@ __global__ void __launch_bounds__(kAdjBlock)
     const int64_t ld = A.ld;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    float* tape_col = A.tape + tid;
+    const uint32_t tbo = (uint32_t)tid << 2;      /* this thread's tape column */
     for (int64_t j = tid; j < A.n; j += stride) {
-        const int64_t i = PERM ? (int64_t)A.perm[j] : j;
-        const TypeConst& c = HET ? tab[A.type[i]] : tab[0];
+        const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
+        const uint32_t bo = i << 2;
+        const TypeConst& c = HET ? tab[elem(A.type, i)] : tab[0];
         int64_t left = (int64_t)c.budget - A.step0;
         left = left < 0 ? 0 : left;
         int steps = left < A.n_steps ? (int)left : A.n_steps;
-        if (A.alive && !A.alive[i]) steps = 0;      /* dead: identity map */
+        if (A.alive && !elem(A.alive, i)) steps = 0;      /* dead: identity map */
         Gains g;
         if (GAINS) {
-            const float* gp = A.gains + i;
+            const float* G = A.gains;
             const int64_t gl = A.gains_ld;
-            g = Gains{gp[0], gp[gl], gp[2 * gl], gp[3 * gl], gp[4 * gl],
-                      gp[5 * gl], gp[6 * gl], gp[7 * gl], gp[8 * gl]};
+            auto gain = [&](int k) { return elem(G + k * gl, bo); };
+            g = Gains{gain(0), gain(1), gain(2), gain(3), gain(4), gain(5), gain(6), gain(7), gain(8)};
         } else {
             g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
                       c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
         }
         AgentAdj lam;
-        load_adj(A.grad_final + i, ld, lam);
+        load_adj<false>(A.grad_final, ld, bo, lam);
         float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (steps > 0)
-            agent_backward(c, lim, g, A.ckpt + i, ld, A.K, steps, A.step0, A.wp + i, A.cmd_ld,
-                           A.n_epochs, A.resample, tape_col, A.tape_ld, lam, gk);
-        store_adj(A.grad_x0 + i, ld, lam);
+            agent_backward<!HET>(c, lim, g, A.ckpt, ld, bo, A.K, steps, A.step0, A.wp, A.cmd_ld, A.n_epochs,
+                                 A.resample, A.tape, A.tape_ld, tbo, lam, gk);
+        store_adj<false>(A.grad_x0, ld, bo, lam);
         if (A.grad_gains) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) A.grad_gains[k * ld + i] = gk[k];
+            for (int k = 0; k < 9; ++k) elem(A.grad_gains + k * ld, bo) = gk[k];
         }
     }
 }

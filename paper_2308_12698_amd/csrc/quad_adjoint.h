@@ -18,6 +18,10 @@
 
 #include "quad_step.h"
 
+#ifndef POTATO_ADJOINT_PREFETCH
+#define POTATO_ADJOINT_PREFETCH 1
+#endif
+
 namespace potato {
 
 /* Cotangents of the 30 physical state rows. */
@@ -382,86 +386,97 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
     for (int i = 0; i < 3; ++i) lam.p[i] -= l_e[i];
 }
 
-/* Waypoint of global step `k` (epoch min(k / resample, n_epochs - 1)). */
-__device__ __forceinline__ void waypoint_at(const float* wp_col, int64_t cmd_ld, int n_epochs, int resample,
-                                            int64_t k, float wp[3]) {
-    int64_t ep = resample > 0 ? k / resample : 0;
-    ep = ep < n_epochs - 1 ? ep : n_epochs - 1;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) wp[i] = wp_col[(ep * 3 + i) * cmd_ld];
+/* Row accessors: `base` is row 0 of a [rows][ld] buffer and `bo` the lane's
+ * byte offset (column index times 4).  U: `base` is the same in every
+ * active lane, so row addresses can stay in scalar registers. */
+template <bool U, typename T>
+__device__ __forceinline__ T* row_ptr(T* base, int64_t ld, int k) {
+    return U ? uniform(base + k * ld) : base + k * ld;
 }
 
-__device__ __forceinline__ void load_rows(const float* r, int64_t ld, Agent& a, bool carries) {
+template <bool U>
+__device__ __forceinline__ void load_rows(const float* base, int64_t ld, uint32_t bo, Agent& a, bool carries) {
+    auto row = [&](int k) { return elem(row_ptr<U>(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        a.p[k] = r[k * ld]; a.v[k] = r[(3 + k) * ld]; a.w[k] = r[(10 + k) * ld];
-        a.ip[k] = r[(17 + k) * ld]; a.ia[k] = r[(20 + k) * ld];
-        a.ir[k] = r[(23 + k) * ld]; a.wprev[k] = r[(26 + k) * ld];
-        a.p_lo[k] = carries ? r[(30 + k) * ld] : 0.0f;
-        a.v_lo[k] = carries ? r[(33 + k) * ld] : 0.0f;
-        a.ip_lo[k] = carries ? r[(37 + k) * ld] : 0.0f;
+        a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k);
+        a.ip[k] = row(17 + k); a.ia[k] = row(20 + k);
+        a.ir[k] = row(23 + k); a.wprev[k] = row(26 + k);
+        a.p_lo[k] = carries ? row(30 + k) : 0.0f;
+        a.v_lo[k] = carries ? row(33 + k) : 0.0f;
+        a.ip_lo[k] = carries ? row(37 + k) : 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { a.q[k] = r[(6 + k) * ld]; a.d[k] = r[(13 + k) * ld]; }
-    a.J = r[29 * ld];
-    a.J_lo = carries ? r[36 * ld] : 0.0f;
+    for (int k = 0; k < 4; ++k) { a.q[k] = row(6 + k); a.d[k] = row(13 + k); }
+    a.J = row(29);
+    a.J_lo = carries ? row(36) : 0.0f;
 }
 
 /* The 30 physical rows (the tape does not need the carries). */
-__device__ __forceinline__ void store_phys_rows(float* r, int64_t ld, const Agent& a) {
+template <bool U>
+__device__ __forceinline__ void store_phys_rows(float* base, int64_t ld, uint32_t bo, const Agent& a) {
+    auto row = [&](int k) -> float& { return elem(row_ptr<U>(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        r[k * ld] = a.p[k]; r[(3 + k) * ld] = a.v[k]; r[(10 + k) * ld] = a.w[k];
-        r[(17 + k) * ld] = a.ip[k]; r[(20 + k) * ld] = a.ia[k];
-        r[(23 + k) * ld] = a.ir[k]; r[(26 + k) * ld] = a.wprev[k];
+        row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k];
+        row(17 + k) = a.ip[k]; row(20 + k) = a.ia[k];
+        row(23 + k) = a.ir[k]; row(26 + k) = a.wprev[k];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { r[(6 + k) * ld] = a.q[k]; r[(13 + k) * ld] = a.d[k]; }
-    r[29 * ld] = a.J;
+    for (int k = 0; k < 4; ++k) { row(6 + k) = a.q[k]; row(13 + k) = a.d[k]; }
+    row(29) = a.J;
 }
 
-__device__ __forceinline__ void load_adj(const float* r, int64_t ld, AgentAdj& l) {
+template <bool U>
+__device__ __forceinline__ void load_adj(const float* base, int64_t ld, uint32_t bo, AgentAdj& l) {
+    auto row = [&](int k) { return elem(row_ptr<U>(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        l.p[k] = r[k * ld]; l.v[k] = r[(3 + k) * ld]; l.w[k] = r[(10 + k) * ld];
-        l.ip[k] = r[(17 + k) * ld]; l.ia[k] = r[(20 + k) * ld];
-        l.ir[k] = r[(23 + k) * ld]; l.wprev[k] = r[(26 + k) * ld];
+        l.p[k] = row(k); l.v[k] = row(3 + k); l.w[k] = row(10 + k);
+        l.ip[k] = row(17 + k); l.ia[k] = row(20 + k);
+        l.ir[k] = row(23 + k); l.wprev[k] = row(26 + k);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { l.q[k] = r[(6 + k) * ld]; l.d[k] = r[(13 + k) * ld]; }
-    l.J = r[29 * ld];
+    for (int k = 0; k < 4; ++k) { l.q[k] = row(6 + k); l.d[k] = row(13 + k); }
+    l.J = row(29);
 }
 
-__device__ __forceinline__ void store_adj(float* r, int64_t ld, const AgentAdj& l) {
+template <bool U>
+__device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, const AgentAdj& l) {
+    auto row = [&](int k) -> float& { return elem(row_ptr<U>(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        r[k * ld] = l.p[k]; r[(3 + k) * ld] = l.v[k]; r[(10 + k) * ld] = l.w[k];
-        r[(17 + k) * ld] = l.ip[k]; r[(20 + k) * ld] = l.ia[k];
-        r[(23 + k) * ld] = l.ir[k]; r[(26 + k) * ld] = l.wprev[k];
+        row(k) = l.p[k]; row(3 + k) = l.v[k]; row(10 + k) = l.w[k];
+        row(17 + k) = l.ip[k]; row(20 + k) = l.ia[k];
+        row(23 + k) = l.ir[k]; row(26 + k) = l.wprev[k];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { r[(6 + k) * ld] = l.q[k]; r[(13 + k) * ld] = l.d[k]; }
-    r[29 * ld] = l.J;
+    for (int k = 0; k < 4; ++k) { row(6 + k) = l.q[k]; row(13 + k) = l.d[k]; }
+    row(29) = l.J;
 }
 
 /*
  * Reverse sweep of one agent's closed-loop rollout of `steps` steps from
- * global step step0.  Checkpoint slot s (40 rows, column ckpt_col, stride
- * ld) holds the state before call-relative step s*K.  Each segment is
- * recomputed forward from its checkpoint with the step-start states written
- * to this agent's tape column (K slots of 30 rows, stride tape_ld), then
- * reversed step by step.  lam: cotangent of the final state on entry, of
+ * global step step0.  Checkpoint slot s (40 rows of stride ld, this agent's
+ * column at byte offset bo) holds the state before call-relative step s*K.
+ * Each segment is recomputed forward from its checkpoint with the
+ * step-start states written to this thread's tape column (K slots of 30
+ * rows of stride tape_ld, byte offset tbo), then reversed step by step.
+ * U: every active lane runs the same number of steps (one type), so the
+ * checkpoint, tape and waypoint rows of an iteration are the same for all
+ * of them.  lam: cotangent of the final state on entry, of
  * the initial state on return; gk accumulates the gain cotangents.
  */
+template <bool U>
 __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits& L, const Gains& g,
-                                               const float* ckpt_col, int64_t ld, int K, int steps,
-                                               int64_t step0, const float* wp_col, int64_t cmd_ld,
-                                               int n_epochs, int resample, float* tape_col,
-                                               int64_t tape_ld, AgentAdj& lam, float gk[9]) {
+                                               const float* ckpt, int64_t ld, uint32_t bo, int K,
+                                               int steps, int64_t step0, const float* wp, int64_t cmd_ld,
+                                               int n_epochs, int resample, float* tape, int64_t tape_ld,
+                                               uint32_t tbo, AgentAdj& lam, float gk[9]) {
     const int n_seg = (steps + K - 1) / K;
     /* the waypoint is reloaded only when the epoch changes */
     int64_t cur_ep = -1;
-    float wp[3] = {0.0f, 0.0f, 0.0f};
+    float wpv[3] = {0.0f, 0.0f, 0.0f};
     auto epoch_of = [&](int64_t k) {
         int64_t ep = resample > 0 ? k / resample : 0;
         return ep < n_epochs - 1 ? ep : (int64_t)n_epochs - 1;
@@ -469,7 +484,7 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
     auto use_epoch = [&](int64_t ep) {
         if (ep != cur_ep) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) wp[i] = wp_col[(ep * 3 + i) * cmd_ld];
+            for (int i = 0; i < 3; ++i) wpv[i] = elem(row_ptr<U>(wp, cmd_ld, (int)ep * 3 + i), bo);
             cur_ep = ep;
         }
     };
@@ -477,25 +492,36 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         const int k_begin = seg * K;
         const int len = steps - k_begin < K ? steps - k_begin : K;
         Agent a;
-        load_rows(ckpt_col + (int64_t)seg * 40 * ld, ld, a, true);
+        load_rows<U>(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
         for (int s = 0; s < len; ++s) {
-            store_phys_rows(tape_col + (int64_t)s * 30 * tape_ld, tape_ld, a);
+            store_phys_rows<U>(tape + (int64_t)s * 30 * tape_ld, tape_ld, tbo, a);
             float dc[4];
             use_epoch(epoch_of(step0 + k_begin + s));
-            controller(c, L, g, a, wp, dc);
+            controller(c, L, g, a, wpv, dc);
             rk4_step(c, L, a, dc);
         }
+#if POTATO_ADJOINT_PREFETCH
         /* reverse sweep; the tape slot of the next (earlier) step is loaded
-         * while the current step is differentiated */
+         * while the current step is differentiated (30 more live registers) */
         Agent x;
-        load_rows(tape_col + (int64_t)(len - 1) * 30 * tape_ld, tape_ld, x, false);
+        load_rows<U>(tape + (int64_t)(len - 1) * 30 * tape_ld, tape_ld, tbo, x, false);
         for (int s = len - 1; s >= 0; --s) {
             Agent nx;
-            if (s > 0) load_rows(tape_col + (int64_t)(s - 1) * 30 * tape_ld, tape_ld, nx, false);
+            if (s > 0) load_rows<U>(tape + (int64_t)(s - 1) * 30 * tape_ld, tape_ld, tbo, nx, false);
             use_epoch(epoch_of(step0 + k_begin + s));
-            step_vjp(c, L, g, x, wp, lam, gk);
+            step_vjp(c, L, g, x, wpv, lam, gk);
             if (s > 0) x = nx;
         }
+#else
+        /* reverse sweep; each step loads its tape slot, and the other
+         * resident waves cover the load latency */
+        for (int s = len - 1; s >= 0; --s) {
+            Agent x;
+            load_rows<U>(tape + (int64_t)s * 30 * tape_ld, tape_ld, tbo, x, false);
+            use_epoch(epoch_of(step0 + k_begin + s));
+            step_vjp(c, L, g, x, wpv, lam, gk);
+        }
+#endif
     }
 }
 

@@ -35,6 +35,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace potato {
 
 /* Per-type constants, derived once on the host from potato_type_params and
@@ -73,6 +75,34 @@ struct Agent {
     float ip[3], ia[3], ir[3], wprev[3];
     float p_lo[3], v_lo[3], J_lo, ip_lo[3];
 };
+
+/* Element of a structure-of-arrays row.  `row` is the same address in every
+ * lane of the wave (it stays in scalar registers) and `boff` is the lane's
+ * byte offset into the row (agent index times the element size), below
+ * 2^32.  Each access is then a single global load or store with a scalar
+ * base and a 32-bit vector offset, and no 64-bit address per row occupies
+ * vector registers. */
+template <typename T>
+__device__ __forceinline__ T& elem(T* row, uint32_t boff) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return *reinterpret_cast<T*>(reinterpret_cast<B*>(row) + boff);
+}
+
+/* `p`, a pointer that is the same in every active lane, marked as such: the
+ * compiler then keeps it in scalar registers and addresses with it as the
+ * scalar base, instead of folding a lane's offset into a 64-bit vector
+ * address per row (which costs two vector registers per row).  Only for
+ * values that are truly uniform over the active lanes. */
+template <typename T>
+__device__ __forceinline__ T* uniform(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    /* the rebuilt address is device (global) memory: passing it through the
+     * global address space keeps the accesses global rather than flat */
+    typedef __attribute__((address_space(1))) char gchar;
+    return (T*)(gchar*)(((uint64_t)hi << 32) | lo);
+}
 
 #define POTATO_FMA(a, b, c) __builtin_fmaf((a), (b), (c))
 

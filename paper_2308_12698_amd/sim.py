@@ -224,3 +224,65 @@ class Simulator:
         L.check(self._lib.potato_order_by_type(self._h, _ptr(type_idx), n, _ptr(perm), _ptr(ws),
                                                nbytes, _stream_handle(stream)))
         return perm
+
+
+class Pipe:
+    """Command ingress and position snapshots around running rollouts.
+
+    ``push(cmd)`` uploads the next commands (numpy float32 [3, n] waypoints
+    in closed loop, [4, n] rotor commands relative to w_ref in open loop)
+    on the pipe's own stream while earlier runs execute; ``run(...)``
+    advances the state with the last pushed commands and streams positions
+    every ``snap_every`` steps to ``snaps`` (a pinned host float32 tensor
+    [n_steps // snap_every, 3, n]) on another stream.  Everything the pipe
+    needs is allocated here, once.
+    """
+
+    def __init__(self, sim: Simulator, n_agents: int):
+        self._lib = sim._lib
+        self.sim = sim
+        self.n = int(n_agents)
+        self.rows = 3 if sim.mode == L.CLOSED_LOOP else 4
+        self.n_snaps = 0
+        h = C.c_void_p()
+        L.check(self._lib.potato_pipe_create(sim._h, self.n, C.byref(h)))
+        self._h = h
+
+    def push(self, cmd):
+        import numpy as np
+        a = np.ascontiguousarray(cmd, dtype=np.float32)
+        if a.shape != (self.rows, self.n):
+            raise ValueError(f"commands must be [{self.rows}, {self.n}], got {a.shape}")
+        L.check(self._lib.potato_pipe_push(self._h, a.ctypes.data_as(C.c_void_p)))
+
+    def run(self, state, n_steps, dt, *, snap_every=0, snaps=None, type_idx=None, perm=None,
+            gains=None, alive=None, stream=None):
+        _check_rows("state", state, N_ROWS, self.n)
+        due = int(n_steps) // int(snap_every) if snap_every > 0 else 0
+        if due:
+            if snaps is None or snaps.is_cuda or snaps.dtype != torch.float32 \
+                    or not snaps.is_contiguous() or snaps.numel() < due * 3 * self.n:
+                raise ValueError(f"snaps must be a contiguous host float32 tensor of >= {due} x 3 x {self.n}")
+        st, pp, _ = self.sim._structs(state, self.n, type_idx, perm, gains, None, None, 0, 0, alive)
+        L.check(self._lib.potato_pipe_run(self._h, C.byref(st), C.byref(pp), float(dt), int(n_steps),
+                                          int(snap_every), _ptr(snaps) if due else None,
+                                          _stream_handle(stream)))
+        self.n_snaps += due
+        return state
+
+    def wait_snapshots(self, count):
+        L.check(self._lib.potato_pipe_wait_snapshots(self._h, int(count)))
+
+    def sync(self):
+        L.check(self._lib.potato_pipe_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.potato_pipe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

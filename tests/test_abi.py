@@ -124,3 +124,14 @@ def test_type_radius_is_validated(lib):
     t["radius"] = -1.0
     st, h = _create(lib, [t])
     assert st == L.EINVAL and not h.value
+
+
+def test_pipe_entry_points_reject_null_handles(lib):
+    h = C.c_void_p()
+    assert lib.potato_pipe_create(None, 10, C.byref(h)) == L.EINVAL
+    assert lib.potato_pipe_create(None, 10, None) == L.EINVAL
+    assert lib.potato_pipe_push(None, None) == L.EINVAL
+    assert lib.potato_pipe_run(None, None, None, C.c_float(1e-3), 1, 0, None, None) == L.EINVAL
+    assert lib.potato_pipe_wait_snapshots(None, 0) == L.EINVAL
+    assert lib.potato_pipe_sync(None) == L.EINVAL
+    assert lib.potato_pipe_destroy(None) == L.OK

@@ -1,0 +1,188 @@
+"""Command ingress and position snapshots around running rollouts: the
+decision and viewer directions that the paper keeps outside the simulation
+loop (Sec. III-A, Fig. 2).
+
+A host decision loop sees the positions streamed out of the GPU one epoch
+late and pushes the next waypoints while the GPU keeps simulating.  The
+pushed command sequence is then replayed as one resident rollout: the final
+state and every snapshot must be bitwise equal (same kernels, same
+arithmetic; only the data movement differs), and the final state must match
+the FP64 reference within the 1e-4 parity bound.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2308_12698_amd import inputs as I
+from tests._util import OPEN_LOOP_GROUPS, rel_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def padded(state, ld):
+    buf = np.full((state.shape[0], ld), 7.0, dtype=np.float32)
+    buf[:, :state.shape[1]] = state
+    return buf
+
+
+def decide(observed, epoch, n):
+    """The host's decision: next waypoint = last observed position + a seeded offset."""
+    r = np.random.default_rng(4242 + epoch)
+    return (observed.astype(np.float64) + r.uniform(-2.0, 2.0, size=(3, n))).astype(np.float32)
+
+
+def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld):
+    """Closed loop through a pipe.  Returns (final state, waypoints [E, 3, n],
+    snapshots per epoch)."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Pipe, Simulator
+    n = sw.state.shape[1]
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
+    pipe = Pipe(sim, n)
+    st = torch.from_numpy(padded(sw.state, ld)).to(dev)
+    per = epoch_steps // snap_every
+    snaps = [torch.empty((per, 3, n), dtype=torch.float32, pin_memory=True) for _ in range(n_epochs)]
+    wps = [sw.wp[0]]
+    pipe.push(wps[0])
+    for e in range(n_epochs):
+        pipe.run(st, epoch_steps, sw.dt, snap_every=snap_every, snaps=snaps[e])
+        if e + 1 == n_epochs:
+            break
+        if e == 0:
+            observed = sw.state[0:3]
+        else:
+            pipe.wait_snapshots(e * per)          # every snapshot of the epochs before e
+            observed = snaps[e - 1][per - 1].numpy()
+        wps.append(decide(observed, e, n))
+        pipe.push(wps[-1])
+    pipe.sync()
+    torch.cuda.synchronize()
+    out = st.cpu().numpy()
+    pipe.close()
+    sim.close()
+    return out, np.stack(wps), [s.numpy().copy() for s in snaps]
+
+
+def resident_replay(torch_dev, sw, wps, epoch_steps, snap_every, ld):
+    """The same rollout with every waypoint epoch resident on the device,
+    stopped at each snapshot step."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    n = sw.state.shape[1]
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
+    st = torch.from_numpy(padded(sw.state, ld)).to(dev)
+    wp = torch.from_numpy(np.ascontiguousarray(wps)).to(dev)
+    snaps = []
+    k = 0
+    for e in range(wps.shape[0]):
+        done = 0
+        while done < epoch_steps:
+            seg = min(snap_every, epoch_steps - done)
+            sim.step(st, seg, sw.dt, n_agents=n, wp=wp, resample_every=epoch_steps, step0=k)
+            k += seg
+            done += seg
+            if seg == snap_every:
+                snaps.append(st[0:3, :n].cpu().numpy())
+    torch.cuda.synchronize()
+    out = st.cpu().numpy()
+    sim.close()
+    return out, snaps
+
+
+@pytest.mark.parametrize("n,ld,epoch_steps,snap_every", [(3000, 3000, 250, 50), (1000, 1037, 250, 60)])
+def test_decision_loop_matches_resident_rollout_and_oracle(oracle, torch_dev, n, ld, epoch_steps, snap_every):
+    sw = I.config1(n=n)
+    n_epochs = 4
+    print(f"pipe closed loop n={n} ld={ld} epochs={n_epochs}x{epoch_steps} snap_every={snap_every}", flush=True)
+    got, wps, snaps = decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld)
+    ref, ref_snaps = resident_replay(torch_dev, sw, wps, epoch_steps, snap_every, ld)
+    assert np.array_equal(got, ref)
+    flat = [s for per_epoch in snaps for s in per_epoch]
+    assert len(flat) == len(ref_snaps) == n_epochs * (epoch_steps // snap_every)
+    for k, (a, b) in enumerate(zip(flat, ref_snaps)):
+        assert np.array_equal(a, b), f"snapshot {k}"
+    # the decision really used streamed positions: epoch 2 waypoints follow snapshot data
+    assert not np.array_equal(wps[2], wps[1])
+    exact = oracle.rollout(sw.state, sw.types, sw.glob, 1, sw.dt, n_epochs * epoch_steps, wp=wps,
+                           resample_every=epoch_steps)
+    errs = rel_errors(got[:30, :n], exact, sw.types)
+    print("pipe parity", {k: f"{v[0]:.2e}" for k, v in errs.items()}, flush=True)
+    assert max(v[0] for v in errs.values()) <= TOL
+
+
+def test_open_loop_commands_and_snapshots(oracle, torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Pipe, Simulator
+    sw = I.config0(n=1000)
+    n, epoch_steps, snap_every = 1000, 200, 100
+    r = np.random.default_rng(77)
+    cmds = [sw.motor_cmd] + [(sw.motor_cmd * r.uniform(0.5, 1.5, size=(4, n))).astype(np.float32)
+                             for _ in range(2)]
+    sim = Simulator(sw.types, sw.glob, mode=0, steps_per_launch=32)
+    pipe = Pipe(sim, n)
+    st = torch.from_numpy(sw.state).to(dev)
+    snaps = torch.empty((len(cmds) * 2, 3, n), dtype=torch.float32, pin_memory=True)
+    for e, c in enumerate(cmds):
+        pipe.push(c)
+        pipe.run(st, epoch_steps, sw.dt, snap_every=snap_every, snaps=snaps[2 * e:2 * e + 2])
+    pipe.sync()
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    pipe.close()
+    ref = torch.from_numpy(sw.state).to(dev)
+    ref_snaps = []
+    for c in cmds:
+        mc = torch.from_numpy(c).to(dev)
+        for _ in range(2):
+            sim.step(ref, snap_every, sw.dt, motor_cmd=mc)
+            ref_snaps.append(ref[0:3].cpu().numpy())
+    torch.cuda.synchronize()
+    assert np.array_equal(got, ref.cpu().numpy())
+    assert np.array_equal(snaps.numpy(), np.stack(ref_snaps))
+    exact = sw.state
+    for c in cmds:
+        exact = oracle.rollout(exact, sw.types, sw.glob, 0, sw.dt, epoch_steps, motor_cmd=c)
+    errs = rel_errors(got[:30], exact, sw.types, groups=OPEN_LOOP_GROUPS)
+    assert max(v[0] for v in errs.values()) <= TOL
+    sim.close()
+
+
+def test_pipe_rejects_invalid_use(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd import _lib as L
+    from paper_2308_12698_amd.sim import Pipe, Simulator
+    sw = I.config1(n=500)
+    sim = Simulator(sw.types, sw.glob, mode=1)
+    pipe = Pipe(sim, 500)
+    st = torch.from_numpy(sw.state).to(dev)
+    with pytest.raises(L.PotatoError, match="before the first"):
+        pipe.run(st, 10, sw.dt)
+    with pytest.raises(ValueError):
+        pipe.push(np.zeros((4, 500), np.float32))
+    pipe.push(sw.wp[0])
+    lib = L.load()
+    sst = L.State(C.c_void_p(st.data_ptr()), st.stride(0))
+    pp = L.Params(None, None, None, 0, None)
+    assert lib.potato_pipe_run(pipe._h, C.byref(sst), C.byref(pp), C.c_float(sw.dt), 20, 10, None,
+                               None) == L.EINVAL                      # snapshot due, no buffer
+    assert lib.potato_pipe_run(pipe._h, C.byref(sst), C.byref(pp), C.c_float(-1.0), 20, 0, None,
+                               None) == L.EINVAL                      # dt
+    assert lib.potato_pipe_wait_snapshots(pipe._h, 1) == L.EINVAL    # none taken
+    pipe.run(st, 20, sw.dt)                                           # first run: current stream
+    side = torch.cuda.Stream()
+    with pytest.raises(L.PotatoError, match="same stream"):
+        pipe.run(st, 20, sw.dt, stream=side)
+    pipe.sync()
+    pipe.close()
+    sim.close()
