@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
  * (grid-stride), cotangents and gain sums in registers, the recomputed
  * segment in this thread's tape column. */
 #ifndef POTATO_ADJOINT_WAVES
-#define POTATO_ADJOINT_WAVES 1
+#define POTATO_ADJOINT_WAVES 2
 #endif
 
 template <bool HET, bool GAINS, bool PERM>
@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(kAdjBlock)
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const uint32_t tbo = (uint32_t)tid << 2;      /* this thread's tape column */
+    const int n_seg_all = (A.n_steps + A.K - 1) / A.K;
     for (int64_t j = tid; j < A.n; j += stride) {
         const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
         const uint32_t bo = i << 2;
@@ -233,12 +234,12 @@ __global__ void __launch_bounds__(kAdjBlock)
                       c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
         }
         AgentAdj lam;
-        load_adj<false>(A.grad_final, ld, bo, lam);
+        load_adj(A.grad_final, ld, bo, lam);
         float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (steps > 0)
-            agent_backward<!HET>(c, lim, g, A.ckpt, ld, bo, A.K, steps, A.step0, A.wp, A.cmd_ld, A.n_epochs,
-                                 A.resample, A.tape, A.tape_ld, tbo, lam, gk);
-        store_adj<false>(A.grad_x0, ld, bo, lam);
+            agent_backward(c, lim, g, A.ckpt, ld, bo, A.K, n_seg_all, steps, A.step0, A.wp, A.cmd_ld,
+                           A.n_epochs, A.resample, A.tape, A.tape_ld, tbo, lam, gk);
+        store_adj(A.grad_x0, ld, bo, lam);
         if (A.grad_gains) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) elem(A.grad_gains + k * ld, bo) = gk[k];

@@ -18,10 +18,6 @@
 
 #include "quad_step.h"
 
-#ifndef POTATO_ADJOINT_PREFETCH
-#define POTATO_ADJOINT_PREFETCH 1
-#endif
-
 namespace potato {
 
 /* Cotangents of the 30 physical state rows. */
@@ -386,17 +382,16 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
     for (int i = 0; i < 3; ++i) lam.p[i] -= l_e[i];
 }
 
-/* Row accessors: `base` is row 0 of a [rows][ld] buffer and `bo` the lane's
- * byte offset (column index times 4).  U: `base` is the same in every
- * active lane, so row addresses can stay in scalar registers. */
-template <bool U, typename T>
+/* Row accessors: `base` is row 0 of a [rows][ld] buffer, the same address
+ * in every active lane, and `bo` the lane's byte offset (column index
+ * times 4). */
+template <typename T>
 __device__ __forceinline__ T* row_ptr(T* base, int64_t ld, int k) {
-    return U ? uniform(base + k * ld) : base + k * ld;
+    return uniform(base + k * ld);
 }
 
-template <bool U>
 __device__ __forceinline__ void load_rows(const float* base, int64_t ld, uint32_t bo, Agent& a, bool carries) {
-    auto row = [&](int k) { return elem(row_ptr<U>(base, ld, k), bo); };
+    auto row = [&](int k) { return elem(row_ptr(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k);
@@ -413,9 +408,8 @@ __device__ __forceinline__ void load_rows(const float* base, int64_t ld, uint32_
 }
 
 /* The 30 physical rows (the tape does not need the carries). */
-template <bool U>
 __device__ __forceinline__ void store_phys_rows(float* base, int64_t ld, uint32_t bo, const Agent& a) {
-    auto row = [&](int k) -> float& { return elem(row_ptr<U>(base, ld, k), bo); };
+    auto row = [&](int k) -> float& { return elem(row_ptr(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k];
@@ -427,9 +421,8 @@ __device__ __forceinline__ void store_phys_rows(float* base, int64_t ld, uint32_
     row(29) = a.J;
 }
 
-template <bool U>
 __device__ __forceinline__ void load_adj(const float* base, int64_t ld, uint32_t bo, AgentAdj& l) {
-    auto row = [&](int k) { return elem(row_ptr<U>(base, ld, k), bo); };
+    auto row = [&](int k) { return elem(row_ptr(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         l.p[k] = row(k); l.v[k] = row(3 + k); l.w[k] = row(10 + k);
@@ -441,9 +434,8 @@ __device__ __forceinline__ void load_adj(const float* base, int64_t ld, uint32_t
     l.J = row(29);
 }
 
-template <bool U>
 __device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, const AgentAdj& l) {
-    auto row = [&](int k) -> float& { return elem(row_ptr<U>(base, ld, k), bo); };
+    auto row = [&](int k) -> float& { return elem(row_ptr(base, ld, k), bo); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         row(k) = l.p[k]; row(3 + k) = l.v[k]; row(10 + k) = l.w[k];
@@ -462,66 +454,56 @@ __device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, 
  * Each segment is recomputed forward from its checkpoint with the
  * step-start states written to this thread's tape column (K slots of 30
  * rows of stride tape_ld, byte offset tbo), then reversed step by step.
- * U: every active lane runs the same number of steps (one type), so the
- * checkpoint, tape and waypoint rows of an iteration are the same for all
- * of them.  lam: cotangent of the final state on entry, of
- * the initial state on return; gk accumulates the gain cotangents.
+ * lam: cotangent of the final state on entry, of the initial state on
+ * return; gk accumulates the gain cotangents.
+ *
+ * The loops run over the call's segments and slots (n_seg_all =
+ * ceil(n_steps / K) and K, the same for every lane), and a lane skips the
+ * iterations beyond its own step count.  All active lanes are therefore at
+ * the same segment, slot and step, so checkpoint, tape and waypoint rows
+ * are wave-uniform addresses even when step budgets differ between lanes.
+ * Each reverse step loads its tape slot; the other resident wave covers
+ * the load latency (holding the next slot in registers instead costs 30
+ * registers and the second wave).
  */
-template <bool U>
 __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits& L, const Gains& g,
                                                const float* ckpt, int64_t ld, uint32_t bo, int K,
-                                               int steps, int64_t step0, const float* wp, int64_t cmd_ld,
-                                               int n_epochs, int resample, float* tape, int64_t tape_ld,
-                                               uint32_t tbo, AgentAdj& lam, float gk[9]) {
+                                               int n_seg_all, int steps, int64_t step0, const float* wp,
+                                               int64_t cmd_ld, int n_epochs, int resample, float* tape,
+                                               int64_t tape_ld, uint32_t tbo, AgentAdj& lam, float gk[9]) {
     const int n_seg = (steps + K - 1) / K;
     /* the waypoint is reloaded only when the epoch changes */
     int64_t cur_ep = -1;
     float wpv[3] = {0.0f, 0.0f, 0.0f};
-    auto epoch_of = [&](int64_t k) {
+    auto use_step = [&](int64_t k) {
         int64_t ep = resample > 0 ? k / resample : 0;
-        return ep < n_epochs - 1 ? ep : (int64_t)n_epochs - 1;
-    };
-    auto use_epoch = [&](int64_t ep) {
+        ep = ep < n_epochs - 1 ? ep : (int64_t)n_epochs - 1;
         if (ep != cur_ep) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) wpv[i] = elem(row_ptr<U>(wp, cmd_ld, (int)ep * 3 + i), bo);
+            for (int i = 0; i < 3; ++i) wpv[i] = elem(uniform(wp + (ep * 3 + i) * cmd_ld), bo);
             cur_ep = ep;
         }
     };
-    for (int seg = n_seg - 1; seg >= 0; --seg) {
+    for (int seg = n_seg_all - 1; seg >= 0; --seg) {
+        if (seg >= n_seg) continue;
         const int k_begin = seg * K;
         const int len = steps - k_begin < K ? steps - k_begin : K;
         Agent a;
-        load_rows<U>(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
+        load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
         for (int s = 0; s < len; ++s) {
-            store_phys_rows<U>(tape + (int64_t)s * 30 * tape_ld, tape_ld, tbo, a);
+            store_phys_rows(tape + (int64_t)s * 30 * tape_ld, tape_ld, tbo, a);
             float dc[4];
-            use_epoch(epoch_of(step0 + k_begin + s));
+            use_step(step0 + k_begin + s);
             controller(c, L, g, a, wpv, dc);
             rk4_step(c, L, a, dc);
         }
-#if POTATO_ADJOINT_PREFETCH
-        /* reverse sweep; the tape slot of the next (earlier) step is loaded
-         * while the current step is differentiated (30 more live registers) */
-        Agent x;
-        load_rows<U>(tape + (int64_t)(len - 1) * 30 * tape_ld, tape_ld, tbo, x, false);
-        for (int s = len - 1; s >= 0; --s) {
-            Agent nx;
-            if (s > 0) load_rows<U>(tape + (int64_t)(s - 1) * 30 * tape_ld, tape_ld, tbo, nx, false);
-            use_epoch(epoch_of(step0 + k_begin + s));
-            step_vjp(c, L, g, x, wpv, lam, gk);
-            if (s > 0) x = nx;
-        }
-#else
-        /* reverse sweep; each step loads its tape slot, and the other
-         * resident waves cover the load latency */
-        for (int s = len - 1; s >= 0; --s) {
+        for (int s = K - 1; s >= 0; --s) {
+            if (s >= len) continue;
             Agent x;
-            load_rows<U>(tape + (int64_t)s * 30 * tape_ld, tape_ld, tbo, x, false);
-            use_epoch(epoch_of(step0 + k_begin + s));
+            load_rows(tape + (int64_t)s * 30 * tape_ld, tape_ld, tbo, x, false);
+            use_step(step0 + k_begin + s);
             step_vjp(c, L, g, x, wpv, lam, gk);
         }
-#endif
     }
 }
 
