@@ -14,7 +14,7 @@
  *      the command held through the four stages;
  *   3. renormalisation of the attitude quaternion.
  * Batching homogeneous agents in tensors is the data-oriented design of
- * Sec. II-A (Fig. 1); several airframe types in one batch through a
+ * Sec. I (Fig. 1); several airframe types in one batch through a
  * per-agent type index replace the paper's one-process-per-type scheme.
  *
  * Conventions shared by every entry point:
@@ -253,7 +253,7 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
                                        int64_t workspace_bytes, void* stream);
 
 /*
- * Command ingress and snapshot egress around a running rollout (Sec. III-A,
+ * Command ingress and snapshot egress around a running rollout (Sec. II-A,
  * Fig. 2: the decision side is kept out of the simulation loop, so the
  * simulated world keeps running while new commands are produced, and the
  * states are streamed out to a viewer).  A pipe owns two device command

@@ -20,7 +20,7 @@
  *     are this project's reading, listed in the design notes);
  *   - first-order rotor lag and linear drag (workload definition, not in the
  *     paper).
- * The paper batches agents as tensors (Sec. II-A, Fig. 1); batching changes
+ * The paper batches agents as tensors (Sec. I, Fig. 1); batching changes
  * no agent's arithmetic, so the reference is simply a loop over agents.
  *
  * The step, controller and dynamics are templates on the scalar type so the

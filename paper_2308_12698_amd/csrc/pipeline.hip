@@ -1,7 +1,7 @@
 /*
  * pipeline.hip -- command ingress and position snapshots overlapped with a
  * running rollout (the decision and viewer directions of the system of
- * Sec. III-A, Fig. 2, which the paper keeps outside the simulation loop).
+ * Sec. II-A, Fig. 2, which the paper keeps outside the simulation loop).
  *
  * Streams and ordering.  Runs go to the caller's compute stream.  Command
  * uploads go to the pipe's ingress stream, snapshot downloads to its egress

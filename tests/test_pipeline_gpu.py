@@ -1,6 +1,6 @@
 """Command ingress and position snapshots around running rollouts: the
 decision and viewer directions that the paper keeps outside the simulation
-loop (Sec. III-A, Fig. 2).
+loop (Sec. II-A, Fig. 2).
 
 A host decision loop sees the positions streamed out of the GPU one epoch
 late and pushes the next waypoints while the GPU keeps simulating.  The
