@@ -10,12 +10,13 @@
  * on entry (simultaneous events).
  *
  * Grid: cell edge h = 2.02 r_max (r_max the largest radius), so any colliding
- * pair sits in the same or an adjacent cell; cells are hashed (Teschner et
- * al. 2003) into M = 2^k >= 2N buckets.  Passes: clear, count agents per
- * bucket, exclusive scan, scatter agent ids, then each alive agent tests the
- * agents of the buckets of its 27 neighbour cells.  Ids within a bucket come
- * out in atomic order, but the result (an OR over neighbours) does not
- * depend on it.  The 1 % margin in h keeps the neighbour property exact for
+ * pair sits in the same or an adjacent cell; cells map to M = 2^k >= 2N
+ * buckets by the low bits of their Z-order (Morton) code.  Passes: clear, count agents per
+ * bucket, exclusive scan, counting-sort scatter of (id, x, y, z, radius)
+ * into bucket order, then one thread per sorted slot tests the slots of the
+ * buckets of its 27 neighbour cells.  Slots within a bucket come out in
+ * atomic order, but the result (an OR over neighbours) does not depend on
+ * it.  The 1 % margin in h keeps the neighbour property exact for
  * |coordinates| < 2^16 h (about 22 km for 0.17 m radii).
  */
 #include "kernels.h"
@@ -26,8 +27,24 @@ namespace {
 
 constexpr int kScanBlock = 1024;
 
-__device__ __forceinline__ uint32_t cell_hash(int32_t ix, int32_t iy, int32_t iz, uint32_t mask) {
-    return ((uint32_t)ix * 73856093u ^ (uint32_t)iy * 19349663u ^ (uint32_t)iz * 83492791u) & mask;
+/* Low 10 bits of v moved to every third bit position (bit interleaving for
+ * a Morton / Z-order code). */
+__device__ __forceinline__ uint32_t spread3(int32_t v) {
+    uint32_t x = (uint32_t)v & 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+/* Bucket of a cell: the low bits of its Z-order code, i.e. a grid that wraps
+ * around every 2^(bits/3) cells per axis.  Cells that share a bucket are far
+ * apart and fail the distance test; cells that are close get nearby bucket
+ * numbers, so agents sorted by bucket are sorted along a space-filling
+ * curve and neighbouring threads of the query read the same buckets. */
+__device__ __forceinline__ uint32_t cell_bucket(uint32_t sx, uint32_t sy, uint32_t sz, uint32_t mask) {
+    return (sx | (sy << 1) | (sz << 2)) & mask;
 }
 
 __device__ __forceinline__ void cell_of(float x, float y, float z, float inv_h, int32_t& ix, int32_t& iy,
@@ -37,11 +54,8 @@ __device__ __forceinline__ void cell_of(float x, float y, float z, float inv_h, 
     iz = (int32_t)floorf(z * inv_h);
 }
 
-__global__ void __launch_bounds__(256) k_coll_clear(int32_t* count, int32_t* cursor, uint32_t m) {
-    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < m; b += gridDim.x * blockDim.x) {
-        count[b] = 0;
-        cursor[b] = 0;
-    }
+__global__ void __launch_bounds__(256) k_coll_clear(int32_t* count, uint32_t m) {
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < m; b += gridDim.x * blockDim.x) count[b] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_coll_count(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
@@ -50,7 +64,7 @@ __global__ void __launch_bounds__(256) k_coll_count(const float* rows, int64_t l
     if (i >= n || !alive[i]) return;
     int32_t ix, iy, iz;
     cell_of(rows[i], rows[ld + i], rows[2 * ld + i], inv_h, ix, iy, iz);
-    const uint32_t b = cell_hash(ix, iy, iz, mask);
+    const uint32_t b = cell_bucket(spread3(ix), spread3(iy), spread3(iz), mask);
     key[i] = b;
     atomicAdd(&count[b], 1);
 }
@@ -73,7 +87,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_chunks(const int32_t* in, i
     if (threadIdx.x == kScanBlock - 1) totals[blockIdx.x] = buf[threadIdx.x];
 }
 
-/* One block: exclusive scan of the chunk totals (any count), in place. */
+/* One block: exclusive scan of the chunk totals (any count), in place;
+ * the grand total goes to *grand. */
 __global__ void __launch_bounds__(kScanBlock) k_scan_totals(int32_t* totals, uint32_t n_chunks, int32_t* grand) {
     __shared__ int32_t buf[kScanBlock];
     int32_t carry = 0;
@@ -101,46 +116,62 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, const int
     if (g < m) out[g] += totals[blockIdx.x];
 }
 
-__global__ void __launch_bounds__(256) k_coll_scatter(int64_t n, const uint8_t* alive, const uint32_t* key,
-                                                      const int32_t* start, int32_t* cursor, int32_t* ids) {
+/* Counting sort of the alive agents by bucket: agent i gets a slot in its
+ * bucket's range (taking the bucket's count down to zero), and the slot
+ * receives the agent id and (x, y, z, radius), so that the query reads each
+ * bucket's candidates from consecutive addresses. */
+__global__ void __launch_bounds__(256) k_coll_scatter(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
+                                                      const uint8_t* type, const float* radius, const uint32_t* key,
+                                                      const int32_t* start, int32_t* count, int32_t* ids,
+                                                      float4* spos) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !alive[i]) return;
     const uint32_t b = key[i];
-    ids[start[b] + atomicAdd(&cursor[b], 1)] = (int32_t)i;
+    const int32_t slot = start[b] + atomicSub(&count[b], 1) - 1;
+    ids[slot] = (int32_t)i;
+    spos[slot] = make_float4(rows[i], rows[ld + i], rows[2 * ld + i], radius[type ? type[i] : 0]);
 }
 
-template <bool HET>
-__global__ void __launch_bounds__(256) k_coll_query(const float* rows, int64_t ld, int64_t n, const uint8_t* type,
-                                                    const float* radius, float inv_h, uint32_t mask,
-                                                    const int32_t* start, const int32_t* count, const int32_t* ids,
+/* One thread per sorted slot: consecutive lanes hold agents of the same or
+ * nearby cells, so the bucket ranges and candidate positions they read are
+ * shared through the caches. */
+__global__ void __launch_bounds__(256) k_coll_query(const float4* spos, const int32_t* ids, const int32_t* start,
+                                                    const int32_t* total, float inv_h, uint32_t mask,
                                                     uint8_t* alive, unsigned long long* died) {
 #pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !alive[i]) return;
-    const float xi = rows[i], yi = rows[ld + i], zi = rows[2 * ld + i];
-    const float ri = radius[HET ? type[i] : 0];
+    const int32_t k = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= *total) return;
+    const float4 pk = spos[k];
     int32_t cx, cy, cz;
-    cell_of(xi, yi, zi, inv_h, cx, cy, cz);
+    cell_of(pk.x, pk.y, pk.z, inv_h, cx, cy, cz);
+    const uint32_t sx[3] = {spread3(cx - 1), spread3(cx), spread3(cx + 1)};
+    const uint32_t sy[3] = {spread3(cy - 1), spread3(cy), spread3(cy + 1)};
+    const uint32_t sz[3] = {spread3(cz - 1), spread3(cz), spread3(cz + 1)};
+    /* all 27 bucket ranges are requested before any is used, so their
+     * loads are in flight together instead of one round trip per cell */
+    int32_t lo[27], hi[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        const uint32_t b = cell_bucket(sx[c % 3], sy[(c / 3) % 3], sz[c / 9], mask);
+        lo[c] = start[b];
+        hi[c] = start[b + 1];
+    }
     bool hit = false;
-    for (int dz = -1; dz <= 1 && !hit; ++dz)
-        for (int dy = -1; dy <= 1 && !hit; ++dy)
-            for (int dx = -1; dx <= 1 && !hit; ++dx) {
-                const uint32_t b = cell_hash(cx + dx, cy + dy, cz + dz, mask);
-                const int32_t s = start[b], e = s + count[b];
-                for (int32_t k = s; k < e; ++k) {
-                    const int32_t j = ids[k];
-                    if (j == (int32_t)i) continue;
-                    const float rj = radius[HET ? type[j] : 0];
-                    const float ex = xi - rows[j], ey = yi - rows[ld + j], ez = zi - rows[2 * ld + j];
-                    const float d2 = (ex * ex + ey * ey) + ez * ez;
-                    const float rs = ri + rj;
-                    if (d2 < rs * rs) { hit = true; break; }
-                }
-            }
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        for (int32_t j = lo[c]; j < hi[c] && !hit; ++j) {
+            if (j == k) continue;
+            const float4 pj = spos[j];
+            const float ex = pk.x - pj.x, ey = pk.y - pj.y, ez = pk.z - pj.z;
+            const float d2 = (ex * ex + ey * ey) + ez * ez;
+            const float rs = pk.w + pj.w;
+            hit = d2 < rs * rs;
+        }
+    }
     if (hit) {
-        /* alive[] is not read by any query of this pass (the bucket lists
-         * hold the entry alive set), so it is updated in place */
-        alive[i] = 0;
+        /* the query reads positions from the sorted copy only, so the mask
+         * is updated in place */
+        alive[ids[k]] = 0;
         if (died) atomicAdd(died, 1ull);
     }
 }
@@ -149,15 +180,16 @@ __global__ void __launch_bounds__(256) k_coll_query(const float* rows, int64_t l
 
 uint32_t collision_buckets(int64_t n) {
     uint32_t m = 1024;
-    while ((int64_t)m < 2 * n) m <<= 1;
+    while ((int64_t)m < 2 * n && m < (1u << 30)) m <<= 1;   /* the Z-order code has 30 bits */
     return m;
 }
 
 int64_t collision_workspace_bytes(int64_t n) {
     const int64_t m = collision_buckets(n);
     const int64_t chunks = (m + kScanBlock - 1) / kScanBlock;
-    /* count, start, cursor [m]; key, ids [n]; chunk totals + grand total */
-    return (3 * m + 2 * n + chunks + 1) * 4 + 256;
+    /* sorted (x, y, z, r) [n] first (16-byte aligned); count [m]; start [m+1];
+     * key, ids [n]; chunk totals [chunks] */
+    return 16 * n + (m + (m + 1) + 2 * n + chunks) * 4 + 256;
 }
 
 hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type,
@@ -165,29 +197,24 @@ hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, co
                                     unsigned long long* died, void* workspace, hipStream_t s) {
     const uint32_t m = collision_buckets(n);
     const uint32_t chunks = (m + kScanBlock - 1) / kScanBlock;
-    int32_t* count = reinterpret_cast<int32_t*>(workspace);
+    float4* spos = reinterpret_cast<float4*>(workspace);
+    int32_t* count = reinterpret_cast<int32_t*>(spos + n);
     int32_t* start = count + m;
-    int32_t* cursor = start + m;
-    uint32_t* key = reinterpret_cast<uint32_t*>(cursor + m);
+    uint32_t* key = reinterpret_cast<uint32_t*>(start + m + 1);
     int32_t* ids = reinterpret_cast<int32_t*>(key + n);
     int32_t* totals = ids + n;
-    int32_t* grand = totals + chunks;
     const float inv_h = 1.0f / (2.02f * r_max);
     const uint32_t mask = m - 1;
     const unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_coll_clear, dim3((m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096), dim3(256), 0, s, count,
-                       cursor, m);
+    hipLaunchKernelGGL(k_coll_clear, dim3((m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096), dim3(256), 0, s, count, m);
     hipLaunchKernelGGL(k_coll_count, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, inv_h, mask, count, key);
     hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(kScanBlock), 0, s, count, start, totals, m);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, s, totals, chunks, grand);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, s, totals, chunks, start + m);
     hipLaunchKernelGGL(k_scan_add, dim3(chunks), dim3(kScanBlock), 0, s, start, totals, m);
-    hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, n, alive, key, start, cursor, ids);
-    if (type)
-        hipLaunchKernelGGL(k_coll_query<true>, dim3(nb), dim3(256), 0, s, rows, ld, n, type, radius_dev, inv_h,
-                           mask, start, count, ids, alive, died);
-    else
-        hipLaunchKernelGGL(k_coll_query<false>, dim3(nb), dim3(256), 0, s, rows, ld, n, type, radius_dev, inv_h,
-                           mask, start, count, ids, alive, died);
+    hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, type, radius_dev, key, start,
+                       count, ids, spos);
+    hipLaunchKernelGGL(k_coll_query, dim3(nb), dim3(256), 0, s, spos, ids, start, start + m, inv_h, mask, alive,
+                       died);
     return hipGetLastError();
 }
 

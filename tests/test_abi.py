@@ -110,7 +110,8 @@ def test_collision_workspace_size(lib):
     assert lib.potato_collision_workspace_bytes(0) == -1
     n = 1000
     m = 2048                                   # smallest power of two >= 2n (and >= 1024)
-    expect = (3 * m + 2 * n + m // 1024 + 1) * 4 + 256
+    # sorted (x, y, z, r) [n]; count [m]; start [m + 1]; key, ids [n]; chunk totals
+    expect = 16 * n + (m + (m + 1) + 2 * n + m // 1024) * 4 + 256
     assert lib.potato_collision_workspace_bytes(n) == expect
 
 
