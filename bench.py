@@ -82,6 +82,9 @@ def main():
                          "500 warm-up rounds, 2,000 timed rounds, 3 executions), GPU plain and "
                          "fused forms and the FP64 reference on 1 and all host threads; prints "
                          "one JSON line per point and exits")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time the FP64 reference on each workload on 1 and all host threads "
+                         "(bounded samples), print one JSON line per row and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of known size (for scaling "
                          "HBM byte counters) and exit")
@@ -91,6 +94,9 @@ def main():
         return
     if args.sweep:
         sweep()
+        return
+    if args.oracle_table:
+        oracle_table()
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the quadrotor step has no cross-agent coupling, "
@@ -152,7 +158,8 @@ def main():
                 "avg_launch_ms": round(launch_ms, 4), "agents_per_launch": N,
                 "steps_per_launch": tuned["steps_per_launch"]}
 
-    forms = {"fused_graph": {"agent_steps_per_s": value, "rollout_ms": float(np.mean(ev_ms))}}
+    forms = {"fused_graph": {"agent_steps_per_s": value, "rollout_ms": float(np.mean(ev_ms)),
+                             "rollout_ms_sd": float(np.std(ev_ms)), "rollouts": len(ev_ms)}}
     if not args.no_extra:
         forms.update(extra_forms(torch, dev, stream, sim, state, wp, sw, T, ops,
                                  set(args.forms.split(","))))
@@ -435,6 +442,51 @@ def sweep(sizes=SWEEP_SIZES, warm=500, rounds=2000, execs=3, cpu_budget_s=4.0):
             cpu_rate[threads] = n * r / dt
             print(json.dumps({"sweep": "oracle", "threads": threads, "n_agents": n, "rounds": r,
                               "ms_per_round": dt / r * 1e3, "agent_steps_per_s": n * r / dt}), flush=True)
+
+
+def oracle_table(budget_s=8.0):
+    """The reference on each workload, single thread and all host threads.
+    Each row runs the workload's agents (or a prefix of them) for as many
+    steps as fit in about budget_s seconds, scaled from a short probe."""
+    from oracle import oracle as O
+    from paper_2308_12698_amd import inputs as I
+    all_threads = max(1, min(16, os.cpu_count() or 1))
+
+    def run(label, sw, n_steps, threads, agents=None):
+        sub = sw if agents is None or agents >= sw.n else I.subset(sw, np.arange(agents))
+        kw = dict(type_idx=sub.type_idx, gains=sub.gains, motor_cmd=sub.motor_cmd, wp=sub.wp,
+                  resample_every=sub.resample_every, threads=threads)
+        probe = max(1, min(n_steps, 20))
+        t0 = time.perf_counter()
+        O.rollout(sub.state, sub.types, sub.glob, sub.mode, sub.dt, probe, **kw)
+        rate = sub.n * probe / max(time.perf_counter() - t0, 1e-6)
+        steps = int(max(1, min(n_steps, budget_s * rate / sub.n)))
+        t0 = time.perf_counter()
+        O.rollout(sub.state, sub.types, sub.glob, sub.mode, sub.dt, steps, **kw)
+        dt = time.perf_counter() - t0
+        print(json.dumps({"oracle": label, "threads": threads, "agents": sub.n, "steps": steps,
+                          "of_steps": n_steps, "seconds": dt, "agent_steps_per_s": sub.n * steps / dt}),
+              flush=True)
+
+    rows = [("open loop, 1,000 agents", I.config0(), 1000, None),
+            ("closed loop, 5,000 agents", I.config1(), 1000, None),
+            ("scale swarm, 1,048,576 agents", I.config2(), 1000, None),
+            ("heterogeneous, 1,007,616 agents (first 1,000 steps)", I.config3(), 1000, None),
+            ("differentiable forward, 65,536 agents", I.config4(), 500, None)]
+    for label, sw, n_steps, agents in rows:
+        for threads in (1, all_threads):
+            run(label, sw, n_steps, threads, agents)
+    # forward-mode dual-number gradients of the differentiable rollout, 64 agents
+    dw = I.config4()
+    sub = I.subset(dw, np.arange(64))
+    for threads in (1, all_threads):
+        t0 = time.perf_counter()
+        O.jacobian(sub.state, sub.types, sub.glob, sub.dt, sub.n_steps, wp=sub.wp, gains=sub.gains,
+                   threads=threads)
+        dt = time.perf_counter() - t0
+        print(json.dumps({"oracle": "dual-number Jacobian (39 directions), 64 agents x 500 steps",
+                          "threads": threads, "agents": 64, "steps": sub.n_steps, "seconds": dt,
+                          "agent_steps_per_s": 64 * sub.n_steps / dt}), flush=True)
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):
