@@ -501,7 +501,7 @@ int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* pa
     const bool het = params->type != nullptr;
     const int grid = adjoint_grid(ctx, het, params->gains != nullptr, het && params->perm != nullptr, n_agents);
     if (grid < 1) return -1;
-    return (int64_t)ckpt_every * 30 * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
+    return (int64_t)ckpt_every * kTapeRows * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
 }
 
 potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params, const potato_cmds* cmds,
@@ -528,7 +528,7 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
     std::lock_guard<std::mutex> g(ctx->mu);
     const int grid = adjoint_grid(ctx, het, gains, perm, n_agents);
     if (grid < 1) return fail(POTATO_EHIP, "occupancy query failed");
-    const int64_t need = (int64_t)ckpt_every * 30 * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
+    const int64_t need = (int64_t)ckpt_every * kTapeRows * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
     if (workspace_bytes < need)
         return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
     AdjArgs a{};

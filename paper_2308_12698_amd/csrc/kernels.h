@@ -70,7 +70,7 @@ struct AdjArgs {
     const float* grad_final;     /* [30][ld] */
     float* grad_x0;              /* [30][ld] */
     float* grad_gains;           /* [9][ld] or null */
-    float* tape;                 /* [K][30][tape_ld], one column per thread of the grid */
+    float* tape;                 /* [K][kTapeRows][tape_ld], one column per thread of the grid */
     int64_t tape_ld;
     int32_t n_types;
     const TypeConst* table;

@@ -291,6 +291,12 @@ def test_step_rejects_invalid_arguments(torch_dev):
     assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 1e-3, 64, 10, C.c_void_p(st.data_ptr()), 0, None) == L.EINVAL
     Cm0 = L.Cmds(None, None, 0, 0, 64, 0)
     assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm0), 1e-3, 64, 10, None, 0, None) == L.EINVAL
+    # more than 2^30 agents: rejected before any device access (byte offsets are 32-bit)
+    big = (1 << 30) + 1
+    Sb = L.State(C.c_void_p(st.data_ptr()), big)
+    Cb = L.Cmds(None, C.c_void_p(wp.data_ptr()), 1, 0, big, 0)
+    assert lib.potato_step(h, C.byref(Sb), C.byref(P), C.byref(Cb), 1e-3, big, 10, None, 0, None) == L.EINVAL
+    assert b"2^30" in lib.potato_last_error()
     torch.cuda.synchronize()
     assert torch.equal(st, before)
     with pytest.raises(ValueError):
