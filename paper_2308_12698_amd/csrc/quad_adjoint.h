@@ -115,17 +115,14 @@ __device__ __forceinline__ void dyn_axpy(const Dyn& x, float h, const Dyn& k, Dy
  * return; gk accumulates the gain cotangents.
  */
 __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, const Gains& k,
-                                         const Agent& a, const float wp[3], const float* dc_taped,
-                                         AgentAdj& lam, float gk[9]) {
-    /* ---------------- held command ----------------
-     * taken from the tape when the recomputation stored it, else the forward
-     * controller on a copy (its intermediates are recomputed below, after the
-     * RK4 reverse, so they are not live while the stage states are) */
+                                         const Agent& a, const float wp[3], AgentAdj& lam,
+                                         float gk[9]) {
+    /* ---------------- held command: the forward controller on a copy ----------------
+     * (its intermediates are recomputed below, after the RK4 reverse, so they
+     * are not live while the stage states are; storing the command on the
+     * tape instead measured no faster) */
     float dc[4];
-    if (dc_taped) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) dc[i] = dc_taped[i];
-    } else {
+    {
         Agent tmp = a;
         controller(c, L, k, tmp, wp, dc);
     }
@@ -495,29 +492,18 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         Agent a;
         load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
         for (int s = 0; s < len; ++s) {
-            float* const slot = tape + (int64_t)s * kTapeRows * tape_ld;
-            store_phys_rows(slot, tape_ld, tbo, a);
+            store_phys_rows(tape + (int64_t)s * kTapeRows * tape_ld, tape_ld, tbo, a);
             float dc[4];
             use_step(step0 + k_begin + s);
             controller(c, L, g, a, wpv, dc);
-            if (kTapeRows > 30) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) elem(row_ptr(slot, tape_ld, 30 + i), tbo) = dc[i];
-            }
             rk4_step(c, L, a, dc);
         }
         for (int s = K - 1; s >= 0; --s) {
             if (s >= len) continue;
-            const float* const slot = tape + (int64_t)s * kTapeRows * tape_ld;
             Agent x;
-            load_rows(slot, tape_ld, tbo, x, false);
-            float dc[4];
-            if (kTapeRows > 30) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) dc[i] = elem(row_ptr(slot, tape_ld, 30 + i), tbo);
-            }
+            load_rows(tape + (int64_t)s * kTapeRows * tape_ld, tape_ld, tbo, x, false);
             use_step(step0 + k_begin + s);
-            step_vjp(c, L, g, x, wpv, kTapeRows > 30 ? dc : nullptr, lam, gk);
+            step_vjp(c, L, g, x, wpv, lam, gk);
         }
     }
 }

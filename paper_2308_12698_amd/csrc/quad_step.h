@@ -105,13 +105,8 @@ __device__ __forceinline__ T* uniform(T* p) {
 }
 
 /* Rows per step of the adjoint's recomputation tape: the 30 physical rows
- * of the step-start state, plus the step's held rotor command when
- * POTATO_TAPE_DC is set (the reverse step then skips one controller
- * evaluation). */
-#ifndef POTATO_TAPE_DC
-#define POTATO_TAPE_DC 0
-#endif
-constexpr int kTapeRows = POTATO_TAPE_DC ? 34 : 30;
+ * of the step-start state. */
+constexpr int kTapeRows = 30;
 
 #define POTATO_FMA(a, b, c) __builtin_fmaf((a), (b), (c))
 
