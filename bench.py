@@ -119,7 +119,7 @@ def main():
     state = torch.from_numpy(sw.state).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
     sim = Simulator(sw.types, sw.glob, mode=1, form="fused", use_graph=True)
-    tuned = sim.autotune(state, sw.dt, 200, wp=wp, resample_every=sw.resample_every)
+    tuned = sim.autotune(state, sw.dt, min(1000, T), wp=wp, resample_every=sw.resample_every)
     sim.set_options(form="fused", use_graph=True, **tuned)
     log(f"autotuned launch shape: {tuned}")
     launches = -(-T // tuned["steps_per_launch"])
@@ -416,7 +416,7 @@ def sweep(sizes=SWEEP_SIZES, warm=500, rounds=2000, execs=3, cpu_budget_s=4.0):
             state = torch.from_numpy(sw.state).to(dev)
             sim = Simulator(sw.types, sw.glob, mode=1, form=form, use_graph=True)
             if form == "fused":
-                tuned = sim.autotune(state, sw.dt, 200, wp=wp)
+                tuned = sim.autotune(state, sw.dt, 1000, wp=wp)
                 sim.set_options(form="fused", use_graph=True, **tuned)
             sim.step(state, warm, sw.dt, wp=wp)
             sim.step(state, rounds, sw.dt, wp=wp)     # captures the graph that is timed below

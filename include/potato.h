@@ -180,11 +180,12 @@ potato_status potato_step(potato_ctx* ctx, const potato_state* state, const pota
                           float* ckpt, int32_t ckpt_every, void* stream);
 
 /*
- * Time the fused form over a grid of (block, steps per launch, grid size)
- * on a scratch copy of the given inputs (the caller's buffers are not
- * modified), store the fastest on the context for this mode and type
- * layout, and return it in *best (may be NULL).  probe_steps is the number
- * of time steps per timed trial.  Allocates scratch memory for the
+ * Time the fused form over a grid of (block in {64, 128, 256, 512}, steps
+ * per launch in {25, 50, 100, 200, 500, 1000} up to probe_steps, grid of one
+ * agent per thread or 1x / 2x the resident blocks) on a scratch copy of the
+ * given inputs (the caller's buffers are not modified), store the fastest on
+ * the context for this mode and type layout, and return it in *best (may be
+ * NULL).  probe_steps is the number of time steps per timed trial.  Allocates scratch memory for the
  * duration of the call and synchronises `stream`.
  */
 potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const potato_params* params,

@@ -425,7 +425,10 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
     Tuned win{256, 100, 0};
     double win_ms = 1e300;
     const int blocks[] = {64, 128, 256, 512};
-    const int steps_opts[] = {25, 50, 100, 200};
+    /* steps per launch: the candidates up to probe_steps (at least one) */
+    std::vector<int> steps_opts;
+    for (int S : {25, 50, 100, 200, 500, 1000})
+        if (S <= probe_steps || steps_opts.empty()) steps_opts.push_back(std::min(S, probe_steps));
     const potato_options saved = ctx->opts;
     ctx->opts.form = POTATO_FORM_FUSED;
     for (int b : blocks) {
