@@ -288,7 +288,9 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
  *   potato_pipe_sync(pipe): blocks until all enqueued uploads and
  *     snapshots are done.
  *   potato_pipe_destroy(pipe): synchronises the pipe's streams and the run
- *     stream, then frees the pipe.  NULL is a no-op.
+ *     stream, then frees the pipe.  NULL is a no-op.  Destroy a pipe before
+ *     its context and before the stream its runs used.
+ * A pipe is not thread-safe: one host thread drives it.
  * Errors: POTATO_EINVAL for null pointers, n_agents < 1, a run before the
  * first push, n_steps < 0, snap_every < 0, missing host_snap when a
  * snapshot is due, a run on another stream than the first run, or a
@@ -303,6 +305,18 @@ potato_status potato_pipe_run(potato_pipe* pipe, const potato_state* state, cons
 potato_status potato_pipe_wait_snapshots(potato_pipe* pipe, int64_t count);
 potato_status potato_pipe_sync(potato_pipe* pipe);
 potato_status potato_pipe_destroy(potato_pipe* pipe);
+
+/*
+ * Failure detection: adds to *count (device int64) the number of agents
+ * 0..n_agents-1 whose state holds a NaN or an infinity in the rows the
+ * context's mode integrates (closed loop: rows 0-29, open loop: rows 0-16).
+ * Agents are independent, so a non-finite agent never contaminates another
+ * (the count is the number of diverged agents, not a global flag).
+ * Errors: POTATO_EINVAL for null pointers, n_agents outside [1, 2^30] or
+ * state.ld < n_agents.
+ */
+potato_status potato_count_nonfinite(potato_ctx* ctx, const potato_state* state, int64_t n_agents, int64_t* count,
+                                     void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* potato_last_error(void);

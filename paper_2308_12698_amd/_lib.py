@@ -98,6 +98,7 @@ def load():
     L.potato_pipe_wait_snapshots.argtypes = [P, I64]
     L.potato_pipe_sync.argtypes = [P]
     L.potato_pipe_destroy.argtypes = [P]
+    L.potato_count_nonfinite.argtypes = [P, P, I64, P, P]
     L.potato_last_error.argtypes = []
     L.potato_last_error.restype = C.c_char_p
     L.potato_version.argtypes = []
@@ -106,7 +107,7 @@ def load():
                "potato_autotune", "potato_order_by_type", "potato_step_backward",
                "potato_detect_collisions", "potato_pipe_create", "potato_pipe_push",
                "potato_pipe_run", "potato_pipe_wait_snapshots", "potato_pipe_sync",
-               "potato_pipe_destroy"):
+               "potato_pipe_destroy", "potato_count_nonfinite"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L

@@ -592,6 +592,19 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_detect_collisions launch");
 }
 
+potato_status potato_count_nonfinite(potato_ctx* ctx, const potato_state* state, int64_t n_agents, int64_t* count,
+                                     void* stream) {
+    if (!ctx || !state || !state->rows || !count)
+        return fail(POTATO_EINVAL, "ctx, state, state.rows and count must be non-null");
+    if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");
+    if (state->ld < n_agents) return fail(POTATO_EINVAL, "state.ld < n_agents");
+    const int n_rows = ctx->opts.mode == POTATO_CLOSED_LOOP ? 30 : 17;
+    hipError_t e = launch_count_nonfinite(state->rows, state->ld, n_agents, n_rows,
+                                          reinterpret_cast<unsigned long long*>(count),
+                                          reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_count_nonfinite launch");
+}
+
 const char* potato_last_error(void) { return g_err.c_str(); }
 
 const char* potato_version(void) { return "potato-mi355x 0.1 (gfx950)"; }

@@ -103,6 +103,10 @@ hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types,
 
 constexpr int kOrderBlock = 256;
 
+/* Adds to *count the agents whose first n_rows rows hold a non-finite value. */
+hipError_t launch_count_nonfinite(const float* rows, int64_t ld, int64_t n, int n_rows, unsigned long long* count,
+                                  hipStream_t stream);
+
 /* Collision detection on a hashed grid (see collide.hip). */
 uint32_t collision_buckets(int64_t n);
 int64_t collision_workspace_bytes(int64_t n);

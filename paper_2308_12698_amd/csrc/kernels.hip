@@ -317,6 +317,21 @@ __global__ void __launch_bounds__(kOrderBlock) k_scatter(const uint8_t* type, in
     perm[base[(int64_t)mine * gridDim.x + blockIdx.x] + rank] = (int32_t)i;
 }
 
+/* Agents whose first n_rows state rows hold a NaN or an infinity: one
+ * count per wave (ballot), one atomic per wave. */
+__global__ void __launch_bounds__(256) k_count_nonfinite(const float* rows, int64_t ld, int64_t n, int n_rows,
+                                                         unsigned long long* count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        const uint32_t bo = (uint32_t)i << 2;
+        for (int k = 0; k < n_rows; ++k) bad |= !isfinite(elem(uniform(rows + k * ld), bo));
+    }
+    const unsigned long long mask = __ballot(bad);
+    if (mask && (threadIdx.x & (warpSize - 1)) == (unsigned)(__ffsll((long long)mask) - 1))
+        atomicAdd(count, (unsigned long long)__popcll(mask));
+}
+
 template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
 const void* kfn() {
     return reinterpret_cast<const void*>(&k_rollout<MODE, HET, GAINS, CKPT, PERM>);
@@ -374,6 +389,13 @@ hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int gr
     void* args[] = {const_cast<StepArgs*>(&a)};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)block), args,
                            rollout_lds_bytes(v, a.n_types), stream);
+}
+
+hipError_t launch_count_nonfinite(const float* rows, int64_t ld, int64_t n, int n_rows, unsigned long long* count,
+                                  hipStream_t stream) {
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(256), 0, stream, rows, ld, n, n_rows, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types, const int32_t* rank,

@@ -7,6 +7,7 @@ computes any part of the method.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 
 import torch
 
@@ -69,6 +70,12 @@ class Simulator:
         L.check(self._lib.potato_set_options(self._h, C.byref(self.opts)))
 
     def close(self):
+        # pipes use the context: they go first
+        for ref in getattr(self, "_pipes", []):
+            pipe = ref()
+            if pipe is not None:
+                pipe.close()
+        self._pipes = []
         if getattr(self, "_h", None):
             self._lib.potato_destroy(self._h)
             self._h = None
@@ -213,6 +220,19 @@ class Simulator:
                                                    _stream_handle(stream)))
         return alive
 
+    def count_nonfinite(self, state, *, n_agents=None, count=None, stream=None):
+        """Device int64 scalar: agents whose integrated rows hold NaN or Inf
+        (added to ``count`` when given)."""
+        n = int(n_agents if n_agents is not None else state.shape[1])
+        _check_rows("state", state, N_ROWS, n)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int64, device=state.device)
+        elif not count.is_cuda or count.dtype != torch.int64 or count.numel() < 1:
+            raise ValueError("count must be a device int64 tensor")
+        st = L.State(C.c_void_p(state.data_ptr()), state.stride(0))
+        L.check(self._lib.potato_count_nonfinite(self._h, C.byref(st), n, _ptr(count), _stream_handle(stream)))
+        return count
+
     def order_by_type(self, type_idx, stream=None):
         """Processing order grouping agents by type, longest step budget first."""
         n = type_idx.shape[0]
@@ -247,6 +267,7 @@ class Pipe:
         h = C.c_void_p()
         L.check(self._lib.potato_pipe_create(sim._h, self.n, C.byref(h)))
         self._h = h
+        sim._pipes = [r for r in getattr(sim, "_pipes", []) if r() is not None] + [weakref.ref(self)]
 
     def push(self, cmd):
         import numpy as np

@@ -136,3 +136,8 @@ def test_pipe_entry_points_reject_null_handles(lib):
     assert lib.potato_pipe_wait_snapshots(None, 0) == L.EINVAL
     assert lib.potato_pipe_sync(None) == L.EINVAL
     assert lib.potato_pipe_destroy(None) == L.OK
+
+
+def test_count_nonfinite_rejects_null_handles(lib):
+    st = L.State(None, 10)
+    assert lib.potato_count_nonfinite(None, C.byref(st), 10, None, None) == L.EINVAL

@@ -262,6 +262,38 @@ def test_budget_zero_and_nan_agents(torch_dev):
     assert np.isnan(got[:, 5]).any()
 
 
+def test_count_nonfinite_agents(torch_dev):
+    """Failure detection: the device count of diverged agents, over the rows
+    each mode integrates, before and after a rollout (NaN stays confined)."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    n = 1000 + 37
+    sw = I.config1(n=n)
+    bad = sw.state.copy()
+    bad[0, 3] = np.nan           # position
+    bad[15, 700] = np.inf        # rotor
+    bad[29, 1036] = -np.inf      # cost (last agent, ragged tail)
+    bad[35, 10] = np.nan         # a rounding-carry row: not counted ...
+    closed = Simulator(sw.types, sw.glob, mode=1)
+    st = _dev(torch, dev, bad)
+    assert int(closed.count_nonfinite(st).item()) == 3
+    closed.step(st, 200, sw.dt, wp=_dev(torch, dev, sw.wp))
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    # ... but the integrator adds it to the velocity, so agent 10 diverges too
+    assert not np.isfinite(got[:30, 10]).all()
+    c = closed.count_nonfinite(st)
+    closed.count_nonfinite(st, count=c)                 # accumulates
+    assert int(c.item()) == 8
+    finite = np.ones(n, bool)
+    finite[[3, 10, 700, 1036]] = False
+    assert np.isfinite(got[:30, finite]).all()          # nothing else is touched
+    closed.close()
+    open_loop = Simulator(sw.types, sw.glob, mode=0)
+    assert int(open_loop.count_nonfinite(_dev(torch, dev, bad)).item()) == 2   # rows 0-16 only
+    open_loop.close()
+
+
 def test_zero_steps_and_single_agent(oracle, torch_dev):
     sw = I.config1(n=1)
     assert np.array_equal(gpu_rollout(torch_dev, sw, 0), sw.state.astype(np.float64))
