@@ -9,9 +9,9 @@
  * grid-stride loop lets a launch use a persistent grid.  Optional pieces
  * are template switches so that the homogeneous path carries no per-agent
  * type or gain traffic:
- *   HET   per-agent type index; the type table is staged in LDS once per
- *         block (the paper runs one process per type, Sec. II-A; here all
- *         types share one launch);
+ *   HET   per-agent type index into the type table staged in LDS (the
+ *         paper runs one process per type, Sec. II-A; here all types share
+ *         one launch);
  *   GAINS per-agent controller gains;
  *   CKPT  checkpoints every ckpt_every steps for the adjoint;
  *   PERM  processing order (agents grouped by type).
@@ -24,12 +24,15 @@ namespace potato {
 
 namespace {
 
-/* Occupancy target of the rollout kernel in waves per SIMD (0 = compiler's
- * choice).  Fewer registers per lane buy more resident waves to hide the
- * latency of dependent FP32 chains and transcendental ops. */
+/* Launch limits read from LDS (1) or kept as kernel arguments in scalar
+ * registers (0); the two measured alike. */
 #ifndef POTATO_LIMITS_FROM_LDS
 #define POTATO_LIMITS_FROM_LDS 0
 #endif
+/* Occupancy target of the rollout kernel in waves per SIMD (0 = compiler's
+ * choice).  More resident waves hide the latency of dependent FP32 chains
+ * and transcendental ops; the closed-loop kernel fits 4 waves (121-127
+ * VGPRs) without spilling, 5 waves spill. */
 #ifndef POTATO_ROLLOUT_WAVES
 #define POTATO_ROLLOUT_WAVES 4
 #endif
@@ -193,7 +196,8 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 
 /* Reverse sweep of the checkpointed closed-loop rollout: one agent per lane
  * (grid-stride), cotangents and gain sums in registers, the recomputed
- * segment in this thread's tape column. */
+ * segment in this thread's tape column.  Two waves per SIMD: the hot loops
+ * fit 256 registers without spills (one wave leaves the tape loads exposed). */
 #ifndef POTATO_ADJOINT_WAVES
 #define POTATO_ADJOINT_WAVES 2
 #endif
