@@ -158,6 +158,37 @@ def test_open_loop_commands_and_snapshots(oracle, torch_dev):
     sim.close()
 
 
+def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(torch_dev):
+    """Eight types with step budgets in the processing order, some agents
+    dead: the pipe's global step index carries the budgets across runs, so
+    the result equals one resident rollout bit for bit."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Pipe, Simulator
+    sw = I.config3(scale=512)
+    n = sw.n
+    epoch_steps, n_epochs = 1500, 4              # budgets 1,000..8,000 end inside epochs
+    alive = torch.from_numpy((np.arange(n) % 7 != 3).astype(np.uint8)).to(dev)
+    ti = torch.from_numpy(sw.type_idx).to(dev)
+    wps = np.ascontiguousarray(sw.wp[:n_epochs])
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=500)
+    perm = sim.order_by_type(ti)
+    pipe = Pipe(sim, n)
+    st = torch.from_numpy(sw.state).to(dev)
+    for e in range(n_epochs):
+        pipe.push(wps[e])
+        pipe.run(st, epoch_steps, sw.dt, type_idx=ti, perm=perm, alive=alive)
+    pipe.sync()
+    ref = torch.from_numpy(sw.state).to(dev)
+    sim.step(ref, n_epochs * epoch_steps, sw.dt, type_idx=ti, perm=perm, alive=alive,
+             wp=torch.from_numpy(wps).to(dev), resample_every=epoch_steps)
+    torch.cuda.synchronize()
+    assert torch.equal(st, ref)
+    dead = alive.cpu().numpy() == 0
+    assert np.array_equal(st.cpu().numpy()[:, dead], sw.state[:, dead])
+    pipe.close()
+    sim.close()
+
+
 def test_pipe_rejects_invalid_use(torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd import _lib as L
