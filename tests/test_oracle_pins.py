@@ -394,3 +394,96 @@ def test_flop_count_is_positive_and_mode_dependent(oracle):
     # four derivative evaluations dominate; the controller adds a few hundred
     assert 500 < c0["flops"] < c1["flops"] < 1500
     assert c0["sqrt"] == 1 and c1["sqrt"] == 1 + 3 + 4
+
+
+# --- linearised closed-loop responses (Sec. II-B cascade; reading R11) ---------
+#
+# Small steps keep the cascade in its linear range, where the decoupled
+# vertical and yaw channels are low-order linear systems driven by the
+# discrete controller through a zero-order hold.  Each is integrated here
+# exactly (matrix exponential of the continuous part between controller
+# updates) from its own first-principles model, and the reference's
+# nonlinear RK4 rollout must follow it to within 1e-3 of the step size.
+
+def _zoh(A, B, dt):
+    from scipy.linalg import expm
+    n = A.shape[0]
+    M = np.zeros((n + 1, n + 1))
+    M[:n, :n] = A
+    M[:n, n] = B
+    E = expm(M * dt)
+    return E[:n, :n], E[:n, n]
+
+
+def test_vertical_step_follows_the_linear_cascade(oracle):
+    """Waypoint 1 mm above hover: position PID (integral updated before use,
+    D on velocity), gravity feed-forward, collective thrust through the
+    mixer, square-root rotor inversion, first-order rotor lag, thrust k_f W^2
+    and linear drag."""
+    t = exact_type()
+    dt, T, d = 1e-3, 3000, 1e-3
+    kpp, kip, kdp = I.DEFAULT_GAINS[0:3]
+    m, kf, tau, cd, Wh = t["mass"], t["k_f"], t["tau_m"], t["drag"], t["w_ref"]
+    b = 8.0 * kf * Wh / m          # d(vertical accel) / d(common rotor speed)
+    A = np.array([[0.0, 1.0, 0.0], [0.0, -cd / m, b], [0.0, 0.0, -1.0 / tau]])
+    Ad, Bd = _zoh(A, np.array([0.0, 0.0, 1.0 / tau]), dt)
+    y = np.zeros(3)                # z - z0, v_z, rotor speed - Wh
+    integ = 0.0
+    z_lin = np.empty(T)
+    for k in range(T):
+        e = d - y[0]
+        integ += e * dt
+        a = kpp * e + kip * integ - kdp * y[1]
+        u = a * m / (8.0 * kf * Wh)          # linearised sqrt(m (g + a) / (4 k_f)) - Wh
+        y = Ad @ y + Bd * u
+        z_lin[k] = y[0]
+    p0 = np.array([5.0, 5.0, 5.0])
+    s = single_state(p=p0)
+    wp = (p0 + np.array([0.0, 0.0, d])).reshape(1, 3, 1)
+    z_ref = np.empty(T)
+    for k in range(T):           # one step at a time to compare the whole path
+        s = run_closed(oracle, s, t, 1, wp=wp, step0=k)[:30]
+        z_ref[k] = s[2, 0] - p0[2]
+    assert np.abs(z_ref - z_lin).max() <= 1e-3 * d
+    assert abs(z_ref[-1] - d) < 0.2 * d          # it does converge towards the waypoint
+    assert np.abs(s[0:2, 0] - p0[0:2]).max() <= 1e-15 and np.abs(s[7:9, 0]).max() <= 1e-15
+
+
+def test_yaw_step_follows_the_linear_cascade(oracle):
+    """1 mrad of yaw with the position held: attitude PID on the error
+    quaternion, body-rate PID with D on the measured rate, I_zz alpha torque,
+    the mixer's yaw row, rotors 1 and 3 spinning up for +yaw torque, rotor
+    lag, k_m W^2 reaction torque and the Euler equation about z."""
+    t = exact_type()
+    dt, T, psi0 = 1e-3, 3000, 1e-3
+    kpa, kia, kda, kpr, kir, kdr = I.DEFAULT_GAINS[3:9]
+    Izz, km, tau, Wh = t["Izz"], t["k_m"], t["tau_m"], t["w_ref"]
+    c = 8.0 * km * Wh / Izz        # yaw acceleration per unit rotor differential
+    A = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, c], [0.0, 0.0, -1.0 / tau]])
+    Ad, Bd = _zoh(A, np.array([0.0, 0.0, 1.0 / tau]), dt)
+    y = np.array([psi0, 0.0, 0.0])  # yaw, yaw rate, differential (rotors 1, 3 up; 2, 4 down)
+    ia = ir = r_prev = 0.0
+    psi_lin = np.empty(T)
+    for k in range(T):
+        e = -y[0]                   # 2 sin(-psi / 2) to first order
+        ia += e * dt
+        wdes = kpa * e + kia * ia - kda * y[1]
+        er = wdes - y[1]
+        ir += er * dt
+        alpha = kpr * er + kir * ir - kdr * (y[1] - r_prev) / dt
+        r_prev = y[1]
+        u = Izz * alpha / (8.0 * km * Wh)
+        y = Ad @ y + Bd * u
+        psi_lin[k] = y[0]
+    p0 = np.array([1.0, 2.0, 3.0])
+    s = single_state(p=p0, q=quat_from_axis_angle((0.0, 0.0, 1.0), psi0))
+    wp = p0.reshape(1, 3, 1)
+    psi_ref = np.empty(T)
+    for k in range(T):
+        s = run_closed(oracle, s, t, 1, wp=wp, step0=k)[:30]
+        psi_ref[k] = 2.0 * math.atan2(s[9, 0], s[6, 0])
+    assert np.abs(psi_ref - psi_lin).max() <= 1e-3 * psi0
+    assert abs(psi_ref[-1]) < 0.2 * psi0
+    # the differential is the one the geometry asks for: rotors 1 and 3 together
+    assert s[13, 0] == pytest.approx(s[15, 0], rel=1e-9, abs=1e-12)
+    assert s[14, 0] == pytest.approx(s[16, 0], rel=1e-9, abs=1e-12)
