@@ -403,7 +403,8 @@ def test_flop_count_is_positive_and_mode_dependent(oracle):
 # discrete controller through a zero-order hold.  Each is integrated here
 # exactly (matrix exponential of the continuous part between controller
 # updates) from its own first-principles model, and the reference's
-# nonlinear RK4 rollout must follow it to within 1e-3 of the step size.
+# nonlinear RK4 rollout must follow it to within 2e-5 of the step size
+# (the neglected terms are second order in the step, ~1e-6 of it here).
 
 def _zoh(A, B, dt):
     from scipy.linalg import expm
@@ -444,7 +445,7 @@ def test_vertical_step_follows_the_linear_cascade(oracle):
     for k in range(T):           # one step at a time to compare the whole path
         s = run_closed(oracle, s, t, 1, wp=wp, step0=k)[:30]
         z_ref[k] = s[2, 0] - p0[2]
-    assert np.abs(z_ref - z_lin).max() <= 1e-3 * d
+    assert np.abs(z_ref - z_lin).max() <= 2e-5 * d
     assert abs(z_ref[-1] - d) < 0.2 * d          # it does converge towards the waypoint
     assert np.abs(s[0:2, 0] - p0[0:2]).max() <= 1e-15 and np.abs(s[7:9, 0]).max() <= 1e-15
 
@@ -482,8 +483,56 @@ def test_yaw_step_follows_the_linear_cascade(oracle):
     for k in range(T):
         s = run_closed(oracle, s, t, 1, wp=wp, step0=k)[:30]
         psi_ref[k] = 2.0 * math.atan2(s[9, 0], s[6, 0])
-    assert np.abs(psi_ref - psi_lin).max() <= 1e-3 * psi0
+    assert np.abs(psi_ref - psi_lin).max() <= 2e-5 * psi0
     assert abs(psi_ref[-1]) < 0.2 * psi0
     # the differential is the one the geometry asks for: rotors 1 and 3 together
     assert s[13, 0] == pytest.approx(s[15, 0], rel=1e-9, abs=1e-12)
     assert s[14, 0] == pytest.approx(s[16, 0], rel=1e-9, abs=1e-12)
+
+
+def test_lateral_step_follows_the_linear_cascade(oracle):
+    """Waypoint 1 mm ahead (+x): position PID → desired tilt (the shortest
+    rotation of body z onto the commanded acceleration, atan(a_x / g) to
+    first order) → attitude PID on the error quaternion → body-rate PID →
+    I_yy alpha → the mixer's pitch row (rotors 3, 4 up, 1, 2 down) → rotor
+    lag → k_f L cos(alpha) W^2 pitch torque → tilt → horizontal thrust
+    g theta with drag."""
+    t = exact_type()
+    dt, T, d = 1e-3, 4000, 1e-3
+    kpp, kip, kdp, kpa, kia, kda, kpr, kir, kdr = I.DEFAULT_GAINS
+    m, kf, tau, cd, Wh, Iyy = t["mass"], t["k_f"], t["tau_m"], t["drag"], t["w_ref"], t["Iyy"]
+    lc = t["arm"] * math.cos(t["alpha"])
+    c = 8.0 * kf * lc * Wh / Iyy   # pitch acceleration per unit front/back rotor differential
+    A = np.zeros((5, 5))           # x, v_x, pitch, pitch rate, differential (rotors 3, 4 up)
+    A[0, 1] = 1.0
+    A[1, 1], A[1, 2] = -cd / m, G
+    A[2, 3] = 1.0
+    A[3, 4] = c
+    A[4, 4] = -1.0 / tau
+    Ad, Bd = _zoh(A, np.array([0.0, 0.0, 0.0, 0.0, 1.0 / tau]), dt)
+    y = np.zeros(5)
+    ip = ia = ir = q_prev = 0.0
+    x_lin = np.empty(T)
+    for k in range(T):
+        e = d - y[0]
+        ip += e * dt
+        ax = kpp * e + kip * ip - kdp * y[1]
+        eatt = ax / G - y[2]        # desired tilt minus tilt
+        ia += eatt * dt
+        wdes = kpa * eatt + kia * ia - kda * y[3]
+        er = wdes - y[3]
+        ir += er * dt
+        alpha = kpr * er + kir * ir - kdr * (y[3] - q_prev) / dt
+        q_prev = y[3]
+        u = Iyy * alpha / (8.0 * kf * lc * Wh)
+        y = Ad @ y + Bd * u
+        x_lin[k] = y[0]
+    p0 = np.array([-3.0, 4.0, 6.0])
+    s = single_state(p=p0)
+    wp = (p0 + np.array([d, 0.0, 0.0])).reshape(1, 3, 1)
+    x_ref = np.empty(T)
+    for k in range(T):
+        s = run_closed(oracle, s, t, 1, wp=wp, step0=k)[:30]
+        x_ref[k] = s[0, 0] - p0[0]
+    assert np.abs(x_ref - x_lin).max() <= 2e-5 * d
+    assert abs(x_ref[-1] - d) < 0.2 * d
