@@ -70,8 +70,8 @@ struct AdjArgs {
     const float* grad_final;     /* [30][ld] */
     float* grad_x0;              /* [30][ld] */
     float* grad_gains;           /* [9][ld] or null */
-    float* tape;                 /* [K][kTapeRows][tape_ld], one column per thread of the grid */
-    int64_t tape_ld;
+    float* tape;                 /* [K][grid threads / 64][kTapeRows][64]: per step, one block per wave */
+    int64_t tape_ld;             /* threads in the grid (a multiple of 64) */
     int32_t n_types;
     const TypeConst* table;
     const uint8_t* alive;

@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 
 /* Reverse sweep of the checkpointed closed-loop rollout: one agent per lane
  * (grid-stride), cotangents and gain sums in registers, the recomputed
- * segment in this thread's tape column.  Two waves per SIMD: the hot loops
+ * segment in this wave's tape blocks.  Two waves per SIMD: the hot loops
  * fit 256 registers without spills (one wave leaves the tape loads exposed). */
 #ifndef POTATO_ADJOINT_WAVES
 #define POTATO_ADJOINT_WAVES 2
@@ -217,7 +217,11 @@ __global__ void __launch_bounds__(kAdjBlock)
     const int64_t ld = A.ld;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const uint32_t tbo = (uint32_t)tid << 2;      /* this thread's tape column */
+    /* this wave's tape blocks: kTapeRows x 64 floats per step, waves side by side */
+    const int64_t wave = tid >> 6;
+    const uint32_t lb = (uint32_t)(tid & 63) << 2;
+    float* const tape = A.tape + wave * (int64_t)kTapeRows * 64;
+    const int64_t tape_step = (stride >> 6) * (int64_t)kTapeRows * 64;
     const int n_seg_all = (A.n_steps + A.K - 1) / A.K;
     for (int64_t j = tid; j < A.n; j += stride) {
         const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(kAdjBlock)
         float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (steps > 0)
             agent_backward(c, lim, g, A.ckpt, ld, bo, A.K, n_seg_all, steps, A.step0, A.wp, A.cmd_ld,
-                           A.n_epochs, A.resample, A.tape, A.tape_ld, tbo, lam, gk);
+                           A.n_epochs, A.resample, tape, tape_step, lb, lam, gk);
         store_adj(A.grad_x0, ld, bo, lam);
         if (A.grad_gains) {
 #pragma unroll

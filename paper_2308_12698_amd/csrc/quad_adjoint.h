@@ -275,10 +275,10 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const bool in_f = !(f[i] < 0.0f) && !(f[i] > c.f_max);
-        const float fi = clampf_(f[i], 0.0f, c.f_max);
-        const float W = sqrt_fast(fi * c.inv_kf);
-        /* d W / d f = inv_kf / (2 W), zero when clamped or W == 0 */
-        lf_scale[i] = (in_f && W > 0.0f) ? 0.5f * c.inv_kf / W : 0.0f;
+        const float w2 = clampf_(f[i], 0.0f, c.f_max) * c.inv_kf;
+        /* W = sqrt(w2): d W / d f = inv_kf / (2 W) = inv_kf rsq(w2) / 2, zero
+         * when clamped or W == 0 */
+        lf_scale[i] = (in_f && w2 > 0.0f) ? 0.5f * c.inv_kf * rsq(w2) : 0.0f;
     }
 
     /* ---------------- reverse: controller ---------------- */
@@ -448,13 +448,46 @@ __device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, 
     row(29) = l.J;
 }
 
+/* Tape slots: one block of kTapeRows x 64 floats per wave and step, a row
+ * being 64 consecutive floats (one per lane).  `slot` is the block's base,
+ * the same for the whole wave, so row k is an immediate offset of k x 256
+ * bytes from a scalar base, and `lb` is the lane's byte offset (lane x 4). */
+__device__ __forceinline__ void store_tape(float* slot, uint32_t lb, const Agent& a) {
+    auto row = [&](int k) -> float& { return elem(slot + k * 64, lb); };
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k];
+        row(17 + k) = a.ip[k]; row(20 + k) = a.ia[k];
+        row(23 + k) = a.ir[k]; row(26 + k) = a.wprev[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { row(6 + k) = a.q[k]; row(13 + k) = a.d[k]; }
+    row(29) = a.J;
+}
+
+__device__ __forceinline__ void load_tape(const float* slot, uint32_t lb, Agent& a) {
+    auto row = [&](int k) { return elem(slot + k * 64, lb); };
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k);
+        a.ip[k] = row(17 + k); a.ia[k] = row(20 + k);
+        a.ir[k] = row(23 + k); a.wprev[k] = row(26 + k);
+        a.p_lo[k] = a.v_lo[k] = a.ip_lo[k] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { a.q[k] = row(6 + k); a.d[k] = row(13 + k); }
+    a.J = row(29);
+    a.J_lo = 0.0f;
+}
+
 /*
  * Reverse sweep of one agent's closed-loop rollout of `steps` steps from
  * global step step0.  Checkpoint slot s (40 rows of stride ld, this agent's
  * column at byte offset bo) holds the state before call-relative step s*K.
  * Each segment is recomputed forward from its checkpoint with the
- * step-start states written to this thread's tape column (K slots of 30
- * rows of stride tape_ld, byte offset tbo), then reversed step by step.
+ * step-start states written to this wave's tape blocks (`tape` is the
+ * wave's block of step 0, consecutive steps tape_step floats apart; lane
+ * byte offset lb), then reversed step by step.
  * lam: cotangent of the final state on entry, of the initial state on
  * return; gk accumulates the gain cotangents.
  *
@@ -471,7 +504,7 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
                                                const float* ckpt, int64_t ld, uint32_t bo, int K,
                                                int n_seg_all, int steps, int64_t step0, const float* wp,
                                                int64_t cmd_ld, int n_epochs, int resample, float* tape,
-                                               int64_t tape_ld, uint32_t tbo, AgentAdj& lam, float gk[9]) {
+                                               int64_t tape_step, uint32_t lb, AgentAdj& lam, float gk[9]) {
     const int n_seg = (steps + K - 1) / K;
     /* the waypoint is reloaded only when the epoch changes */
     int64_t cur_ep = -1;
@@ -492,7 +525,7 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         Agent a;
         load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
         for (int s = 0; s < len; ++s) {
-            store_phys_rows(tape + (int64_t)s * kTapeRows * tape_ld, tape_ld, tbo, a);
+            store_tape(uniform(tape + (int64_t)s * tape_step), lb, a);
             float dc[4];
             use_step(step0 + k_begin + s);
             controller(c, L, g, a, wpv, dc);
@@ -501,7 +534,7 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         for (int s = K - 1; s >= 0; --s) {
             if (s >= len) continue;
             Agent x;
-            load_rows(tape + (int64_t)s * kTapeRows * tape_ld, tape_ld, tbo, x, false);
+            load_tape(uniform(tape + (int64_t)s * tape_step), lb, x);
             use_step(step0 + k_begin + s);
             step_vjp(c, L, g, x, wpv, lam, gk);
         }
