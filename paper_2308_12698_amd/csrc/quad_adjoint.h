@@ -450,10 +450,20 @@ __device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, 
 
 /* Tape slots: one block of kTapeRows x 64 floats per wave and step, a row
  * being 64 consecutive floats (one per lane).  `slot` is the block's base,
- * the same for the whole wave, so row k is an immediate offset of k x 256
- * bytes from a scalar base, and `lb` is the lane's byte offset (lane x 4). */
+ * the same for the whole wave; rows 0-15 and 16-29 are addressed from two
+ * scalar bases at immediate offsets (k x 256 bytes, within the 4 KiB range
+ * of the instruction's offset field), and `lb` is the lane's byte offset. */
+template <typename T>
+struct TapeRows {
+    T* lo;
+    T* hi;
+    __device__ __forceinline__ explicit TapeRows(T* slot) : lo(uniform(slot)), hi(uniform(slot + 16 * 64)) {}
+    __device__ __forceinline__ T* row(int k) const { return k < 16 ? lo + k * 64 : hi + (k - 16) * 64; }
+};
+
 __device__ __forceinline__ void store_tape(float* slot, uint32_t lb, const Agent& a) {
-    auto row = [&](int k) -> float& { return elem(slot + k * 64, lb); };
+    const TapeRows<float> t(slot);
+    auto row = [&](int k) -> float& { return elem(t.row(k), lb); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k];
@@ -466,7 +476,8 @@ __device__ __forceinline__ void store_tape(float* slot, uint32_t lb, const Agent
 }
 
 __device__ __forceinline__ void load_tape(const float* slot, uint32_t lb, Agent& a) {
-    auto row = [&](int k) { return elem(slot + k * 64, lb); };
+    const TapeRows<const float> t(slot);
+    auto row = [&](int k) { return elem(t.row(k), lb); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k);
@@ -506,12 +517,15 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
                                                int64_t cmd_ld, int n_epochs, int resample, float* tape,
                                                int64_t tape_step, uint32_t lb, AgentAdj& lam, float gk[9]) {
     const int n_seg = (steps + K - 1) / K;
-    /* the waypoint is reloaded only when the epoch changes */
+    /* Waypoint epochs: global step k uses epoch min(k / resample, n_epochs - 1).
+     * The epoch is divided out once per sweep of a segment and then tracked
+     * across its boundaries, and the waypoint is reloaded only when the
+     * (clamped) epoch changes. */
+    const int64_t period = resample > 0 ? resample : INT64_MAX;
     int64_t cur_ep = -1;
     float wpv[3] = {0.0f, 0.0f, 0.0f};
-    auto use_step = [&](int64_t k) {
-        int64_t ep = resample > 0 ? k / resample : 0;
-        ep = ep < n_epochs - 1 ? ep : (int64_t)n_epochs - 1;
+    auto use_epoch = [&](int64_t e) {
+        const int64_t ep = e < n_epochs - 1 ? e : (int64_t)n_epochs - 1;
         if (ep != cur_ep) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) wpv[i] = elem(uniform(wp + (ep * 3 + i) * cmd_ld), bo);
@@ -522,20 +536,28 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         if (seg >= n_seg) continue;
         const int k_begin = seg * K;
         const int len = steps - k_begin < K ? steps - k_begin : K;
+        const int64_t k0 = step0 + k_begin;        /* global index of the segment's first step */
         Agent a;
         load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
+        int64_t e = resample > 0 ? k0 / resample : 0;
+        int64_t next = resample > 0 ? (e + 1) * period : INT64_MAX;   /* first step of epoch e + 1 */
         for (int s = 0; s < len; ++s) {
-            store_tape(uniform(tape + (int64_t)s * tape_step), lb, a);
+            store_tape(tape + (int64_t)s * tape_step, lb, a);
+            if (k0 + s == next) { ++e; next += period; }
+            use_epoch(e);
             float dc[4];
-            use_step(step0 + k_begin + s);
             controller(c, L, g, a, wpv, dc);
             rk4_step(c, L, a, dc);
         }
+        /* reverse: start from the epoch of the segment's last step */
+        e = resample > 0 ? (k0 + len - 1) / resample : 0;
+        int64_t first = resample > 0 ? e * period : INT64_MIN;         /* first step of epoch e */
         for (int s = K - 1; s >= 0; --s) {
             if (s >= len) continue;
+            if (k0 + s < first) { --e; first -= period; }
             Agent x;
-            load_tape(uniform(tape + (int64_t)s * tape_step), lb, x);
-            use_step(step0 + k_begin + s);
+            load_tape(tape + (int64_t)s * tape_step, lb, x);
+            use_epoch(e);
             step_vjp(c, L, g, x, wpv, lam, gk);
         }
     }
