@@ -330,9 +330,18 @@ def fwd_bwd_form(torch, dev, timed, N):
         ms_f = timed(fwd)
         ms_fb = timed(lambda: (fwd(), bwd()))
         key = "fwd_bwd" if n_agents == N else "fwd_bwd_65536"
+        # backward pass roofline: its algorithmic HBM traffic is the recomputation
+        # tape (30 rows written and read per agent-step) plus one 40-row
+        # checkpoint read per segment
+        ms_b = ms_fb - ms_f
+        bwd_bytes = dw.n * dw.n_steps * (2 * 30 * 4 + 40 * 4 / K)
+        gbs = bwd_bytes / (ms_b * 1e-3) / 1e9
         res[key] = {"agent_steps_per_s": dw.n * dw.n_steps / (ms_fb * 1e-3), "n_agents": dw.n,
                     "sim_steps": dw.n_steps, "ckpt_every": K, "fwd_ms": ms_f,
-                    "fwd_bwd_ms": ms_fb, "bwd_ms": ms_fb - ms_f}
+                    "fwd_bwd_ms": ms_fb, "bwd_ms": ms_b,
+                    "bwd_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                     "bytes_per_agent_step": round(2 * 30 * 4 + 40 * 4 / K, 1)}}
         log(f"{key}: {res[key]['agent_steps_per_s']:.4e} agent-steps/s (fwd {ms_f:.2f} ms, "
             f"fwd+bwd {ms_fb:.2f} ms)")
         dsim.close()
