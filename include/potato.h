@@ -276,12 +276,18 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
  *     the most recently pushed commands (held for the whole run; the
  *     stream waits for their upload).  The
  *     pipe keeps the global step index across runs (step budgets).  With
- *     snap_every > 0, after every snap_every steps positions (rows 0-2)
- *     are copied to a device slot and from there, on the egress stream, to
- *     host_snap[k] (float[n_steps / snap_every][3][n_agents], host memory;
- *     pinned for the copy to overlap the next steps).  Snapshot k of the
- *     run holds the positions after step (k+1)*snap_every of the run.
- *     Every run of a pipe must use the same stream.
+ *     snap_every > 0, after every snap_every steps the positions (rows
+ *     0-2) go to host_snap[k] (float[n_steps / snap_every][3][n_agents],
+ *     host memory).  Pinned memory from hipHostMalloc (what torch's
+ *     pin_memory gives) is written directly by the last launch before the
+ *     snapshot, as its waves finish, so the transfer overlaps the rest of
+ *     that launch; any other host memory goes through a device slot and a
+ *     download on the egress stream.  Snapshot k of the run holds the
+ *     positions after step (k+1)*snap_every of the run.  Every run of a
+ *     pipe must use the same stream.
+ *   potato_pipe_stats(pipe, snapshots, direct): snapshots enqueued since
+ *     creation, and how many of them were written directly to pinned host
+ *     memory.
  *   potato_pipe_wait_snapshots(pipe, count): blocks until the first
  *     `count` snapshots taken by the pipe since its creation (counted over
  *     all runs) are in host memory.
@@ -293,7 +299,8 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
  * A pipe is not thread-safe: one host thread drives it.
  * Errors: POTATO_EINVAL for null pointers, n_agents < 1, a run before the
  * first push, n_steps < 0, snap_every < 0, missing host_snap when a
- * snapshot is due, a run on another stream than the first run, or a
+ * snapshot is due, a pinned host_snap whose allocation ends before the
+ * snapshots due, a run on another stream than the first run, or a
  * context whose mode changed since the pipe was created; the errors of
  * potato_step otherwise.  After a POTATO_EHIP the pipe must be destroyed.
  */
@@ -304,6 +311,7 @@ potato_status potato_pipe_run(potato_pipe* pipe, const potato_state* state, cons
                               float dt, int32_t n_steps, int32_t snap_every, float* host_snap, void* stream);
 potato_status potato_pipe_wait_snapshots(potato_pipe* pipe, int64_t count);
 potato_status potato_pipe_sync(potato_pipe* pipe);
+potato_status potato_pipe_stats(const potato_pipe* pipe, int64_t* snapshots, int64_t* direct);
 potato_status potato_pipe_destroy(potato_pipe* pipe);
 
 /*

@@ -97,6 +97,7 @@ def load():
     L.potato_pipe_run.argtypes = [P, P, P, F, I32, I32, P, P]
     L.potato_pipe_wait_snapshots.argtypes = [P, I64]
     L.potato_pipe_sync.argtypes = [P]
+    L.potato_pipe_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64)]
     L.potato_pipe_destroy.argtypes = [P]
     L.potato_count_nonfinite.argtypes = [P, P, I64, P, P]
     L.potato_last_error.argtypes = []
@@ -107,7 +108,7 @@ def load():
                "potato_autotune", "potato_order_by_type", "potato_step_backward",
                "potato_detect_collisions", "potato_pipe_create", "potato_pipe_push",
                "potato_pipe_run", "potato_pipe_wait_snapshots", "potato_pipe_sync",
-               "potato_pipe_destroy", "potato_count_nonfinite"):
+               "potato_pipe_stats", "potato_pipe_destroy", "potato_count_nonfinite"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L

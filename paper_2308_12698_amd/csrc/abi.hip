@@ -220,6 +220,7 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     a.ckpt = ckpt; a.ckpt_every = ckpt_every > 0 ? ckpt_every : 1;
     a.n_types = ctx->n_types; a.table = ctx->d_table;
     a.alive = pp->alive;
+    a.snap = nullptr;
     a.lim = make_limits(ctx->limits, dt);
     if (!P.v.het) a.n_types = 1;      /* homogeneous launch: only type 0 is staged */
 
@@ -241,12 +242,15 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     return P;
 }
 
-hipError_t enqueue(const Plan& P, int32_t n_steps, hipStream_t s) {
+/* `snap` (device view of mapped host memory, [3][n], or null) receives every
+ * agent's position from the last launch. */
+hipError_t enqueue(const Plan& P, int32_t n_steps, hipStream_t s, float* snap = nullptr) {
     StepArgs a = P.a;
     for (int32_t k0 = 0; k0 < n_steps; k0 += P.steps) {
         a.k0 = k0;
         a.step0 = P.a.step0 + k0;
         a.n_steps = std::min(P.steps, n_steps - k0);
+        a.snap = k0 + a.n_steps == n_steps ? snap : nullptr;
         hipError_t e = launch_rollout(P.v, a, P.block, P.grid, s);
         if (e != hipSuccess) return e;
     }
@@ -284,13 +288,13 @@ int ctx_device(const potato_ctx* ctx) { return ctx->device; }
 
 potato_status step_eager(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                          const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
-                         hipStream_t stream) {
+                         hipStream_t stream, float* snap) {
     potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, n_steps, nullptr, 0);
     if (s != POTATO_OK) return s;
     if (n_steps == 0) return POTATO_OK;
     std::lock_guard<std::mutex> g(ctx->mu);
     Plan P = make_plan(ctx, state, params, cmds, dt, n_agents, nullptr, 0);
-    hipError_t e = enqueue(P, n_steps, stream);
+    hipError_t e = enqueue(P, n_steps, stream, snap);
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato step launch");
 }
 

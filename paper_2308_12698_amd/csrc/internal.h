@@ -20,9 +20,11 @@ int ctx_mode(const potato_ctx* ctx);
 int ctx_device(const potato_ctx* ctx);
 
 /* potato_step without hipGraph capture: validates, plans with the tuned
- * launch shape and enqueues the launches on `stream`. */
+ * launch shape and enqueues the launches on `stream`.  With `snap` (the
+ * device view of mapped pinned host memory holding [3][n_agents] floats)
+ * the last launch also writes every agent's position there. */
 potato_status step_eager(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                          const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
-                         hipStream_t stream);
+                         hipStream_t stream, float* snap = nullptr);
 
 }  // namespace potato

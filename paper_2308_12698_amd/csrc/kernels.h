@@ -40,6 +40,8 @@ struct StepArgs {
     int32_t n_types;
     const TypeConst* table;      /* device [n_types] */
     const uint8_t* alive;        /* [ld] or null: 0 = dead, not advanced */
+    float* snap;                 /* [3][n] device view of pinned host memory, or null: every
+                                    agent's position after this launch (not with ckpt) */
     Limits lim;
 };
 

@@ -77,15 +77,33 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
         const uint32_t bo = i << 2;
         const TypeConst& c = HET ? tab[elem(A.type, i)] : tab[0];
-        if (A.alive && !elem(A.alive, i)) continue;
+        float* const R = A.rows;
+        auto row = [&](int k) -> float& { return elem(uniform(R + k * ld), bo); };
+        /* position snapshot (rows 0-2, [3][n]) written straight to mapped host
+         * memory; never requested together with checkpoints, and left out of
+         * those variants (whose step loop has no scalar registers to spare) */
+        const bool snapshot = !CKPT && A.snap != nullptr;
+        auto snap = [&](int k) -> float& { return elem(uniform(A.snap + k * A.n), bo); };
+        /* an agent that is not advanced keeps its stored position */
+        auto snap_stored = [&]() {
+            if (snapshot) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) snap(k) = row(k);
+            }
+        };
+        if (A.alive && !elem(A.alive, i)) {
+            snap_stored();
+            continue;
+        }
 
         int64_t left = (int64_t)c.budget - A.step0;
         left = left < 0 ? 0 : left;
         const int steps = left < A.n_steps ? (int)left : A.n_steps;
-        if (steps == 0) continue;
+        if (steps == 0) {
+            snap_stored();
+            continue;
+        }
 
-        float* const R = A.rows;
-        auto row = [&](int k) -> float& { return elem(uniform(R + k * ld), bo); };
         Agent a;
 #pragma unroll
         for (int k = 0; k < 3; ++k) { a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k); }
@@ -190,6 +208,10 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
             row(36) = a.J_lo;
 #pragma unroll
             for (int k = 0; k < 3; ++k) row(37 + k) = a.ip_lo[k];
+        }
+        if (snapshot) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) snap(k) = a.p[k];
         }
     }
 }

@@ -12,11 +12,20 @@
  *           that used slot s), uploads, records "slot s ready";
  *   run     (slot of the last push): compute waits "slot ready", runs,
  *           records "slot read";
- *   snapshot j (slot t = j mod 2): compute waits "snapshot slot t free"
- *           (the download of snapshot j-2), copies rows 0-2 into slot t,
- *           records "slot t taken"; egress waits it, downloads, records
- *           "snapshot slot t free" and landed[j mod kRing].
- * Everything the pipe uses is allocated at creation.
+ *   snapshot j, direct (host_snap is pinned host memory mapped into the
+ *           device's address space): the last launch before the snapshot
+ *           writes every agent's position straight into host_snap as its
+ *           waves finish, so the PCIe writes overlap the other waves' work;
+ *           compute records "taken", egress waits it and records
+ *           landed[j mod kRing];
+ *   snapshot j, copied (any other host memory; slot t = j mod 2): compute
+ *           waits "snapshot slot t free" (the download of snapshot j-2),
+ *           copies rows 0-2 into slot t, records "slot t taken"; egress
+ *           waits it, downloads, records "snapshot slot t free" and
+ *           landed[j mod kRing].
+ * Both kinds record landed[] on the egress stream, so snapshots land in
+ * order whichever way each one went.  Everything the pipe uses is
+ * allocated at creation.
  */
 #include <hip/hip_runtime.h>
 
@@ -49,6 +58,7 @@ struct potato_pipe {
     hipEvent_t landed[kRing] = {};
     int64_t pushed = 0;
     int64_t snaps = 0;                 /* snapshots enqueued since creation */
+    int64_t direct = 0;                /* of which written straight to mapped host memory */
     int64_t step = 0;                  /* global index of the next step */
 };
 
@@ -73,6 +83,34 @@ void release(potato_pipe* p) {
 }
 
 hipError_t make_event(hipEvent_t* ev) { return hipEventCreateWithFlags(ev, hipEventDisableTiming); }
+
+/* Device view of `host` if it is pinned host memory that the device
+ * addresses at the same virtual address (ROCm maps hipHostMalloc memory
+ * so); null for pageable memory or when the allocation's extent is
+ * unknown.  *short_range is set when the allocation ends before
+ * host + bytes. */
+float* mapped_view(float* host, size_t bytes, bool* short_range) {
+    *short_range = false;
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, host) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (at.type != hipMemoryTypeHost || !at.devicePointer || at.devicePointer != at.hostPointer) return nullptr;
+    void* base = nullptr;
+    size_t size = 0;
+    if (hipPointerGetAttribute(&base, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, host) != hipSuccess ||
+        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, host) != hipSuccess || !base || !size) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base), h = reinterpret_cast<uintptr_t>(host);
+    if (h < b || h - b > size || size - (h - b) < bytes) {
+        *short_range = true;
+        return nullptr;
+    }
+    return host;
+}
 
 }  // namespace
 
@@ -170,15 +208,36 @@ potato_status potato_pipe_run(potato_pipe* p, const potato_state* state, const p
     const int32_t seg = snap_every > 0 ? snap_every : n_steps;
     const size_t row_bytes = sizeof(float) * (size_t)p->n;
     const size_t snap_bytes = 3 * row_bytes;
+    const int64_t due = snap_every > 0 ? n_steps / snap_every : 0;
+    float* view = nullptr;
+    if (due > 0) {
+        bool short_range = false;
+        view = mapped_view(host_snap, (size_t)due * snap_bytes, &short_range);
+        if (short_range)
+            return set_error(POTATO_EINVAL, "host_snap's allocation holds fewer than the %lld snapshots due",
+                             (long long)due);
+    }
     int64_t k = 0;   /* snapshot index within this run */
     for (int32_t k0 = 0; k0 < n_steps; k0 += seg) {
         const int32_t len = std::min(seg, n_steps - k0);
+        const bool snapshot = snap_every > 0 && len == snap_every;
+        float* direct = snapshot && view ? view + k * 3 * p->n : nullptr;
         cmds.step0 = p->step;
-        potato_status st = step_eager(p->ctx, state, params, &cmds, dt, p->n, len, hs);
+        potato_status st = step_eager(p->ctx, state, params, &cmds, dt, p->n, len, hs, direct);
         if (st != POTATO_OK) return st;
         p->step += len;
-        if (snap_every == 0 || len < snap_every) continue;
+        if (!snapshot) continue;
         const int t = (int)(p->snaps & 1);
+        if (direct) {
+            e = hipEventRecord(p->snap_taken[t], hs);
+            if (e == hipSuccess) e = hipStreamWaitEvent(p->egress, p->snap_taken[t], 0);
+            if (e == hipSuccess) e = hipEventRecord(p->landed[p->snaps % kRing], p->egress);
+            if (e != hipSuccess) return set_hip_error(e, "potato_pipe_run (snapshot)");
+            p->snaps += 1;
+            p->direct += 1;
+            k += 1;
+            continue;
+        }
         if (p->snap_used[t]) e = hipStreamWaitEvent(hs, p->snap_free[t], 0);
         if (e == hipSuccess)
             e = hipMemcpy2DAsync(p->d_snap[t], row_bytes, state->rows, sizeof(float) * (size_t)state->ld, row_bytes,
@@ -217,6 +276,13 @@ potato_status potato_pipe_sync(potato_pipe* p) {
     hipError_t e = hipStreamSynchronize(p->ingress);
     if (e == hipSuccess) e = hipStreamSynchronize(p->egress);
     return e == hipSuccess ? POTATO_OK : set_hip_error(e, "potato_pipe_sync");
+}
+
+potato_status potato_pipe_stats(const potato_pipe* p, int64_t* snapshots, int64_t* direct) {
+    if (!p || !snapshots || !direct) return set_error(POTATO_EINVAL, "pipe, snapshots and direct must be non-null");
+    *snapshots = p->snaps;
+    *direct = p->direct;
+    return POTATO_OK;
 }
 
 potato_status potato_pipe_destroy(potato_pipe* p) {

@@ -297,6 +297,12 @@ class Pipe:
     def sync(self):
         L.check(self._lib.potato_pipe_sync(self._h))
 
+    def stats(self):
+        """(snapshots enqueued, of which written directly to pinned host memory)."""
+        total, direct = C.c_int64(0), C.c_int64(0)
+        L.check(self._lib.potato_pipe_stats(self._h, C.byref(total), C.byref(direct)))
+        return total.value, direct.value
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.potato_pipe_destroy(self._h)

@@ -135,6 +135,8 @@ def test_pipe_entry_points_reject_null_handles(lib):
     assert lib.potato_pipe_run(None, None, None, C.c_float(1e-3), 1, 0, None, None) == L.EINVAL
     assert lib.potato_pipe_wait_snapshots(None, 0) == L.EINVAL
     assert lib.potato_pipe_sync(None) == L.EINVAL
+    a, b = C.c_int64(0), C.c_int64(0)
+    assert lib.potato_pipe_stats(None, C.byref(a), C.byref(b)) == L.EINVAL
     assert lib.potato_pipe_destroy(None) == L.OK
 
 

@@ -42,9 +42,10 @@ def decide(observed, epoch, n):
     return (observed.astype(np.float64) + r.uniform(-2.0, 2.0, size=(3, n))).astype(np.float32)
 
 
-def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld):
+def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld, pinned=True):
     """Closed loop through a pipe.  Returns (final state, waypoints [E, 3, n],
-    snapshots per epoch)."""
+    snapshots per epoch).  Pinned snapshot buffers are written by the
+    rollout kernel itself; pageable ones go through the copy path."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Pipe, Simulator
     n = sw.state.shape[1]
@@ -52,7 +53,7 @@ def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld):
     pipe = Pipe(sim, n)
     st = torch.from_numpy(padded(sw.state, ld)).to(dev)
     per = epoch_steps // snap_every
-    snaps = [torch.empty((per, 3, n), dtype=torch.float32, pin_memory=True) for _ in range(n_epochs)]
+    snaps = [torch.full((per, 3, n), -1.0, dtype=torch.float32, pin_memory=pinned) for _ in range(n_epochs)]
     wps = [sw.wp[0]]
     pipe.push(wps[0])
     for e in range(n_epochs):
@@ -69,6 +70,9 @@ def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld):
     pipe.sync()
     torch.cuda.synchronize()
     out = st.cpu().numpy()
+    total, direct = pipe.stats()
+    assert total == n_epochs * per
+    assert direct == (total if pinned else 0), (total, direct)
     pipe.close()
     sim.close()
     return out, np.stack(wps), [s.numpy().copy() for s in snaps]
@@ -100,12 +104,16 @@ def resident_replay(torch_dev, sw, wps, epoch_steps, snap_every, ld):
     return out, snaps
 
 
-@pytest.mark.parametrize("n,ld,epoch_steps,snap_every", [(3000, 3000, 250, 50), (1000, 1037, 250, 60)])
-def test_decision_loop_matches_resident_rollout_and_oracle(oracle, torch_dev, n, ld, epoch_steps, snap_every):
+@pytest.mark.parametrize("n,ld,epoch_steps,snap_every,pinned", [(3000, 3000, 250, 50, True),
+                                                                 (1000, 1037, 250, 60, True),
+                                                                 (1000, 1037, 250, 60, False)])
+def test_decision_loop_matches_resident_rollout_and_oracle(oracle, torch_dev, n, ld, epoch_steps, snap_every,
+                                                           pinned):
     sw = I.config1(n=n)
     n_epochs = 4
-    print(f"pipe closed loop n={n} ld={ld} epochs={n_epochs}x{epoch_steps} snap_every={snap_every}", flush=True)
-    got, wps, snaps = decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld)
+    print(f"pipe closed loop n={n} ld={ld} epochs={n_epochs}x{epoch_steps} snap_every={snap_every} "
+          f"pinned={pinned}", flush=True)
+    got, wps, snaps = decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld, pinned)
     ref, ref_snaps = resident_replay(torch_dev, sw, wps, epoch_steps, snap_every, ld)
     assert np.array_equal(got, ref)
     flat = [s for per_epoch in snaps for s in per_epoch]
@@ -161,30 +169,42 @@ def test_open_loop_commands_and_snapshots(oracle, torch_dev):
 def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(torch_dev):
     """Eight types with step budgets in the processing order, some agents
     dead: the pipe's global step index carries the budgets across runs, so
-    the result equals one resident rollout bit for bit."""
+    the result equals one resident rollout bit for bit.  The snapshots hold
+    every agent's position, also of the dead agents and of those past their
+    budget (which the kernel does not advance)."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Pipe, Simulator
     sw = I.config3(scale=512)
     n = sw.n
-    epoch_steps, n_epochs = 1500, 4              # budgets 1,000..8,000 end inside epochs
+    epoch_steps, n_epochs, snap_every = 1500, 4, 500   # budgets 1,000..8,000 end inside epochs
+    per = epoch_steps // snap_every
     alive = torch.from_numpy((np.arange(n) % 7 != 3).astype(np.uint8)).to(dev)
     ti = torch.from_numpy(sw.type_idx).to(dev)
     wps = np.ascontiguousarray(sw.wp[:n_epochs])
-    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=500)
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=200)
     perm = sim.order_by_type(ti)
     pipe = Pipe(sim, n)
     st = torch.from_numpy(sw.state).to(dev)
+    snaps = torch.full((n_epochs, per, 3, n), -1.0, dtype=torch.float32, pin_memory=True)
     for e in range(n_epochs):
         pipe.push(wps[e])
-        pipe.run(st, epoch_steps, sw.dt, type_idx=ti, perm=perm, alive=alive)
+        pipe.run(st, epoch_steps, sw.dt, type_idx=ti, perm=perm, alive=alive, snap_every=snap_every,
+                 snaps=snaps[e])
     pipe.sync()
+    assert pipe.stats() == (n_epochs * per, n_epochs * per)
     ref = torch.from_numpy(sw.state).to(dev)
-    sim.step(ref, n_epochs * epoch_steps, sw.dt, type_idx=ti, perm=perm, alive=alive,
-             wp=torch.from_numpy(wps).to(dev), resample_every=epoch_steps)
+    rwp = torch.from_numpy(wps).to(dev)
+    ref_snaps = []
+    for k in range(n_epochs * per):
+        sim.step(ref, snap_every, sw.dt, type_idx=ti, perm=perm, alive=alive, wp=rwp,
+                 resample_every=epoch_steps, step0=k * snap_every)
+        ref_snaps.append(ref[0:3].cpu().numpy())
     torch.cuda.synchronize()
     assert torch.equal(st, ref)
+    assert np.array_equal(snaps.numpy().reshape(-1, 3, n), np.stack(ref_snaps))
     dead = alive.cpu().numpy() == 0
     assert np.array_equal(st.cpu().numpy()[:, dead], sw.state[:, dead])
+    assert np.array_equal(snaps.numpy()[-1, -1][:, dead], sw.state[0:3, dead])
     pipe.close()
     sim.close()
 
@@ -211,6 +231,29 @@ def test_pipe_rejects_invalid_use(torch_dev):
                                None) == L.EINVAL                      # dt
     assert lib.potato_pipe_wait_snapshots(pipe._h, 1) == L.EINVAL    # none taken
     pipe.run(st, 20, sw.dt)                                           # first run: current stream
+    # a pinned buffer whose allocation is shorter than the snapshots due is
+    # refused before anything is enqueued; checked only where pinned buffers
+    # are recognised (else the copy path would be taken, which cannot know
+    # the extent)
+    ok = torch.empty((2, 3, 500), dtype=torch.float32, pin_memory=True)
+    pipe.run(st, 20, sw.dt, snap_every=10, snaps=ok)
+    pipe.sync()
+    if pipe.stats()[1] == 2:
+        hip = C.CDLL("libamdhip64.so")
+        hip.hipHostMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t, C.c_uint]
+        hip.hipHostFree.argtypes = [C.c_void_p]
+        small = C.c_void_p()
+        assert hip.hipHostMalloc(C.byref(small), 4096, 0) == 0
+        before = st.clone()
+        step_before = pipe.stats()
+        assert lib.potato_pipe_run(pipe._h, C.byref(sst), C.byref(pp), C.c_float(sw.dt), 64, 1, small,
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream)) == L.EINVAL
+        assert "fewer than" in lib.potato_last_error().decode()
+        torch.cuda.synchronize()
+        assert torch.equal(st, before) and pipe.stats() == step_before
+        assert hip.hipHostFree(small) == 0
+    else:
+        print("pinned snapshot buffers not recognised: extent check not exercised", flush=True)
     side = torch.cuda.Stream()
     with pytest.raises(L.PotatoError, match="same stream"):
         pipe.run(st, 20, sw.dt, stream=side)
