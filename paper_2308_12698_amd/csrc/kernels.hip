@@ -24,8 +24,15 @@ namespace potato {
 
 namespace {
 
-/* Launch limits read from LDS (1) or kept as kernel arguments in scalar
- * registers (0); the two measured alike. */
+/* Where the step reads the launch's limits and time-step constants from:
+ * 0 (default) keeps them as kernel arguments in scalar registers; 2 reads
+ * the three that the RK4 stages use ~50 times per step (dt, dt/2, dt/6)
+ * from the LDS copy into vector registers; 1 reads all of them from LDS
+ * (the extra vector registers then spill at 4 waves per SIMD).  A VALU
+ * instruction with a scalar-register operand issues at half the rate of one
+ * with vector operands only on gfx950 (measured: 62 against 93-107 lanes
+ * per clock per CU), but the step is latency bound at its occupancy: 2
+ * removes 53 such operands per step and measured no faster. */
 #ifndef POTATO_LIMITS_FROM_LDS
 #define POTATO_LIMITS_FROM_LDS 0
 #endif
@@ -63,8 +70,11 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
     Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
     TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw + (sizeof(Limits) + 15) / 16);
     stage_constants(A.table, A.n_types, A.lim, tab, lim_lds);
-#if POTATO_LIMITS_FROM_LDS
+#if POTATO_LIMITS_FROM_LDS == 1
     const Limits& lim = *lim_lds;
+#elif POTATO_LIMITS_FROM_LDS == 2
+    Limits lim = A.lim;
+    lim.dt = lim_lds->dt; lim.half_dt = lim_lds->half_dt; lim.dt6 = lim_lds->dt6;
 #else
     const Limits& lim = A.lim;
 #endif
@@ -223,6 +233,10 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 #ifndef POTATO_ADJOINT_WAVES
 #define POTATO_ADJOINT_WAVES 2
 #endif
+/* Limits of the adjoint: same choices as the rollout's POTATO_LIMITS_FROM_LDS. */
+#ifndef POTATO_ADJOINT_LIMITS_FROM_LDS
+#define POTATO_ADJOINT_LIMITS_FROM_LDS 0
+#endif
 
 template <bool HET, bool GAINS, bool PERM>
 __global__ void __launch_bounds__(kAdjBlock)
@@ -231,8 +245,11 @@ __global__ void __launch_bounds__(kAdjBlock)
     Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
     TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw + (sizeof(Limits) + 15) / 16);
     stage_constants(A.table, A.n_types, A.lim, tab, lim_lds);
-#if POTATO_LIMITS_FROM_LDS
+#if POTATO_ADJOINT_LIMITS_FROM_LDS == 1
     const Limits& lim = *lim_lds;
+#elif POTATO_ADJOINT_LIMITS_FROM_LDS == 2
+    Limits lim = A.lim;
+    lim.dt = lim_lds->dt; lim.half_dt = lim_lds->half_dt; lim.dt6 = lim_lds->dt6;
 #else
     const Limits& lim = A.lim;
 #endif
