@@ -47,11 +47,22 @@ __device__ __forceinline__ uint32_t cell_bucket(uint32_t sx, uint32_t sy, uint32
     return (sx | (sy << 1) | (sz << 2)) & mask;
 }
 
+/* Cell index along one axis.  The coordinate in cells is clamped to
+ * [-2^24, 2^24] before the conversion, so infinite, NaN (max/min return the
+ * other operand) and huge coordinates give a defined index and the
+ * neighbour indices +-1 cannot overflow.  Agents beyond the clamp share the
+ * edge cells, which only adds candidates; the decision is the distance
+ * test, and a NaN or infinite position never passes it. */
+__device__ __forceinline__ int32_t cell_index(float x, float inv_h) {
+    const float c = fminf(fmaxf(x * inv_h, -16777216.0f), 16777216.0f);
+    return (int32_t)floorf(c);
+}
+
 __device__ __forceinline__ void cell_of(float x, float y, float z, float inv_h, int32_t& ix, int32_t& iy,
                                         int32_t& iz) {
-    ix = (int32_t)floorf(x * inv_h);
-    iy = (int32_t)floorf(y * inv_h);
-    iz = (int32_t)floorf(z * inv_h);
+    ix = cell_index(x, inv_h);
+    iy = cell_index(y, inv_h);
+    iz = cell_index(z, inv_h);
 }
 
 __global__ void __launch_bounds__(256) k_coll_clear(int32_t* count, uint32_t m) {

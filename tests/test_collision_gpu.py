@@ -52,6 +52,38 @@ def test_detection_matches_brute_force(oracle, torch_dev, n, box):
     print(f"collisions n={n}: {ref_died} died", flush=True)
 
 
+def test_detection_degenerate_geometry(oracle, torch_dev):
+    """Coincident agents (one cell holds 1,500), pairs far from the origin,
+    huge negative coordinates, NaN and infinite positions: the same
+    decisions as the brute-force reference (a NaN or infinite position never
+    passes the distance test)."""
+    rng = np.random.default_rng(99)
+    n = 4000
+    pos = np.empty((3, n))
+    pos[:, 0:1500] = np.array([[10.0], [10.0], [10.0]])
+    base = np.stack([rng.uniform(-1e5, 1e5, 250), rng.uniform(-1e5, 1e5, 250), np.full(250, 5e4)])
+    pos[:, 1500:2000:2] = base
+    pos[:, 1501:2000:2] = base + np.array([[0.2], [0.0], [0.0]])
+    pos[:, 2000:3000] = rng.uniform(-3e6, -2.9e6, size=(3, 1000))
+    pos[:, 3000:3100] = rng.uniform(0.0, 50.0, size=(3, 100))
+    pos[0, 3000:3050] = np.nan
+    pos[1, 3050:3100] = np.nan
+    pos[:, 3100:3200] = rng.uniform(0.0, 50.0, size=(3, 100))
+    pos[2, 3100:3150] = np.inf
+    pos[0, 3150:3200] = -np.inf
+    pos[:, 3200:] = rng.uniform(0.0, 50.0, size=(3, n - 3200))
+    state = I.hover_state(pos.astype(np.float32).astype(np.float64))
+    alive = np.ones(n, np.uint8)
+    alive[::97] = 0
+    t = I.base_type()
+    got, died = gpu_detect(torch_dev, state, [t], alive)
+    ref, ref_died = oracle.detect_collisions(state, [t["radius"]], alive)
+    assert np.array_equal(got, ref) and died == ref_died
+    assert not got[0:1500][alive[0:1500] == 1].any()           # the coincident cluster
+    assert got[3000:3200][alive[3000:3200] == 1].all()          # NaN / infinite positions
+    print(f"degenerate geometry: {ref_died} died", flush=True)
+
+
 def test_detection_with_type_radii(oracle, torch_dev):
     n = 15000
     state = dense_swarm(n, (25, 25, 5), seed=7)
