@@ -115,11 +115,14 @@ typedef struct {
 
 /* Optional per-agent data (device pointers; each may be NULL):
  *   type   uint8[n_agents] type index into the context's table (NULL: all
- *          type 0).  Values >= n_types are undefined behaviour (not checked
- *          on the device).
+ *          type 0).  The device reads a value >= n_types as n_types - 1
+ *          (it does not report it; the Python binding's debug mode does).
  *   perm   int32[n_agents] processing order: lane j advances agent perm[j]
  *          (a permutation of 0..n_agents-1, e.g. from
- *          potato_order_by_type).  NULL = identity.
+ *          potato_order_by_type).  NULL = identity.  The device reads an
+ *          entry outside [0, n_agents) as n_agents - 1: nothing outside the
+ *          rows is addressed, but an order that is not a permutation leaves
+ *          agents unadvanced and races on others.
  *   gains  float[9][gains_ld] per-agent gains (NULL: the type's gains).
  *   alive  uint8[n_agents]: agents with 0 are dead and are neither advanced
  *          nor differentiated (their state and cotangent pass through);
@@ -197,8 +200,8 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
  * int32[n_agents]) lists agents grouped by type, types ordered by step
  * budget (longest first, ties by type index), agents of one type in
  * increasing index order.  Waves then hold one type and the longest
- * budgets are scheduled first.  type (device uint8[n_agents]) must be
- * < n_types.  workspace: device buffer of at least
+ * budgets are scheduled first.  type (device uint8[n_agents]): values
+ * >= n_types are read as n_types - 1.  workspace: device buffer of at least
  * potato_order_workspace_bytes(n_agents, n_types) bytes.
  */
 int64_t potato_order_workspace_bytes(int64_t n_agents, int32_t n_types);

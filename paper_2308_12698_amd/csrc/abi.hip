@@ -592,7 +592,7 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
     if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
     if (!(ctx->r_max > 0.0f)) return fail(POTATO_EINVAL, "every type has radius 0: nothing can collide");
     hipError_t e = launch_detect_collisions(state->rows, state->ld, n_agents, params ? params->type : nullptr,
-                                            ctx->d_radius, ctx->r_max, alive,
+                                            ctx->n_types, ctx->d_radius, ctx->r_max, alive,
                                             reinterpret_cast<unsigned long long*>(died), workspace,
                                             reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_detect_collisions launch");

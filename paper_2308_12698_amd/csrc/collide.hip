@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, const int
  * receives the agent id and (x, y, z, radius), so that the query reads each
  * bucket's candidates from consecutive addresses. */
 __global__ void __launch_bounds__(256) k_coll_scatter(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
-                                                      const uint8_t* type, const float* radius, const uint32_t* key,
+                                                      const uint8_t* type, int n_types, const float* radius,
+                                                      const uint32_t* key,
                                                       const int32_t* start, int32_t* count, int32_t* ids,
                                                       float4* spos) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +141,8 @@ __global__ void __launch_bounds__(256) k_coll_scatter(const float* rows, int64_t
     const uint32_t b = key[i];
     const int32_t slot = start[b] + atomicSub(&count[b], 1) - 1;
     ids[slot] = (int32_t)i;
-    spos[slot] = make_float4(rows[i], rows[ld + i], rows[2 * ld + i], radius[type ? type[i] : 0]);
+    spos[slot] = make_float4(rows[i], rows[ld + i], rows[2 * ld + i],
+                             radius[type ? type_entry(type, (uint32_t)i, n_types) : 0]);
 }
 
 /* One thread per sorted slot: consecutive lanes hold agents of the same or
@@ -203,7 +205,7 @@ int64_t collision_workspace_bytes(int64_t n) {
     return 16 * n + (m + (m + 1) + 2 * n + chunks) * 4 + 256;
 }
 
-hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type,
+hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type, int n_types,
                                     const float* radius_dev, float r_max, uint8_t* alive,
                                     unsigned long long* died, void* workspace, hipStream_t s) {
     const uint32_t m = collision_buckets(n);
@@ -222,8 +224,8 @@ hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, co
     hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(kScanBlock), 0, s, count, start, totals, m);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, s, totals, chunks, start + m);
     hipLaunchKernelGGL(k_scan_add, dim3(chunks), dim3(kScanBlock), 0, s, start, totals, m);
-    hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, type, radius_dev, key, start,
-                       count, ids, spos);
+    hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, type, n_types, radius_dev, key,
+                       start, count, ids, spos);
     hipLaunchKernelGGL(k_coll_query, dim3(nb), dim3(256), 0, s, spos, ids, start, start + m, inv_h, mask, alive,
                        died);
     return hipGetLastError();

@@ -84,9 +84,9 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         /* agent index < 2^30, so byte offsets into rows fit 32 bits.  Row
          * addresses are uniform: every active lane starts at step 0 and
          * steps together, so the epoch and checkpoint slot agree too. */
-        const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
+        const uint32_t i = PERM ? order_entry(A.perm, (uint32_t)j, A.n) : (uint32_t)j;
         const uint32_t bo = i << 2;
-        const TypeConst& c = HET ? tab[elem(A.type, i)] : tab[0];
+        const TypeConst& c = HET ? tab[type_entry(A.type, i, A.n_types)] : tab[0];
         float* const R = A.rows;
         auto row = [&](int k) -> float& { return elem(uniform(R + k * ld), bo); };
         /* position snapshot (rows 0-2, [3][n]) written straight to mapped host
@@ -263,9 +263,9 @@ __global__ void __launch_bounds__(kAdjBlock)
     const int64_t tape_step = (stride >> 6) * (int64_t)kTapeRows * 64;
     const int n_seg_all = (A.n_steps + A.K - 1) / A.K;
     for (int64_t j = tid; j < A.n; j += stride) {
-        const uint32_t i = PERM ? (uint32_t)elem(A.perm, (uint32_t)j << 2) : (uint32_t)j;
+        const uint32_t i = PERM ? order_entry(A.perm, (uint32_t)j, A.n) : (uint32_t)j;
         const uint32_t bo = i << 2;
-        const TypeConst& c = HET ? tab[elem(A.type, i)] : tab[0];
+        const TypeConst& c = HET ? tab[type_entry(A.type, i, A.n_types)] : tab[0];
         int64_t left = (int64_t)c.budget - A.step0;
         left = left < 0 ? 0 : left;
         int steps = left < A.n_steps ? (int)left : A.n_steps;
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kOrderBlock) k_block_hist(const uint8_t* type,
     for (int t = threadIdx.x; t < n_types; t += blockDim.x) h[t] = 0;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[type[i]], 1);
+    if (i < n) atomicAdd(&h[type_entry(type, (uint32_t)i, n_types)], 1);
     __syncthreads();
     for (int t = threadIdx.x; t < n_types; t += blockDim.x) counts[(int64_t)t * gridDim.x + blockIdx.x] = h[t];
 }
@@ -351,11 +351,11 @@ __global__ void __launch_bounds__(kOrderBlock) k_scan(const int32_t* counts, int
         for (int b = threadIdx.x; b < nb; b += kOrderBlock) base[(int64_t)t * nb + b] += offset[t];
 }
 
-__global__ void __launch_bounds__(kOrderBlock) k_scatter(const uint8_t* type, int64_t n, const int32_t* base,
-                                                         int32_t* perm) {
+__global__ void __launch_bounds__(kOrderBlock) k_scatter(const uint8_t* type, int64_t n, int n_types,
+                                                         const int32_t* base, int32_t* perm) {
     __shared__ uint8_t ty[kOrderBlock];
     const int64_t i = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    const uint8_t mine = i < n ? type[i] : 0;
+    const uint8_t mine = i < n ? (uint8_t)type_entry(type, (uint32_t)i, n_types) : 0;
     ty[threadIdx.x] = mine;
     __syncthreads();
     if (i >= n) return;
@@ -451,7 +451,7 @@ hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types, con
     const int nb = (int)((n + kOrderBlock - 1) / kOrderBlock);
     hipLaunchKernelGGL(k_block_hist, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, block_counts);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kOrderBlock), 0, stream, block_counts, nb, n_types, rank, block_base);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, block_base, perm);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, block_base, perm);
     return hipGetLastError();
 }
 

@@ -104,6 +104,23 @@ __device__ __forceinline__ T* uniform(T* p) {
     return (T*)(gchar*)(((uint64_t)hi << 32) | lo);
 }
 
+/* Type index of agent i, clamped to the table: an index >= n_types reads
+ * as the last type, so a bad index never addresses past the table. */
+__device__ __forceinline__ uint32_t type_entry(const uint8_t* type, uint32_t i, int n_types) {
+    const uint32_t t = type[i];
+    const uint32_t last = (uint32_t)(n_types - 1);
+    return t < last ? t : last;
+}
+
+/* Entry j of a processing order over n agents, clamped to [0, n): an entry
+ * outside the range (a caller's order that is not a permutation) reads as
+ * the last agent, so no lane addresses past the state rows. */
+__device__ __forceinline__ uint32_t order_entry(const int32_t* perm, uint32_t j, int64_t n) {
+    const uint32_t a = (uint32_t)elem(perm, j << 2);
+    const uint32_t last = (uint32_t)(n - 1);
+    return a < last ? a : last;
+}
+
 /* Rows per step of the adjoint's recomputation tape: the 30 physical rows
  * of the step-start state. */
 constexpr int kTapeRows = 30;

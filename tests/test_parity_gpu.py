@@ -246,6 +246,48 @@ def test_order_by_type_is_the_stable_budget_order(torch_dev):
     assert np.array_equal(perm, expect)
 
 
+def test_out_of_range_type_and_order_entries(torch_dev):
+    """The device clamps a type index >= n_types to the last type and an
+    order entry outside [0, n) to the last agent, so bad inputs address
+    nothing outside the table and the state rows."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config3(scale=256)
+    n, steps = sw.n, 300
+    bad_types = sw.type_idx.copy()
+    bad_types[::50] = 200
+    clamped = np.minimum(bad_types, len(sw.types) - 1).astype(np.uint8)
+    sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=100)
+    wp = _pad3(torch, dev, sw.wp, n)
+    runs = {}
+    for label, ti in (("bad", bad_types), ("clamped", clamped)):
+        st = _dev(torch, dev, sw.state)
+        t = _dev(torch, dev, ti)
+        perm = sim.order_by_type(t)
+        sim.step(st, steps, sw.dt, type_idx=t, perm=perm, wp=wp, resample_every=sw.resample_every)
+        runs[label] = (st.cpu().numpy(), perm.cpu().numpy())
+    assert np.array_equal(runs["bad"][1], runs["clamped"][1])
+    assert np.array_equal(np.sort(runs["bad"][1]), np.arange(n))
+    assert np.array_equal(runs["bad"][0], runs["clamped"][0])
+    # an order that is not a permutation: entries 5 and 6 point outside [0, n)
+    perm = np.arange(n, dtype=np.int32)
+    perm[5], perm[6] = np.iinfo(np.int32).max, -3
+    t = _dev(torch, dev, clamped)
+    st = _dev(torch, dev, sw.state)
+    sim.step(st, steps, sw.dt, type_idx=t, perm=_dev(torch, dev, perm), wp=wp, resample_every=sw.resample_every)
+    ref = _dev(torch, dev, sw.state)
+    sim.step(ref, steps, sw.dt, type_idx=t, perm=_dev(torch, dev, np.arange(n, dtype=np.int32)), wp=wp,
+             resample_every=sw.resample_every)
+    torch.cuda.synchronize()
+    got, want = st.cpu().numpy(), ref.cpu().numpy()
+    sim.close()
+    keep = np.ones(n, bool)
+    keep[[5, 6, n - 1]] = False        # 5, 6: no lane; n - 1: three lanes
+    assert np.array_equal(got[:, keep], want[:, keep])
+    assert np.array_equal(got[:, [5, 6]], sw.state[:, [5, 6]])
+    assert np.isfinite(got[:30]).all()
+
+
 def test_budget_zero_and_nan_agents(torch_dev):
     sw = I.config1(n=700)
     t0 = dict(sw.types[0]); t0["budget"] = 0
