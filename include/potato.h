@@ -286,8 +286,10 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
  *     snapshot, as its waves finish, so the transfer overlaps the rest of
  *     that launch; any other host memory goes through a device slot and a
  *     download on the egress stream.  Snapshot k of the run holds the
- *     positions after step (k+1)*snap_every of the run.  Every run of a
- *     pipe must use the same stream.
+ *     positions after step (k+1)*snap_every of the run; host_snap must
+ *     stay allocated, and unread, until potato_pipe_wait_snapshots (or
+ *     potato_pipe_sync) reports the snapshot landed.  Every run of a pipe
+ *     must use the same stream.
  *   potato_pipe_stats(pipe, snapshots, direct): snapshots enqueued since
  *     creation, and how many of them were written directly to pinned host
  *     memory.
