@@ -558,8 +558,7 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
 
 int64_t potato_order_workspace_bytes(int64_t n_agents, int32_t n_types) {
     if (n_agents < 1 || n_types < 1 || n_types > POTATO_MAX_TYPES) return -1;
-    const int64_t nb = (n_agents + kOrderBlock - 1) / kOrderBlock;
-    return 2 * nb * n_types * (int64_t)sizeof(int32_t);
+    return order_workspace_words(n_agents, n_types) * (int64_t)sizeof(int32_t);
 }
 
 potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t n_agents, int32_t* perm,
@@ -568,10 +567,8 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
     if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");
     const int64_t need = potato_order_workspace_bytes(n_agents, ctx->n_types);
     if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
-    const int64_t nb = (n_agents + kOrderBlock - 1) / kOrderBlock;
-    int32_t* counts = reinterpret_cast<int32_t*>(workspace);
-    int32_t* base = counts + nb * ctx->n_types;
-    hipError_t e = launch_order_by_type(type, n_agents, ctx->n_types, ctx->d_rank, perm, counts, base,
+    hipError_t e = launch_order_by_type(type, n_agents, ctx->n_types, ctx->d_rank, perm,
+                                        reinterpret_cast<int32_t*>(workspace),
                                         reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_order_by_type");
 }

@@ -20,12 +20,12 @@
  * |coordinates| < 2^16 h (about 22 km for 0.17 m radii).
  */
 #include "kernels.h"
+#include "scan.h"
 
 namespace potato {
 
 namespace {
 
-constexpr int kScanBlock = 1024;
 
 /* Low 10 bits of v moved to every third bit position (bit interleaving for
  * a Morton / Z-order code). */
@@ -78,53 +78,6 @@ __global__ void __launch_bounds__(256) k_coll_count(const float* rows, int64_t l
     const uint32_t b = cell_bucket(spread3(ix), spread3(iy), spread3(iz), mask);
     key[i] = b;
     atomicAdd(&count[b], 1);
-}
-
-/* Exclusive scan in chunks of kScanBlock: per-chunk scan + chunk totals. */
-__global__ void __launch_bounds__(kScanBlock) k_scan_chunks(const int32_t* in, int32_t* out, int32_t* totals,
-                                                            uint32_t m) {
-    __shared__ int32_t buf[kScanBlock];
-    const uint32_t g = blockIdx.x * kScanBlock + threadIdx.x;
-    const int32_t v = g < m ? in[g] : 0;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanBlock; off <<= 1) {
-        const int32_t add = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
-        __syncthreads();
-        buf[threadIdx.x] += add;
-        __syncthreads();
-    }
-    if (g < m) out[g] = buf[threadIdx.x] - v;
-    if (threadIdx.x == kScanBlock - 1) totals[blockIdx.x] = buf[threadIdx.x];
-}
-
-/* One block: exclusive scan of the chunk totals (any count), in place;
- * the grand total goes to *grand. */
-__global__ void __launch_bounds__(kScanBlock) k_scan_totals(int32_t* totals, uint32_t n_chunks, int32_t* grand) {
-    __shared__ int32_t buf[kScanBlock];
-    int32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < n_chunks; c0 += kScanBlock) {
-        const uint32_t c = c0 + threadIdx.x;
-        const int32_t v = c < n_chunks ? totals[c] : 0;
-        buf[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < kScanBlock; off <<= 1) {
-            const int32_t add = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (c < n_chunks) totals[c] = carry + buf[threadIdx.x] - v;
-        const int32_t chunk = buf[kScanBlock - 1];
-        __syncthreads();
-        carry += chunk;
-    }
-    if (threadIdx.x == 0) *grand = carry;
-}
-
-__global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, const int32_t* totals, uint32_t m) {
-    const uint32_t g = blockIdx.x * kScanBlock + threadIdx.x;
-    if (g < m) out[g] += totals[blockIdx.x];
 }
 
 /* Counting sort of the alive agents by bucket: agent i gets a slot in its
@@ -199,7 +152,7 @@ uint32_t collision_buckets(int64_t n) {
 
 int64_t collision_workspace_bytes(int64_t n) {
     const int64_t m = collision_buckets(n);
-    const int64_t chunks = (m + kScanBlock - 1) / kScanBlock;
+    const int64_t chunks = scan_chunks(m);
     /* sorted (x, y, z, r) [n] first (16-byte aligned); count [m]; start [m+1];
      * key, ids [n]; chunk totals [chunks] */
     return 16 * n + (m + (m + 1) + 2 * n + chunks) * 4 + 256;
@@ -209,7 +162,6 @@ hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, co
                                     const float* radius_dev, float r_max, uint8_t* alive,
                                     unsigned long long* died, void* workspace, hipStream_t s) {
     const uint32_t m = collision_buckets(n);
-    const uint32_t chunks = (m + kScanBlock - 1) / kScanBlock;
     float4* spos = reinterpret_cast<float4*>(workspace);
     int32_t* count = reinterpret_cast<int32_t*>(spos + n);
     int32_t* start = count + m;
@@ -221,9 +173,7 @@ hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, co
     const unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_coll_clear, dim3((m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096), dim3(256), 0, s, count, m);
     hipLaunchKernelGGL(k_coll_count, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, inv_h, mask, count, key);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(kScanBlock), 0, s, count, start, totals, m);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, s, totals, chunks, start + m);
-    hipLaunchKernelGGL(k_scan_add, dim3(chunks), dim3(kScanBlock), 0, s, start, totals, m);
+    launch_exclusive_scan(count, start, totals, start + m, m, s);   /* grand total in start[m] */
     hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, type, n_types, radius_dev, key,
                        start, count, ids, spos);
     hipLaunchKernelGGL(k_coll_query, dim3(nb), dim3(256), 0, s, spos, ids, start, start + m, inv_h, mask, alive,

@@ -98,10 +98,12 @@ constexpr int kAdjBlock = 256;
 /* Dynamic LDS bytes the variant needs for n_types. */
 size_t rollout_lds_bytes(const Variant& v, int n_types);
 
-/* Processing order by type (see potato_order_by_type). */
+/* Processing order by type (see potato_order_by_type): workspace of
+ * order_workspace_words(n, n_types) int32 words. */
+int64_t order_workspace_words(int64_t n, int n_types);
 hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types,
                                 const int32_t* type_rank_dev, int32_t* perm,
-                                int32_t* block_counts, int32_t* block_base, hipStream_t stream);
+                                int32_t* workspace, hipStream_t stream);
 
 constexpr int kOrderBlock = 256;
 

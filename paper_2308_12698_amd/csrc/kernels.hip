@@ -19,6 +19,7 @@
  */
 #include "kernels.h"
 #include "quad_adjoint.h"
+#include "scan.h"
 
 namespace potato {
 
@@ -297,71 +298,33 @@ __global__ void __launch_bounds__(kAdjBlock)
 /* ---- processing order by type: block histograms, scan, stable scatter ---- */
 
 __global__ void __launch_bounds__(kOrderBlock) k_block_hist(const uint8_t* type, int64_t n, int n_types,
-                                                            int32_t* counts /* [T][nb] */) {
+                                                            const int32_t* rank,
+                                                            int32_t* counts /* [rank][nb] */) {
     __shared__ int32_t h[256];
     for (int t = threadIdx.x; t < n_types; t += blockDim.x) h[t] = 0;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
     if (i < n) atomicAdd(&h[type_entry(type, (uint32_t)i, n_types)], 1);
     __syncthreads();
-    for (int t = threadIdx.x; t < n_types; t += blockDim.x) counts[(int64_t)t * gridDim.x + blockIdx.x] = h[t];
+    for (int t = threadIdx.x; t < n_types; t += blockDim.x)
+        counts[(int64_t)rank[t] * gridDim.x + blockIdx.x] = h[t];
 }
 
-/* One block: exclusive scan of each type's block counts, then offsets of
- * the types in rank order (rank 0 first). */
-__global__ void __launch_bounds__(kOrderBlock) k_scan(const int32_t* counts, int nb, int n_types,
-                                                      const int32_t* rank, int32_t* base) {
-    __shared__ int32_t buf[kOrderBlock];
-    __shared__ int32_t total[256];
-    __shared__ int32_t offset[256];
-    for (int t = 0; t < n_types; ++t) {
-        int32_t carry = 0;
-        for (int b0 = 0; b0 < nb; b0 += kOrderBlock) {
-            const int b = b0 + threadIdx.x;
-            const int32_t v = b < nb ? counts[(int64_t)t * nb + b] : 0;
-            buf[threadIdx.x] = v;
-            __syncthreads();
-            for (int off = 1; off < kOrderBlock; off <<= 1) {
-                const int32_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
-                __syncthreads();
-                buf[threadIdx.x] += add;
-                __syncthreads();
-            }
-            if (b < nb) base[(int64_t)t * nb + b] = carry + buf[threadIdx.x] - v;
-            const int32_t chunk = buf[kOrderBlock - 1];
-            __syncthreads();
-            carry += chunk;
-        }
-        if (threadIdx.x == 0) total[t] = carry;
-        __syncthreads();
-    }
-    __shared__ int32_t by_rank[256];
-    for (int t = threadIdx.x; t < n_types; t += blockDim.x) by_rank[rank[t]] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int r = 0; r < n_types; ++r) {
-            const int t = by_rank[r];
-            offset[t] = run;
-            run += total[t];
-        }
-    }
-    __syncthreads();
-    for (int t = 0; t < n_types; ++t)
-        for (int b = threadIdx.x; b < nb; b += kOrderBlock) base[(int64_t)t * nb + b] += offset[t];
-}
-
+/* Stable scatter: agent i of block b, type t, goes to base[rank t][b] plus
+ * the number of earlier agents of type t in the block.  base is the
+ * exclusive prefix sum of the counts laid out rank-major, i.e. the agents of
+ * all lower-ranked types plus those of type t in earlier blocks. */
 __global__ void __launch_bounds__(kOrderBlock) k_scatter(const uint8_t* type, int64_t n, int n_types,
-                                                         const int32_t* base, int32_t* perm) {
+                                                         const int32_t* rank, const int32_t* base, int32_t* perm) {
     __shared__ uint8_t ty[kOrderBlock];
     const int64_t i = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
     const uint8_t mine = i < n ? (uint8_t)type_entry(type, (uint32_t)i, n_types) : 0;
     ty[threadIdx.x] = mine;
     __syncthreads();
     if (i >= n) return;
-    int32_t rank = 0;
-    for (int j = 0; j < (int)threadIdx.x; ++j) rank += ty[j] == mine ? 1 : 0;
-    perm[base[(int64_t)mine * gridDim.x + blockIdx.x] + rank] = (int32_t)i;
+    int32_t before = 0;
+    for (int j = 0; j < (int)threadIdx.x; ++j) before += ty[j] == mine ? 1 : 0;
+    perm[base[(int64_t)rank[mine] * gridDim.x + blockIdx.x] + before] = (int32_t)i;
 }
 
 /* Agents whose first n_rows state rows hold a NaN or an infinity: one
@@ -445,13 +408,21 @@ hipError_t launch_count_nonfinite(const float* rows, int64_t ld, int64_t n, int 
     return hipGetLastError();
 }
 
+int64_t order_workspace_words(int64_t n, int n_types) {
+    const int64_t m = ((n + kOrderBlock - 1) / kOrderBlock) * n_types;
+    return 2 * m + scan_chunks((uint32_t)m) + 1;
+}
+
 hipError_t launch_order_by_type(const uint8_t* type, int64_t n, int n_types, const int32_t* rank,
-                                int32_t* perm, int32_t* block_counts, int32_t* block_base,
-                                hipStream_t stream) {
+                                int32_t* perm, int32_t* workspace, hipStream_t stream) {
     const int nb = (int)((n + kOrderBlock - 1) / kOrderBlock);
-    hipLaunchKernelGGL(k_block_hist, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, block_counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kOrderBlock), 0, stream, block_counts, nb, n_types, rank, block_base);
-    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, block_base, perm);
+    const uint32_t m = (uint32_t)nb * (uint32_t)n_types;
+    int32_t* counts = workspace;          /* [rank][nb] */
+    int32_t* base = counts + m;           /* its exclusive prefix sum */
+    int32_t* totals = base + m;           /* scan_chunks(m) chunk totals, then the grand total */
+    hipLaunchKernelGGL(k_block_hist, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, rank, counts);
+    launch_exclusive_scan(counts, base, totals, totals + scan_chunks(m), m, stream);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kOrderBlock), 0, stream, type, n, n_types, rank, base, perm);
     return hipGetLastError();
 }
 

@@ -95,7 +95,11 @@ def test_step_rejects_null_context(lib):
 def test_order_workspace_size(lib):
     assert lib.potato_order_workspace_bytes(0, 8) == -1
     assert lib.potato_order_workspace_bytes(1000, 0) == -1
-    assert lib.potato_order_workspace_bytes(1000, 8) == 2 * math.ceil(1000 / 256) * 8 * 4
+    # block counts and their prefix sums (rank-major, 256-agent blocks), the
+    # scan's chunk totals (1,024 entries per chunk) and its grand total
+    for n, t in ((1000, 8), (1 << 20, 8), (1007616, 256)):
+        m = math.ceil(n / 256) * t
+        assert lib.potato_order_workspace_bytes(n, t) == (2 * m + math.ceil(m / 1024) + 1) * 4
 
 
 @pytest.mark.skipif(gpu_available(), reason="checks the no-device error path")
