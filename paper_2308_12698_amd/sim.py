@@ -101,12 +101,18 @@ class Simulator:
             if not type_idx.is_cuda or type_idx.dtype != torch.uint8 or type_idx.dim() != 1 \
                     or type_idx.shape[0] < n or not type_idx.is_contiguous():
                 raise ValueError("type_idx must be a contiguous device uint8 tensor of length >= n")
-            # the device does not range-check type indices; debug mode does (syncs)
+            # the device reads an index >= n_types as the last type; debug
+            # mode reports it instead (syncs)
             if self.debug and int(type_idx[:n].max().item()) >= self.n_types:
                 raise ValueError("type_idx holds an index >= n_types")
         if perm is not None:
             if not perm.is_cuda or perm.dtype != torch.int32 or perm.shape[0] < n or not perm.is_contiguous():
                 raise ValueError("perm must be a contiguous device int32 tensor of length >= n")
+            # the device clamps entries to [0, n); debug mode checks that the
+            # order is a permutation (syncs)
+            if self.debug and not torch.equal(torch.sort(perm[:n]).values,
+                                              torch.arange(n, dtype=torch.int32, device=perm.device)):
+                raise ValueError("perm is not a permutation of 0..n-1")
         _check_rows("gains", gains, 9, n)
         _check_rows("motor_cmd", motor_cmd, 4, n)
         cmd_ld = ld
