@@ -90,6 +90,8 @@ TypeConst derive(const potato_type_params& p, const potato_limits& L) {
     c.F0 = (float)F0;
     c.F0_g = (float)(F0 - (double)L.g);
     c.kf_m = (float)(kf / m);
+    c.F0_2 = 2.0f * c.F0;
+    c.kf_m2 = 2.0f * c.kf_m;
     c.kf_ls = (float)(kf * ls);
     c.kf_lc = (float)(kf * lc);
     c.km = p.k_m;
@@ -125,6 +127,8 @@ Limits make_limits(const potato_limits& L, float dt) {
     r.dt = dt;
     r.half_dt = 0.5f * dt;
     r.dt6 = dt / 6.0f;
+    r.quarter_dt = 0.5f * r.half_dt;
+    r.dt12 = 0.5f * r.dt6;
     r.inv_dt = 1.0f / dt;
     r.dt2_6 = dt * dt / 6.0f;
     return r;

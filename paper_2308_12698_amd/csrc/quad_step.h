@@ -21,7 +21,10 @@
  *     R the RK4 stability polynomial (the numbers RK4 produces);
  *   - position obeys p' = v, so RK4 gives p + dt v + dt^2/6 (a1 + a2 + a3);
  *   - divisions by mass, inertia, tau_m and dt are multiplications by
- *     reciprocals precomputed per type.
+ *     reciprocals precomputed per type;
+ *   - the quaternion rate is evaluated as q o (0, w), and its factor 1/2
+ *     rides on the RK4 step sizes (dt/4, dt/2, dt/12 instead of dt/2, dt,
+ *     dt/6), a power of two, so the results are the same bits.
  * p, v, J and the position-loop integral are updated with a carried rounding
  * error (Fast2Sum), so long runs of nearly equal increments do not drift.
  *
@@ -45,6 +48,7 @@ struct TypeConst {
     float mass, inv_m, cd_m, ncd_m;       /* m, 1/m, c_d/m, -c_d/m */
     float Ix, Iy, Iz, iIx, iIy, iIz;      /* inertia and its inverse */
     float F0, F0_g, kf_m;                 /* 4 k_f w_ref^2/m, F0 - g, k_f/m */
+    float F0_2, kf_m2;                    /* 2 F0, 2 k_f/m (exact doublings) */
     float kf_ls, kf_lc, km;               /* k_f L sin(a), k_f L cos(a), k_m */
     float ax, ay, az;                     /* k_f L sin(a)/Ixx, k_f L cos(a)/Iyy, k_m/Izz */
     float gx, gy, gz;                     /* (Izz-Iyy)/Ixx, (Ixx-Izz)/Iyy, (Iyy-Ixx)/Izz */
@@ -61,6 +65,7 @@ struct TypeConst {
 struct Limits {
     float g, r_sat, r_sat2, ipos_max, iatt_max, irate_max, az_min;
     float dt, half_dt, dt6, inv_dt, dt2_6;   /* dt, dt/2, dt/6, 1/dt, dt^2/6 */
+    float quarter_dt, dt12;                  /* half_dt/2, dt6/2 (exact halvings) */
 };
 
 struct Gains {
@@ -154,8 +159,10 @@ __device__ __forceinline__ void body_z(const float q[4], float bz[3]) {
     bz[2] = POTATO_FMA(-2.0f, POTATO_FMA(q[1], q[1], q[2] * q[2]), 1.0f);
 }
 
-/* Rates of v, q, w at rotor deviations d (eqs. 2, 3, qd2-qd4).  Returns
- * sum_i s_i (collective thrust and cost rate follow from it). */
+/* Rates of v and w at rotor deviations d (eqs. 2, 3, qd2, qd4), and
+ * dq = q o (0, w), twice the quaternion rate of eq. (qd3): the factor 1/2
+ * is carried by the RK4 step sizes instead (exactly, as a power of two).
+ * Returns sum_i s_i (collective thrust and cost rate follow from it). */
 __device__ __forceinline__ float rates(const TypeConst& c, const float v[3], const float q[4],
                                        const float w[3], const float d[4], float dv[3], float dq[4],
                                        float dw[3]) {
@@ -168,19 +175,18 @@ __device__ __forceinline__ float rates(const TypeConst& c, const float v[3], con
     const float P01 = s[0] + s[1], P23 = s[2] + s[3];
     const float ssum = P01 + P23;
     /* eq. (qd2) + drag: (f_c/m) R(q) z - (c_d/m) v - g z */
-    const float ftm2 = 2.0f * POTATO_FMA(c.kf_m, ssum, c.F0);
+    const float ftm2 = POTATO_FMA(c.kf_m2, ssum, c.F0_2);
     const float bx2 = POTATO_FMA(q[0], q[2], q[1] * q[3]);
     const float by2 = POTATO_FMA(q[2], q[3], -(q[0] * q[1]));
     const float x2y2 = POTATO_FMA(q[1], q[1], q[2] * q[2]);
     dv[0] = POTATO_FMA(ftm2, bx2, c.ncd_m * v[0]);
     dv[1] = POTATO_FMA(ftm2, by2, c.ncd_m * v[1]);
     dv[2] = POTATO_FMA(c.ncd_m, v[2], POTATO_FMA(-ftm2, x2y2, POTATO_FMA(c.kf_m, ssum, c.F0_g)));
-    /* eq. (qd3): q' = 1/2 q o (0, w) */
-    const float h0 = 0.5f * w[0], h1 = 0.5f * w[1], h2 = 0.5f * w[2];
-    dq[0] = -POTATO_FMA(q[3], h2, POTATO_FMA(q[2], h1, q[1] * h0));
-    dq[1] = POTATO_FMA(-q[3], h1, POTATO_FMA(q[2], h2, q[0] * h0));
-    dq[2] = POTATO_FMA(-q[1], h2, POTATO_FMA(q[3], h0, q[0] * h1));
-    dq[3] = POTATO_FMA(-q[2], h0, POTATO_FMA(q[1], h1, q[0] * h2));
+    /* eq. (qd3) without its factor 1/2: q o (0, w) */
+    dq[0] = -POTATO_FMA(q[3], w[2], POTATO_FMA(q[2], w[1], q[1] * w[0]));
+    dq[1] = POTATO_FMA(-q[3], w[1], POTATO_FMA(q[2], w[2], q[0] * w[0]));
+    dq[2] = POTATO_FMA(-q[1], w[2], POTATO_FMA(q[3], w[0], q[0] * w[1]));
+    dq[3] = POTATO_FMA(-q[2], w[0], POTATO_FMA(q[1], w[1], q[0] * w[2]));
     /* eq. (3) torques and eq. (qd4): w' = I^-1 (tau - w x I w) */
     dw[0] = POTATO_FMA(-c.gx, w[1] * w[2], c.ax * (A + B));
     dw[1] = POTATO_FMA(-c.gy, w[2] * w[0], c.ay * (P23 - P01));
@@ -196,6 +202,8 @@ __device__ __forceinline__ void derivative(const TypeConst& c, const float v[3],
                                            float& dJ) {
 #pragma clang fp contract(off)
     const float ssum = rates(c, v, q, w, d, dv, dq, dw);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dq[i] *= 0.5f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) dd[i] = (dc[i] - d[i]) * c.inv_tau;
     dJ = c.four_w2 + ssum;
@@ -311,7 +319,7 @@ __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Ag
         sw[i] = POTATO_FMA(L.half_dt, kw[i], a.w[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.half_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c2, dc[i]); }
+    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.quarter_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c2, dc[i]); }
     ss = rates(c, sv, sq, sw, sd, kv, kq, kw);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -329,7 +337,7 @@ __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Ag
         sw[i] = POTATO_FMA(L.half_dt, kw[i], a.w[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.half_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c3, dc[i]); }
+    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.quarter_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c3, dc[i]); }
     ss = rates(c, sv, sq, sw, sd, kv, kq, kw);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -347,11 +355,12 @@ __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Ag
         sw[i] = POTATO_FMA(L.dt, kw[i], a.w[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c4, dc[i]); }
+    for (int i = 0; i < 4; ++i) { sq[i] = POTATO_FMA(L.half_dt, kq[i], a.q[i]); sd[i] = POTATO_FMA(e[i], c4, dc[i]); }
     ss = rates(c, sv, sq, sw, sd, kv, kq, kw);
     ass += ss;
 
-    /* combine: p with dt v + dt^2/6 (a1 + a2 + a3), the rest dt/6 (k1 + 2k2 + 2k3 + k4) */
+    /* combine: p with dt v + dt^2/6 (a1 + a2 + a3), the rest dt/6 (k1 + 2k2 + 2k3 + k4)
+     * (dt/12 for q, whose stage rates are doubled) */
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         add_carry(a.p[i], a.p_lo[i], POTATO_FMA(L.dt2_6, A3[i], L.dt * a.v[i]));
@@ -360,7 +369,7 @@ __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Ag
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        a.q[i] = POTATO_FMA(L.dt6, aq[i] + kq[i], a.q[i]);
+        a.q[i] = POTATO_FMA(L.dt12, aq[i] + kq[i], a.q[i]);
         a.d[i] = POTATO_FMA(e[i], cR, dc[i]);
     }
     add_carry(a.J, a.J_lo, POTATO_FMA(L.dt6, ass, L.dt * c.four_w2));
