@@ -148,6 +148,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
             g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
                       c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
         }
+        g.kdr_dt = g.kdr * lim.inv_dt;
 
         float dc[4];
         float wp[3];
@@ -281,6 +282,7 @@ __global__ void __launch_bounds__(kAdjBlock)
             g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
                       c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
         }
+        g.kdr_dt = g.kdr * lim.inv_dt;
         AgentAdj lam;
         load_adj(A.grad_final, ld, bo, lam);
         float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};

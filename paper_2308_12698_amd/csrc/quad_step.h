@@ -70,6 +70,7 @@ struct Limits {
 
 struct Gains {
     float kpp, kip, kdp, kpa, kia, kda, kpr, kir, kdr;
+    float kdr_dt;                         /* kdr / dt, set once per agent and launch */
 };
 
 /* 17 integrated rows + running cost, the controller memory, and the
@@ -263,8 +264,7 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
         /* body-rate loop, derivative on the measured rate */
         const float erate = wdes - a.w[i];
         a.ir[i] = clampf_(POTATO_FMA(erate, L.dt, a.ir[i]), -L.irate_max, L.irate_max);
-        const float dwr = (a.w[i] - a.wprev[i]) * L.inv_dt;
-        alpha[i] = POTATO_FMA(-k.kdr, dwr, POTATO_FMA(k.kir, a.ir[i], k.kpr * erate));
+        alpha[i] = POTATO_FMA(-k.kdr_dt, a.w[i] - a.wprev[i], POTATO_FMA(k.kir, a.ir[i], k.kpr * erate));
         a.wprev[i] = a.w[i];
     }
     /* torque for the desired angular acceleration, eq. (qd4) inverted */
