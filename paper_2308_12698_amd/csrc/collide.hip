@@ -122,31 +122,68 @@ __global__ void __launch_bounds__(256) k_coll_query(const float4* spos, const in
         lo[c] = start[b];
         hi[c] = start[b + 1];
     }
+    /* The decision for one candidate j: the same FP32 operations, in the
+     * same order, as the reference's pair test. */
+    auto collides = [&](const float4& pj) {
+        const float ex = pk.x - pj.x, ey = pk.y - pj.y, ez = pk.z - pj.z;
+        const float d2 = (ex * ex + ey * ey) + ez * ez;
+        const float rs = pk.w + pj.w;
+        return d2 < rs * rs;
+    };
+    /* Candidates are read in groups of three cells, the first two slots of
+     * each cell unconditionally (at a clamped, always valid index, the
+     * result masked), so that six independent loads are in flight per
+     * round trip instead of one load per dependent loop iteration; a cell
+     * holds ~0.5 candidates on average, and the rare further ones are read
+     * by a loop. */
+    const int32_t last = *total - 1;
     bool hit = false;
 #pragma unroll
-    for (int c = 0; c < 27; ++c) {
-        for (int32_t j = lo[c]; j < hi[c] && !hit; ++j) {
-            if (j == k) continue;
-            const float4 pj = spos[j];
-            const float ex = pk.x - pj.x, ey = pk.y - pj.y, ez = pk.z - pj.z;
-            const float d2 = (ex * ex + ey * ey) + ez * ez;
-            const float rs = pk.w + pj.w;
-            hit = d2 < rs * rs;
+    for (int g = 0; g < 9; ++g) {
+        float4 pc[6];
+        bool use[6];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int c = 3 * g + u;
+            const int32_t j0 = lo[c], j1 = lo[c] + 1;
+            pc[2 * u] = spos[j0 < last ? j0 : last];
+            pc[2 * u + 1] = spos[j1 < last ? j1 : last];
+            use[2 * u] = j0 < hi[c] && j0 != k;
+            use[2 * u + 1] = j1 < hi[c] && j1 != k;
+        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t) hit |= use[t] && collides(pc[t]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int c = 3 * g + u;
+            for (int32_t j = lo[c] + 2; j < hi[c]; ++j)
+                if (j != k) hit |= collides(spos[j]);
         }
     }
-    if (hit) {
-        /* the query reads positions from the sorted copy only, so the mask
-         * is updated in place */
-        alive[ids[k]] = 0;
-        if (died) atomicAdd(died, 1ull);
+    /* the query reads positions from the sorted copy only, so the mask is
+     * updated in place */
+    if (hit) alive[ids[k]] = 0;
+    if (died) {
+        /* one atomic per wave: most agents of a dense swarm collide, and one
+         * atomic each on a single counter serialises the whole pass */
+        const unsigned long long m = __ballot(hit);
+        if (m && (threadIdx.x & (warpSize - 1)) == (unsigned)(__ffsll((long long)m) - 1))
+            atomicAdd(died, (unsigned long long)__popcll(m));
     }
 }
 
 }  // namespace
 
+/* Buckets per agent (rounded up to a power of two).  More buckets mean
+ * fewer far cells sharing a bucket, but longer clear and scan passes: at
+ * 1M agents 2 measured 0.36 ms per pass, 4, 8 and 16 0.37, 0.40, 0.47. */
+#ifndef POTATO_BUCKETS_PER_AGENT
+#define POTATO_BUCKETS_PER_AGENT 2
+#endif
+
 uint32_t collision_buckets(int64_t n) {
     uint32_t m = 1024;
-    while ((int64_t)m < 2 * n && m < (1u << 30)) m <<= 1;   /* the Z-order code has 30 bits */
+    while ((int64_t)m < POTATO_BUCKETS_PER_AGENT * n && m < (1u << 30)) m <<= 1;   /* the Z-order code has 30 bits */
     return m;
 }
 
