@@ -536,7 +536,23 @@ def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000):
     log(f"cpu baseline: {v:.4e} agent-steps/s on {threads} threads ({dt:.1f} s)")
     return {"value": v, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sub.n} agents of the same swarm x {sample_steps} steps, FP64, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall",
+            "host": host_cpu()}
+
+
+def host_cpu() -> str:
+    """CPU model and logical CPU count of the host the reference ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs"
+
 
 
 if __name__ == "__main__":

@@ -52,3 +52,8 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=100)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_host_cpu_is_described():
+    text = bench.host_cpu()
+    assert "logical CPUs" in text and text.split(",")[0].strip()
