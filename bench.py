@@ -190,6 +190,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
+        "env": run_environment(torch),
     }
     print(json.dumps(out), flush=True)
 
@@ -538,6 +539,15 @@ def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000):
             "sample": f"first {sub.n} agents of the same swarm x {sample_steps} steps, FP64, "
                       f"{dt:.1f} s wall",
             "host": host_cpu()}
+
+
+def run_environment(torch) -> dict:
+    """Software versions and the device the numbers were taken on."""
+    from paper_2308_12698_amd import _lib
+    p = torch.cuda.get_device_properties(0)
+    return {"device": p.name, "gcn_arch": getattr(p, "gcnArchName", ""), "compute_units": p.multi_processor_count,
+            "torch": torch.__version__, "hip": torch.version.hip,
+            "library": _lib.load().potato_version().decode(), "seeds": "numpy PCG64, 12698 + 100 config + stream"}
 
 
 def host_cpu() -> str:
