@@ -7,6 +7,9 @@ computes any part of the method.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
+import os
 import weakref
 
 import torch
@@ -35,6 +38,42 @@ def _check_rows(name, t, rows, n, dtype=torch.float32):
     if t.dim() != 2 or t.shape[0] != rows or t.stride(1) != 1 or t.shape[1] < n:
         raise ValueError(f"{name} must be [{rows}, >= {n}] with unit column stride, got "
                          f"{tuple(t.shape)} strides {t.stride()}")
+
+
+_LIB_DIGEST = None
+
+
+def _library_digest() -> str:
+    """Hash of the loaded library file: tuned shapes are kept per build."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        with open(L.LIB_PATH, "rb") as f:
+            _LIB_DIGEST = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _LIB_DIGEST
+
+
+def autotune_cached(path: str, key: str, run) -> dict:
+    """The launch shape stored under ``key`` in the JSON file ``path``, or
+    ``run()``'s result, which is then stored there (written to a temporary
+    file and renamed, so a reader never sees a partial file).  An unreadable
+    file counts as empty."""
+    try:
+        with open(path) as f:
+            table = json.load(f)
+        if not isinstance(table, dict):
+            table = {}
+    except (OSError, ValueError):
+        table = {}
+    hit = table.get(key)
+    if isinstance(hit, dict) and {"block", "steps_per_launch", "grid_blocks"} <= hit.keys():
+        return {k: int(hit[k]) for k in ("block", "steps_per_launch", "grid_blocks")}
+    result = run()
+    table[key] = result
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return result
 
 
 class Simulator:
@@ -154,17 +193,33 @@ class Simulator:
         return state
 
     def autotune(self, state, dt, probe_steps=200, *, n_agents=None, type_idx=None, perm=None,
-                 gains=None, motor_cmd=None, wp=None, resample_every=0, step0=0, stream=None):
-        """Time the fused form's launch shapes on a scratch copy; keep the best."""
+                 gains=None, motor_cmd=None, wp=None, resample_every=0, step0=0, stream=None,
+                 cache=None):
+        """Time the fused form's launch shapes on a scratch copy; keep the best.
+
+        ``cache`` (default: the POTATO_AUTOTUNE_CACHE environment variable) is
+        a JSON file of earlier results, keyed by device, library build,
+        variant, agent count and probe length; a hit skips the timing."""
         n = int(n_agents if n_agents is not None else state.shape[1])
         st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
                                    resample_every, step0)
-        best = L.Options()
-        L.check(self._lib.potato_autotune(self._h, C.byref(st), C.byref(pp), C.byref(cm),
-                                          float(dt), n, int(probe_steps), C.byref(best),
-                                          _stream_handle(stream)))
-        return dict(block=best.block, steps_per_launch=best.steps_per_launch,
-                    grid_blocks=best.grid_blocks)
+
+        def run():
+            best = L.Options()
+            L.check(self._lib.potato_autotune(self._h, C.byref(st), C.byref(pp), C.byref(cm),
+                                              float(dt), n, int(probe_steps), C.byref(best),
+                                              _stream_handle(stream)))
+            return dict(block=best.block, steps_per_launch=best.steps_per_launch,
+                        grid_blocks=best.grid_blocks)
+
+        path = cache if cache is not None else os.environ.get("POTATO_AUTOTUNE_CACHE")
+        if not path:
+            return run()
+        props = torch.cuda.get_device_properties(state.device)
+        key = "|".join(str(x) for x in (
+            getattr(props, "gcnArchName", props.name), _library_digest(), self.mode, self.n_types,
+            type_idx is not None, gains is not None, perm is not None, n, int(probe_steps)))
+        return autotune_cached(path, key, run)
 
     def step_backward(self, ckpt, ckpt_every, n_steps, dt, grad_final, *, n_agents=None,
                       type_idx=None, perm=None, gains=None, wp=None, resample_every=0, step0=0,

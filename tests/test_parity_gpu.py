@@ -396,3 +396,28 @@ def test_checkpoints_are_the_intermediate_states(torch_dev):
     for c in range(5):
         ref = gpu_rollout(torch_dev, sw, c * K, steps_per_launch=37)
         assert np.array_equal(ck[c].astype(np.float64), ref), c
+
+
+def test_autotune_cache_round_trip(torch_dev, tmp_path):
+    """A cached launch shape is returned without timing and runs the same
+    rollout bit for bit."""
+    import time
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config1(n=4096)
+    sim = Simulator(sw.types, sw.glob, mode=1, form="fused")
+    st = _dev(torch, dev, sw.state)
+    wp = _dev(torch, dev, sw.wp)
+    path = str(tmp_path / "tune.json")
+    first = sim.autotune(st, sw.dt, 100, wp=wp, cache=path)
+    t0 = time.perf_counter()
+    again = sim.autotune(st, sw.dt, 100, wp=wp, cache=path)
+    assert again == first and time.perf_counter() - t0 < 0.5
+    out = []
+    for shape in (first, again):
+        sim.set_options(form="fused", **shape)
+        x = _dev(torch, dev, sw.state)
+        sim.step(x, 300, sw.dt, wp=wp)
+        out.append(x.cpu().numpy())
+    sim.close()
+    assert np.array_equal(out[0], out[1])
