@@ -218,7 +218,8 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, which):
                     steps_per_launch=sim.opts.steps_per_launch, grid_blocks=sim.opts.grid_blocks)
     if "fused_eager" in which:
         ms = timed(lambda: sim.step(state, 2000, sw.dt, wp=wp, resample_every=sw.resample_every))
-        res["fused_eager"] = {"agent_steps_per_s": N * 2000 / (ms * 1e-3), "steps_timed": 2000}
+        res["fused_eager"] = {"agent_steps_per_s": N * 2000 / (ms * 1e-3), "steps_timed": 2000,
+                              "roofline": alu_roofline(N * 2000 / (ms * 1e-3))}
         log(f"fused eager: {res['fused_eager']['agent_steps_per_s']:.4e} agent-steps/s")
     if "hetero" in which:
         res.update(hetero_form(torch, dev, timed))
@@ -270,7 +271,8 @@ def hetero_form(torch, dev, timed):
         ms = timed(lambda: hsim.step(s0, hw.n_steps, hw.dt, type_idx=ti, perm=perm, wp=hwp,
                                      resample_every=hw.resample_every), reps=1)
         res[label] = {"agent_steps_per_s": work / (ms * 1e-3), "agent_steps": work,
-                      "n_agents": hw.n, "rollout_ms": ms}
+                      "n_agents": hw.n, "rollout_ms": ms,
+                      "roofline": alu_roofline(work / (ms * 1e-3))}
         log(f"{label}: {res[label]['agent_steps_per_s']:.4e} agent-steps/s")
     hsim.close()
     return res
@@ -548,6 +550,13 @@ def run_environment(torch) -> dict:
     return {"device": p.name, "gcn_arch": getattr(p, "gcnArchName", ""), "compute_units": p.multi_processor_count,
             "torch": torch.__version__, "hip": torch.version.hip,
             "library": _lib.load().potato_version().decode(), "seeds": "numpy PCG64, 12698 + 100 config + stream"}
+
+
+def alu_roofline(agent_steps_per_s: float) -> dict:
+    """Algorithmic FP32 rate of a closed-loop form against the FP32 peak."""
+    tf = FLOPS_PER_AGENT_STEP * agent_steps_per_s / 1e12
+    return {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_FP32_TFLOPS, 4)}
 
 
 def host_cpu() -> str:

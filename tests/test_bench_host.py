@@ -57,3 +57,9 @@ def test_more_than_one_gpu_is_refused():
 def test_host_cpu_is_described():
     text = bench.host_cpu()
     assert "logical CPUs" in text and text.split(",")[0].strip()
+
+
+def test_alu_roofline_prices_the_flop_count():
+    r = bench.alu_roofline(1e11)
+    assert r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP32_TFLOPS
+    assert abs(r["achieved"] - 96.2) < 1e-9 and abs(r["frac"] - round(96.2 / 157.3, 4)) < 1e-12
