@@ -33,6 +33,16 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
+@pytest.fixture(autouse=True)
+def release_memory(torch_dev):
+    """Hand the cached blocks back after each case, so that later tests and
+    the library's own allocations see the whole device again."""
+    yield
+    import gc
+    gc.collect()
+    torch_dev[0].cuda.empty_cache()
+
+
 def need_memory(torch, n_bytes):
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
