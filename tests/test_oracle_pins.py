@@ -536,3 +536,131 @@ def test_lateral_step_follows_the_linear_cascade(oracle):
         x_ref[k] = s[0, 0] - p0[0]
     assert np.abs(x_ref - x_lin).max() <= 2e-5 * d
     assert abs(x_ref[-1] - d) < 0.2 * d
+
+
+# --- saturated regimes: clamps and limits of the cascade (Sec. II-B, eq. 3) ----
+#
+# A waypoint far straight above or below a level hovering airframe keeps
+# the position error at its saturation radius and the attitude at identity,
+# so the cascade reduces to a constant collective command that one of its
+# limits fixes: the rotor speed limit when climbing, the minimum vertical
+# acceleration when descending.  The vertical motion is then the linear
+# ODE  v' = 4 k_f W(t)^2 / m - (c_d / m) v - g  with the rotor speed W
+# relaxing exponentially to the command, which is integrated here to
+# 1e-12 by an adaptive solver, independent of the reference's RK4.  The
+# position integral grows by r_sat dt per step until its clamp.
+
+def _vertical_limit_case(O, t, dz, T=3000, every=250):
+    """Roll the reference out from hover at p0 towards p0 + (0, 0, dz),
+    recording (step, state) every ``every`` steps."""
+    p0 = np.array([4.0, -6.0, 50.0])
+    s = single_state(p=p0)
+    wp = (p0 + np.array([0.0, 0.0, dz])).reshape(1, 3, 1)
+    out = []
+    for k in range(0, T, every):
+        s = run_closed(O, s, t, every, wp=wp, step0=k)[:30]
+        out.append((k + every, s[:, 0].copy()))
+    return p0, out
+
+
+def _vertical_exact(t, w_cmd, t_end, t_eval):
+    """z - z0, v_z and the motor-speed integral J of the vertical ODE with
+    rotor speed w_cmd + (w_ref - w_cmd) exp(-t / tau_m), all four equal."""
+    from scipy.integrate import solve_ivp
+    m, kf, cd, tau, w0 = t["mass"], t["k_f"], t["drag"], t["tau_m"], t["w_ref"]
+
+    def rhs(tt, y):
+        w = w_cmd + (w0 - w_cmd) * math.exp(-tt / tau)
+        return [y[1], 4.0 * kf * w * w / m - cd / m * y[1] - G, 4.0 * w * w]
+
+    sol = solve_ivp(rhs, (0.0, t_end), [0.0, 0.0, 0.0], method="DOP853", t_eval=t_eval,
+                    rtol=1e-12, atol=1e-12)
+    assert sol.success
+    return sol.y
+
+
+def _check_vertical_limit_case(t, p0, out, w_cmd, i_sign, dt=1e-3):
+    ks = np.array([k for k, _ in out])
+    z, v, J = _vertical_exact(t, w_cmd, ks[-1] * dt, ks * dt)
+    zz = 1 - 1e-3 / t["tau_m"]
+    R = zz + (1e-3 / t["tau_m"]) ** 2 / 2 - (1e-3 / t["tau_m"]) ** 3 / 6 + (1e-3 / t["tau_m"]) ** 4 / 24
+    r_sat, ipos_max = GLOB["r_sat"], GLOB["ipos_max"]
+    for j, (k, s) in enumerate(out):
+        # vertical motion: thrust k_f W^2 per rotor, drag c_d v, gravity
+        assert s[2] - p0[2] == pytest.approx(z[j], rel=1e-6, abs=1e-9)
+        assert s[5] == pytest.approx(v[j], rel=1e-6, abs=1e-9)
+        assert s[29] == pytest.approx(J[j], rel=1e-6)
+        # rotors: RK4 of the first-order lag towards the held command
+        w = w_cmd + (t["w_ref"] - w_cmd) * R ** k
+        assert np.abs(s[13:17] + t["w_ref"] - w).max() <= 1e-9 * w_cmd
+        # position integral: r_sat dt per step in the direction of the error, clamped
+        assert s[19] == pytest.approx(i_sign * min(k * r_sat * dt, ipos_max), rel=1e-12, abs=1e-12)
+        # no lateral motion, no rotation
+        assert np.abs(s[0:2] - p0[0:2]).max() <= 1e-9 and np.abs(s[3:5]).max() <= 1e-9
+        assert np.abs(s[6:10] - [1, 0, 0, 0]).max() <= 1e-12 and np.abs(s[10:13]).max() <= 1e-9
+        assert np.abs(s[17:19]).max() == 0.0
+
+
+def test_climb_at_the_rotor_speed_limit(oracle):
+    """Waypoint 10 km above with a stiff position loop (k_pp = 100, no I or
+    D): the collective asks for 52 N per rotor of 1.7 kg x (200 + g) / 4,
+    above k_f W_max^2 = 38.1 N, so every rotor is commanded exactly W_max.
+    The mass is not 1, so drag divided by mass differs from drag."""
+    gains = (100.0, 0.0, 0.0) + tuple(I.DEFAULT_GAINS[3:])
+    t = exact_type(mass=1.7, gains=gains)
+    assert t["mass"] * (100.0 * GLOB["r_sat"] + G) / 4 > t["k_f"] * t["w_max"] ** 2
+    p0, out = _vertical_limit_case(oracle, t, 1e4)
+    _check_vertical_limit_case(t, p0, out, t["w_max"], +1.0)
+    assert out[-1][1][19] == GLOB["ipos_max"]          # the clamp was reached
+
+
+def test_descent_at_the_minimum_vertical_acceleration(oracle):
+    """Waypoint 10 km below (k_pp = 10, no I or D): the commanded vertical
+    acceleration -20 + g is raised to its floor az_min_frac g, so the
+    collective is m az_min_frac g and each rotor is commanded
+    sqrt(m az_min_frac g / (4 k_f)); the airframe sinks towards the
+    terminal speed of the remaining half weight against drag."""
+    gains = (10.0, 0.0, 0.0) + tuple(I.DEFAULT_GAINS[3:])
+    t = exact_type(mass=1.7, gains=gains)
+    a_floor = GLOB["az_min_frac"] * G
+    assert -10.0 * GLOB["r_sat"] + G < a_floor
+    w_cmd = math.sqrt(t["mass"] * a_floor / (4.0 * t["k_f"]))
+    p0, out = _vertical_limit_case(oracle, t, -1e4)
+    _check_vertical_limit_case(t, p0, out, w_cmd, -1.0)
+    assert out[-1][1][19] == -GLOB["ipos_max"]
+    assert out[-1][1][5] < -5.0                        # sinking
+
+
+def test_controller_yaw_with_clamped_integrals_and_rotor_limits(oracle):
+    """Level hover yawed by 90 degrees, waypoint at the position, attitude
+    and rate integrals 1e-4 short of their clamps: one controller step.
+    The error quaternion is conj(q), a yaw error of -2 sin(45 deg); both
+    integrals hit their clamps; the yaw torque I_zz alpha_z is produced by
+    the rotors' reaction torques k_m W^2 (signs +, -, +, - for rotors 1-4),
+    so the mixer asks thrust f_c / 4 + s_i tau_z k_f / (4 k_m) of rotor i,
+    which is negative for rotors 1 and 3 (commanded 0) and above
+    k_f W_max^2 for rotors 2 and 4 (commanded W_max)."""
+    t = exact_type()
+    dt = 1e-3
+    psi = math.pi / 2
+    x = np.zeros(18)
+    x[6], x[9] = math.cos(psi / 2), math.sin(psi / 2)
+    x[13:17] = t["w_ref"]
+    mem = np.zeros(12)
+    mem[5] = -(GLOB["iatt_max"] - 1e-4)          # i_att z
+    mem[8] = -(GLOB["irate_max"] - 1e-4)         # i_rate z
+    wcmd, mem1 = oracle.controller(t, GLOB, x, mem, (0.0, 0.0, 0.0), dt)
+    kpp, kip, kdp, kpa, kia, kda, kpr, kir, kdr = I.DEFAULT_GAINS
+    e_att = -2.0 * math.sin(psi / 2)
+    assert e_att * dt < -1e-4                    # the step crosses the clamp
+    i_att = -GLOB["iatt_max"]
+    w_des = kpa * e_att + kia * i_att
+    i_rate = -GLOB["irate_max"]
+    alpha = kpr * w_des + kir * i_rate
+    tau_z = t["Izz"] * alpha
+    f = t["mass"] * G / 4 + np.array([1, -1, 1, -1]) * tau_z * t["k_f"] / (4 * t["k_m"])
+    assert f[0] < 0 and f[1] > t["k_f"] * t["w_max"] ** 2
+    assert wcmd[0] == 0.0 and wcmd[2] == 0.0
+    assert wcmd[1] == pytest.approx(t["w_max"], rel=1e-14) and wcmd[3] == pytest.approx(t["w_max"], rel=1e-14)
+    assert mem1[5] == i_att and mem1[8] == i_rate
+    assert np.abs(mem1[[0, 1, 2, 3, 4, 6, 7, 9, 10, 11]]).max() <= 1e-15
