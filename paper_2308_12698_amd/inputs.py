@@ -231,6 +231,53 @@ def config4(n: int = 65536, n_steps: int = 500, dt: float = 2e-3) -> Swarm:
                  extra=dict(target=target, ckpt_every=50, cost_weight=1e-4))
 
 
+def limits_swarm(n_group: int = 64, n_steps: int = 1000) -> Swarm:
+    """Agents driven into the controller's limits (a parity case, not a
+    workload of the paper), four groups of ``n_group``:
+
+    - climbers: waypoint 10 km above, stiff position loop (k_pp in [60, 120],
+      no I or D), so every rotor is commanded at the speed limit;
+    - descenders: waypoint 10 km below (k_pp in [8, 15], no I or D), so the
+      commanded vertical acceleration sits at its floor;
+    - yawed: level, yawed by up to 150 degrees, waypoint at the position,
+      attitude and rate integrals 1e-4 short of their clamps (rotors hit 0
+      and the speed limit);
+    - tumbling: tilted by up to 60 degrees about a random axis, body rates up
+      to 5 rad/s, waypoint 1 km away in a random direction.
+    Gains are per agent (default gains outside the first two groups).
+    """
+    r = rng(5, 0)
+    n = 4 * n_group
+    pos = _box_positions(r, n)
+    s = np.zeros((N_ROWS, n), dtype=np.float64)
+    s[0:3] = pos
+    s[6] = 1.0
+    gains = np.tile(np.asarray(DEFAULT_GAINS, dtype=np.float64)[:, None], (1, n))
+    wp = pos.copy()
+    up, down, yaw, tumble = (slice(k * n_group, (k + 1) * n_group) for k in range(4))
+    wp[2, up] += 1e4
+    gains[0, up] = r.uniform(60.0, 120.0, n_group)
+    gains[1:3, up] = 0.0
+    wp[2, down] -= 1e4
+    gains[0, down] = r.uniform(8.0, 15.0, n_group)
+    gains[1:3, down] = 0.0
+    psi = r.uniform(-150.0, 150.0, n_group) * math.pi / 180.0
+    s[6, yaw], s[9, yaw] = np.cos(psi / 2), np.sin(psi / 2)
+    s[22, yaw] = -np.sign(psi) * (DEFAULT_GLOBALS["iatt_max"] - 1e-4)     # i_att z
+    s[25, yaw] = -np.sign(psi) * (DEFAULT_GLOBALS["irate_max"] - 1e-4)   # i_rate z
+    axis = r.normal(size=(3, n_group))
+    axis /= np.linalg.norm(axis, axis=0)
+    ang = r.uniform(0.0, 60.0, n_group) * math.pi / 180.0
+    s[6, tumble] = np.cos(ang / 2)
+    s[7:10, tumble] = axis * np.sin(ang / 2)
+    s[10:13, tumble] = r.uniform(-5.0, 5.0, (3, n_group))
+    d = r.normal(size=(3, n_group))
+    wp[:, tumble] += 1e3 * d / np.linalg.norm(d, axis=0)
+    return Swarm("limits", 1, 1e-3, n_steps, f32(s), [base_type()], globals_f32(),
+                 gains=f32(gains), wp=f32(wp[None]), resample_every=0,
+                 extra=dict(groups=("climb", "descend", "yaw", "tumble")))
+
+
 def subset(sw: Swarm, idx: np.ndarray) -> Swarm:
     """The same workload restricted to the agents ``idx`` (column gather)."""
     idx = np.asarray(idx)

@@ -120,6 +120,22 @@ def test_waypoint_epochs_ragged_agents(oracle, torch_dev):
     assert np.all(got[:, sw.n:] == 7.0)            # columns past n_agents untouched
 
 
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_controller_limits_match_oracle(oracle, torch_dev, form):
+    """Agents held at the rotor speed limit, at the vertical-acceleration
+    floor, with attitude and rate integrals in their clamps and rotors at 0
+    and the limit, and tumbling towards far waypoints (inputs.limits_swarm),
+    with per-agent gains; every agent against the oracle after 1,000 steps."""
+    sw = I.limits_swarm()
+    got = gpu_rollout(torch_dev, sw, sw.n_steps, form=form, steps_per_launch=250)
+    ref = oracle_rollout(oracle, sw, sw.n_steps)
+    for k, name in enumerate(sw.extra["groups"]):
+        idx = np.arange(k * sw.n // 4, (k + 1) * sw.n // 4)
+        sub = I.subset(sw, idx)
+        print(name, end=" ")
+        assert_parity(got[:, idx], ref[:, idx], sub)
+
+
 def test_scale_workload_full_size_sampled(oracle, torch_dev):
     """1,048,576 agents, 1,000 steps with the bench's launch shape (tuned,
     graph-captured); 4,096 sampled agents against the oracle."""
