@@ -227,3 +227,44 @@ def test_backward_rejects_invalid_arguments(diff_run, torch_dev):
                                wp=diff_run["wp_t"])
     assert e.value.status == L.EUNSUPPORTED
     open_sim.close()
+
+
+def test_adjoint_in_the_controller_limits(oracle, torch_dev):
+    """Gradients through the saturations and clamps (inputs.limits_swarm:
+    rotors at the speed limit and at 0, the vertical-acceleration floor,
+    clamped integrals, tumbling agents), 300 steps, checkpoints every 50,
+    every agent against the reference's dual numbers.  A clamp passes no
+    derivative while it holds, so for the climbers every path from the gains
+    to the final state is cut: their reference gain gradient is exactly 0,
+    and there the GPU's must be 0 too."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.limits_swarm(n_group=32, n_steps=300)
+    K = 50
+    sim = Simulator(sw.types, sw.glob, mode=1, form="fused", steps_per_launch=100)
+    x = torch.from_numpy(sw.state).to(dev)
+    gains = torch.from_numpy(sw.gains).to(dev)
+    wp = torch.from_numpy(sw.wp).to(dev)
+    ckpt = torch.empty((sw.n_steps // K, 40, sw.n), device=dev)
+    sim.step(x, sw.n_steps, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
+    seed = np.zeros((30, sw.n), dtype=np.float32)
+    seed[0:3], seed[3:6], seed[29] = 1.0, 0.5, 1e-4
+    gx0, gg = sim.step_backward(ckpt, K, sw.n_steps, sw.dt, torch.from_numpy(seed).to(dev),
+                                gains=gains, wp=wp)
+    torch.cuda.synchronize()
+    got = np.concatenate([gx0.cpu().numpy().T, gg.cpu().numpy().T], axis=1)
+    sim.close()
+    _, jac = oracle.jacobian(sw.state, sw.types, sw.glob, sw.dt, sw.n_steps, wp=sw.wp, gains=sw.gains)
+    ref = np.einsum("ar,arc->ac", seed.T.astype(np.float64), jac)
+    g = sw.n // 4
+    for k, name in enumerate(sw.extra["groups"]):
+        sl = slice(k * g, (k + 1) * g)
+        for blk, cols in (("state", slice(0, 30)), ("gains", slice(30, 39))):
+            r = np.linalg.norm(ref[sl, cols], axis=1)
+            d = np.linalg.norm(got[sl, cols] - ref[sl, cols], axis=1)
+            cut = r == 0.0
+            e = np.where(cut, 0.0, d / np.where(cut, 1.0, r))
+            print(f"{name} {blk}: worst {e.max():.2e}, {int(cut.sum())} exactly zero "
+                  f"(GPU there <= {d[cut].max() if cut.any() else 0.0:.1e})", flush=True)
+            assert e.max() <= TOL
+            assert not cut.any() or d[cut].max() == 0.0
