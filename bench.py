@@ -250,8 +250,27 @@ def plain_form(timed, sw, state, wp, N):
                                  "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                                  "bytes_per_agent_step": bytes_step,
                                  "traffic": measured_traffic("plain")}}
-    log(f"plain: {res['plain']['agent_steps_per_s']:.4e} agent-steps/s, {gbs:.0f} GB/s")
+    res["plain"]["hbm_reference"] = hbm_reference(timed, state)
+    log(f"plain: {res['plain']['agent_steps_per_s']:.4e} agent-steps/s, {gbs:.0f} GB/s "
+        f"(torch copy {res['plain']['hbm_reference']['torch_copy_GBps']:.0f}, "
+        f"triad {res['plain']['hbm_reference']['torch_triad_GBps']:.0f} GB/s)")
     return res
+
+
+def hbm_reference(timed, like):
+    """What torch's own elementwise kernels reach on this HBM, as context for
+    the plain kernel's rate: a device copy (read + write) and a triad
+    y = x + z / 2 (two reads, one write) over 1 GiB FP32 buffers."""
+    import torch
+    n = (1 << 30) // 4
+    x = torch.ones(n, device=like.device)
+    z = torch.full((n,), 2.0, device=like.device)
+    y = torch.empty(n, device=like.device)
+    copy_ms = timed(lambda: y.copy_(x), reps=20)
+    triad_ms = timed(lambda: torch.add(x, z, alpha=0.5, out=y), reps=20)
+    return {"torch_copy_GBps": round(2 * 4 * n / (copy_ms * 1e-3) / 1e9, 1),
+            "torch_triad_GBps": round(3 * 4 * n / (triad_ms * 1e-3) / 1e9, 1),
+            "buffer_bytes": 4 * n}
 
 
 def hetero_form(torch, dev, timed):
