@@ -25,6 +25,10 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function"]
 
 
+# roctx ranges name each entry point in marker traces.
+LIBS = ["-lrocprofiler-sdk-roctx"]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -35,7 +39,7 @@ def hipcc() -> str:
 def build_library(verbose: bool = False) -> str:
     """Compile the sources into libpotato.so (always recompiles)."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-I", INCLUDE, *SOURCES, "-o", tmp]
+    cmd = [hipcc(), *HIP_FLAGS, "-I", INCLUDE, *SOURCES, *LIBS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

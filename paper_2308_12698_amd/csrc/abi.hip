@@ -382,6 +382,7 @@ potato_status potato_set_options(potato_ctx* ctx, const potato_options* opts) {
 potato_status potato_step(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                           const potato_cmds* cmds, float dt, int64_t n_agents, int32_t n_steps,
                           float* ckpt, int32_t ckpt_every, void* stream) {
+    ApiRange range("potato_step");
     potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, n_steps, ckpt, ckpt_every);
     if (s != POTATO_OK) return s;
     if (n_steps == 0) return POTATO_OK;
@@ -416,6 +417,7 @@ potato_status potato_step(potato_ctx* ctx, const potato_state* state, const pota
 potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                               const potato_cmds* cmds, float dt, int64_t n_agents, int32_t probe_steps,
                               potato_options* best, void* stream) {
+    ApiRange range("potato_autotune");
     potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, probe_steps, nullptr, 0);
     if (s != POTATO_OK) return s;
     if (probe_steps < 1) return fail(POTATO_EINVAL, "probe_steps must be >= 1");
@@ -549,6 +551,7 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
                                    float dt, int64_t n_agents, int32_t n_steps, const float* ckpt,
                                    int32_t ckpt_every, int64_t ld, const float* grad_final, float* grad_x0,
                                    float* grad_gains, void* workspace, int64_t workspace_bytes, void* stream) {
+    ApiRange range("potato_step_backward");
     if (!ctx || !params || !cmds) return fail(POTATO_EINVAL, "ctx, params and cmds must be non-null");
     if (ctx->opts.mode != POTATO_CLOSED_LOOP)
         return fail(POTATO_EUNSUPPORTED, "the adjoint is implemented for closed-loop rollouts");
@@ -595,6 +598,7 @@ int64_t potato_order_workspace_bytes(int64_t n_agents, int32_t n_types) {
 
 potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t n_agents, int32_t* perm,
                                    void* workspace, int64_t workspace_bytes, void* stream) {
+    ApiRange range("potato_order_by_type");
     if (!ctx || !type || !perm || !workspace) return fail(POTATO_EINVAL, "ctx, type, perm and workspace must be non-null");
     if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");
     const int64_t need = potato_order_workspace_bytes(n_agents, ctx->n_types);
@@ -613,6 +617,7 @@ int64_t potato_collision_workspace_bytes(int64_t n_agents) {
 potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                                        int64_t n_agents, uint8_t* alive, int64_t* died, void* workspace,
                                        int64_t workspace_bytes, void* stream) {
+    ApiRange range("potato_detect_collisions");
     if (!ctx || !state || !state->rows || !alive || !workspace)
         return fail(POTATO_EINVAL, "ctx, state, state.rows, alive and workspace must be non-null");
     if (n_agents < 1 || n_agents > 0x3fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30)");
@@ -629,6 +634,7 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
 
 potato_status potato_count_nonfinite(potato_ctx* ctx, const potato_state* state, int64_t n_agents, int64_t* count,
                                      void* stream) {
+    ApiRange range("potato_count_nonfinite");
     if (!ctx || !state || !state->rows || !count)
         return fail(POTATO_EINVAL, "ctx, state, state.rows and count must be non-null");
     if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");

@@ -5,11 +5,23 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include "../../include/potato.h"
 
 namespace potato {
+
+/* A named roctx range over one call of an entry point that enqueues GPU
+ * work, so that a marker trace (rocprofv3 --marker-trace) shows which
+ * library call each kernel came from.  Without a profiler attached a range
+ * costs a call into the roctx library and nothing else. */
+struct ApiRange {
+    explicit ApiRange(const char* name) { roctxRangePushA(name); }
+    ~ApiRange() { roctxRangePop(); }
+    ApiRange(const ApiRange&) = delete;
+    ApiRange& operator=(const ApiRange&) = delete;
+};
 
 /* Record `fmt` as the calling thread's last error and return `st`. */
 potato_status set_error(potato_status st, const char* fmt, ...);

@@ -158,6 +158,7 @@ potato_status potato_pipe_create(potato_ctx* ctx, int64_t n_agents, potato_pipe*
 }
 
 potato_status potato_pipe_push(potato_pipe* p, const float* host_cmd) {
+    ApiRange range("potato_pipe_push");
     if (!p || !host_cmd) return set_error(POTATO_EINVAL, "pipe and host_cmd must be non-null");
     const int s = (int)(p->pushed & 1);
     const size_t bytes = sizeof(float) * p->rows * (size_t)p->n;
@@ -177,6 +178,7 @@ potato_status potato_pipe_push(potato_pipe* p, const float* host_cmd) {
 
 potato_status potato_pipe_run(potato_pipe* p, const potato_state* state, const potato_params* params, float dt,
                               int32_t n_steps, int32_t snap_every, float* host_snap, void* stream) {
+    ApiRange range("potato_pipe_run");
     if (!p || !state || !params) return set_error(POTATO_EINVAL, "pipe, state and params must be non-null");
     if (p->pushed < 1) return set_error(POTATO_EINVAL, "potato_pipe_run before the first potato_pipe_push");
     if (n_steps < 0 || snap_every < 0) return set_error(POTATO_EINVAL, "n_steps and snap_every must be >= 0");
@@ -260,6 +262,7 @@ potato_status potato_pipe_run(potato_pipe* p, const potato_state* state, const p
 }
 
 potato_status potato_pipe_wait_snapshots(potato_pipe* p, int64_t count) {
+    ApiRange range("potato_pipe_wait_snapshots");
     if (!p) return set_error(POTATO_EINVAL, "pipe is null");
     if (count < 0 || count > p->snaps)
         return set_error(POTATO_EINVAL, "count must be in [0, %lld] (snapshots enqueued)", (long long)p->snaps);
@@ -272,6 +275,7 @@ potato_status potato_pipe_wait_snapshots(potato_pipe* p, int64_t count) {
 }
 
 potato_status potato_pipe_sync(potato_pipe* p) {
+    ApiRange range("potato_pipe_sync");
     if (!p) return set_error(POTATO_EINVAL, "pipe is null");
     hipError_t e = hipStreamSynchronize(p->ingress);
     if (e == hipSuccess) e = hipStreamSynchronize(p->egress);

@@ -28,7 +28,7 @@ def test_abi_host_code_under_asan_and_ubsan(tmp_path):
            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
            "-I", os.path.join(ROOT, "include"), *sources, os.path.join(HERE, "abi_sanitize_main.cpp"),
-           "-o", str(exe)]
+           "-lrocprofiler-sdk-roctx", "-o", str(exe)]
     build = subprocess.run(cmd, capture_output=True, text=True, timeout=540)
     if build.returncode != 0 and "asan" in (build.stderr or "").lower():
         pytest.skip("sanitizer runtime not available: " + build.stderr[-300:])
