@@ -522,18 +522,42 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
 
 namespace {
 
-/* Grid of the adjoint launch: enough resident blocks to fill the chip,
- * never more than the agents need (one tape column per thread). */
-int adjoint_grid(potato_ctx* ctx, bool het, bool gains, bool perm, int64_t n) {
-    int per_cu = 0, n_cu = 0;
+/* Launch shape of the adjoint.  One agent per thread, with enough resident
+ * blocks to fill the chip and never more than the agents need; or, when
+ * that would leave more than half of the resident wave slots empty (the
+ * reverse sweep is latency bound, so a SIMD needs two waves), the
+ * pipelined kernel whose recomputing and reversing waves serve the same 64
+ * agents (two waves per 64 agents). */
+struct AdjShape {
+    bool pipe;
+    int block;
+    int grid;
+};
+
+bool adjoint_shape(potato_ctx* ctx, bool het, bool gains, bool perm, int64_t n, AdjShape& out) {
+    int per_cu = 0, per_cu_pipe = 0, n_cu = 0;
     const size_t lds = adjoint_lds_bytes(het, ctx->n_types);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adjoint_kernel(het, gains, perm), kAdjBlock, lds) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adjoint_kernel(het, gains, perm, false), kAdjBlock,
+                                                     lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pipe, adjoint_kernel(het, gains, perm, true),
+                                                     kAdjPipeBlock, lds) != hipSuccess ||
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
-        return -1;
-    int64_t resident = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
-    int64_t need = (n + kAdjBlock - 1) / kAdjBlock;
-    return (int)std::min(resident, need);
+        return false;
+    n_cu = std::max(n_cu, 1);
+    const int64_t resident = (int64_t)std::max(per_cu, 1) * n_cu;
+    const int64_t wave_slots = resident * (kAdjBlock / 64);
+    const int64_t groups = (n + 63) / 64;                    /* waves of the one-agent-per-thread kernel */
+    if (POTATO_ADJOINT_PIPE && 2 * groups <= wave_slots) {
+        const int64_t resident_pipe = (int64_t)std::max(per_cu_pipe, 1) * n_cu;
+        out = AdjShape{true, kAdjPipeBlock, (int)std::min(resident_pipe, groups)};
+    } else {
+        out = AdjShape{false, kAdjBlock, (int)std::min(resident, (n + kAdjBlock - 1) / kAdjBlock)};
+    }
+    return true;
+}
+
+int64_t adjoint_tape_bytes(const AdjShape& sh, int32_t ckpt_every) {
+    return (int64_t)ckpt_every * kTapeRows * (int64_t)sh.grid * sh.block * (int64_t)sizeof(float);
 }
 
 }  // namespace
@@ -542,9 +566,9 @@ int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* pa
                                         int32_t ckpt_every) {
     if (!ctx || !params || n_agents < 1 || ckpt_every < 1) return -1;
     const bool het = params->type != nullptr;
-    const int grid = adjoint_grid(ctx, het, params->gains != nullptr, het && params->perm != nullptr, n_agents);
-    if (grid < 1) return -1;
-    return (int64_t)ckpt_every * kTapeRows * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
+    AdjShape sh;
+    if (!adjoint_shape(ctx, het, params->gains != nullptr, het && params->perm != nullptr, n_agents, sh)) return -1;
+    return adjoint_tape_bytes(sh, ckpt_every);
 }
 
 potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params, const potato_cmds* cmds,
@@ -570,9 +594,9 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
     const bool gains = params->gains != nullptr;
     const bool perm = het && params->perm != nullptr;
     std::lock_guard<std::mutex> g(ctx->mu);
-    const int grid = adjoint_grid(ctx, het, gains, perm, n_agents);
-    if (grid < 1) return fail(POTATO_EHIP, "occupancy query failed");
-    const int64_t need = (int64_t)ckpt_every * kTapeRows * (int64_t)grid * kAdjBlock * (int64_t)sizeof(float);
+    AdjShape sh;
+    if (!adjoint_shape(ctx, het, gains, perm, n_agents, sh)) return fail(POTATO_EHIP, "occupancy query failed");
+    const int64_t need = adjoint_tape_bytes(sh, ckpt_every);
     if (workspace_bytes < need)
         return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
     AdjArgs a{};
@@ -582,11 +606,11 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
     a.wp = cmds->wp; a.cmd_ld = cmds->ld; a.n_epochs = cmds->n_epochs; a.resample = cmds->resample_every;
     a.step0 = cmds->step0; a.n_steps = n_steps; a.K = ckpt_every;
     a.grad_final = grad_final; a.grad_x0 = grad_x0; a.grad_gains = grad_gains;
-    a.tape = reinterpret_cast<float*>(workspace); a.tape_ld = (int64_t)grid * kAdjBlock;
+    a.tape = reinterpret_cast<float*>(workspace); a.tape_ld = (int64_t)sh.grid * sh.block;
     a.n_types = het ? ctx->n_types : 1; a.table = ctx->d_table;
     a.alive = params->alive;
     a.lim = make_limits(ctx->limits, dt);
-    hipError_t e = launch_adjoint(het, gains, perm, a, kAdjBlock, grid, reinterpret_cast<hipStream_t>(stream));
+    hipError_t e = launch_adjoint(het, gains, perm, sh.pipe, a, sh.grid, reinterpret_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_step_backward launch");
 }

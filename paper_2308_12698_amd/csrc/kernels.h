@@ -72,7 +72,7 @@ struct AdjArgs {
     const float* grad_final;     /* [30][ld] */
     float* grad_x0;              /* [30][ld] */
     float* grad_gains;           /* [9][ld] or null */
-    float* tape;                 /* [K][grid threads / 64][kTapeRows][64]: per step, one block per wave */
+    float* tape;                 /* layouts at launch_adjoint */
     int64_t tape_ld;             /* threads in the grid (a multiple of 64) */
     int32_t n_types;
     const TypeConst* table;
@@ -87,13 +87,22 @@ hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int gr
 /* Kernel function pointer of a variant (occupancy queries). */
 const void* rollout_kernel(const Variant& v);
 
-/* Adjoint: kernel pointer (occupancy queries) and launch on exactly
- * grid_blocks x block threads (the tape has one column per thread). */
-const void* adjoint_kernel(bool het, bool gains, bool perm);
-hipError_t launch_adjoint(bool het, bool gains, bool perm, const AdjArgs& a, int block, int grid_blocks,
+/* Adjoint: kernel pointer (occupancy queries) and launch of grid_blocks
+ * blocks.  One agent per thread, kAdjBlock threads per block, tape
+ * [K][grid threads / 64][kTapeRows][64]; or, with `pipe`, kAdjPipeBlock
+ * threads per block serving 64 agents with one recomputing and one
+ * reversing wave, tape [grid][2][K][kTapeRows][64].  Either way the tape
+ * takes K x kTapeRows x grid x block floats. */
+const void* adjoint_kernel(bool het, bool gains, bool perm, bool pipe);
+hipError_t launch_adjoint(bool het, bool gains, bool perm, bool pipe, const AdjArgs& a, int grid_blocks,
                           hipStream_t stream);
 size_t adjoint_lds_bytes(bool het, int n_types);
 constexpr int kAdjBlock = 256;
+constexpr int kAdjPipeBlock = 128;
+/* Use the pipelined adjoint for small swarms (1) or never (0). */
+#ifndef POTATO_ADJOINT_PIPE
+#define POTATO_ADJOINT_PIPE 1
+#endif
 
 /* Dynamic LDS bytes the variant needs for n_types. */
 size_t rollout_lds_bytes(const Variant& v, int n_types);

@@ -297,6 +297,88 @@ __global__ void __launch_bounds__(kAdjBlock)
     }
 }
 
+/*
+ * Pipelined reverse sweep for swarms too small to give every SIMD two
+ * waves of the kernel above: a block of two waves serves 64 agents, wave 0
+ * recomputing segment s - 1 into one tape buffer while wave 1 reverses
+ * segment s from the other, one block barrier per segment.  Each wave
+ * performs the same operations as the one-wave-per-agent kernel, so the
+ * gradients are bitwise the same.  The segment loop and its barrier are
+ * outside every per-lane condition, and every iteration of every agent
+ * group reaches the barrier in both waves (ceil(n_steps / K) + 1 per
+ * group, the group loop bounds being the same for the whole block).
+ * Tape: per block, 2 buffers x K slots x kTapeRows x 64 floats.
+ */
+template <bool HET, bool GAINS, bool PERM>
+__global__ void __launch_bounds__(kAdjPipeBlock)
+    __attribute__((amdgpu_waves_per_eu(POTATO_ADJOINT_WAVES, POTATO_ADJOINT_WAVES))) k_adjoint_pipe(const AdjArgs A) {
+    extern __shared__ float4 lds_raw[];
+    Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
+    TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw + (sizeof(Limits) + 15) / 16);
+    stage_constants(A.table, A.n_types, A.lim, tab, lim_lds);
+    const Limits& lim = A.lim;
+    const int64_t ld = A.ld;
+    const bool producer = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t lb = lane << 2;
+    const int64_t tape_step = (int64_t)kTapeRows * 64;
+    const int64_t buf_stride = (int64_t)A.K * tape_step;
+    float* const tape = A.tape + (int64_t)blockIdx.x * 2 * buf_stride;
+    const int n_seg_all = (A.n_steps + A.K - 1) / A.K;
+    const int64_t n_groups = (A.n + 63) >> 6;
+    for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+        const int64_t j = (grp << 6) + lane;
+        const bool valid = j < A.n;
+        const uint32_t i = !valid ? 0u : PERM ? order_entry(A.perm, (uint32_t)j, A.n) : (uint32_t)j;
+        const uint32_t bo = i << 2;
+        const TypeConst& c = HET ? tab[type_entry(A.type, i, A.n_types)] : tab[0];
+        int64_t left = (int64_t)c.budget - A.step0;
+        left = left < 0 ? 0 : left;
+        int steps = left < A.n_steps ? (int)left : A.n_steps;
+        if (!valid || (A.alive && !elem(A.alive, i))) steps = 0;
+        const int n_seg = (steps + A.K - 1) / A.K;
+        Gains g;
+        if (GAINS) {
+            const float* G = A.gains;
+            const int64_t gl = A.gains_ld;
+            auto gain = [&](int k) { return elem(G + k * gl, bo); };
+            g = Gains{gain(0), gain(1), gain(2), gain(3), gain(4), gain(5), gain(6), gain(7), gain(8)};
+        } else {
+            g = Gains{c.gains[0], c.gains[1], c.gains[2], c.gains[3], c.gains[4],
+                      c.gains[5], c.gains[6], c.gains[7], c.gains[8]};
+        }
+        g.kdr_dt = g.kdr * lim.inv_dt;
+        WaypointCache wc{A.wp, A.cmd_ld, A.n_epochs, bo};
+        AgentAdj lam;
+        float gk[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (!producer && valid) load_adj(A.grad_final, ld, bo, lam);
+        /* iteration t: wave 0 recomputes segment n_seg_all - 1 - t into
+         * buffer (segment & 1), wave 1 reverses segment n_seg_all - t,
+         * recomputed in the previous iteration, from the other buffer */
+        for (int t = 0; t <= n_seg_all; ++t) {
+            if (producer) {
+                const int seg = n_seg_all - 1 - t;
+                if (seg >= 0 && seg < n_seg)
+                    recompute_segment(c, lim, g, A.ckpt, ld, bo, A.K, seg, steps, A.step0, A.resample, wc,
+                                      tape + (seg & 1) * buf_stride, tape_step, lb);
+            } else {
+                const int seg = n_seg_all - t;
+                if (t > 0 && seg < n_seg)
+                    reverse_segment(c, lim, g, A.K, seg, steps, A.step0, A.resample, wc,
+                                    tape + (seg & 1) * buf_stride, tape_step, lb, lam, gk);
+            }
+            __syncthreads();
+        }
+        if (!producer && valid) {
+            store_adj(A.grad_x0, ld, bo, lam);
+            if (A.grad_gains) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) elem(A.grad_gains + k * ld, bo) = gk[k];
+            }
+        }
+    }
+}
+
 /* ---- processing order by type: block histograms, scan, stable scatter ---- */
 
 __global__ void __launch_bounds__(kOrderBlock) k_block_hist(const uint8_t* type, int64_t n, int n_types,
@@ -370,23 +452,32 @@ template <bool H, bool G, bool P>
 const void* afn() {
     return reinterpret_cast<const void*>(&k_adjoint<H, G, P>);
 }
+template <bool H, bool G, bool P>
+const void* apfn() {
+    return reinterpret_cast<const void*>(&k_adjoint_pipe<H, G, P>);
+}
 
 size_t adjoint_lds_bytes(bool het, int n_types) {
     return ((sizeof(Limits) + 15) / 16) * 16 + (size_t)(het ? n_types : 1) * sizeof(TypeConst);
 }
 
-const void* adjoint_kernel(bool het, bool gains, bool perm) {
+const void* adjoint_kernel(bool het, bool gains, bool perm, bool pipe) {
+    if (pipe) {
+        if (!het) return gains ? apfn<false, true, false>() : apfn<false, false, false>();
+        if (perm) return gains ? apfn<true, true, true>() : apfn<true, false, true>();
+        return gains ? apfn<true, true, false>() : apfn<true, false, false>();
+    }
     if (!het) return gains ? afn<false, true, false>() : afn<false, false, false>();
     if (perm) return gains ? afn<true, true, true>() : afn<true, false, true>();
     return gains ? afn<true, true, false>() : afn<true, false, false>();
 }
 
-hipError_t launch_adjoint(bool het, bool gains, bool perm, const AdjArgs& a, int block, int grid_blocks,
+hipError_t launch_adjoint(bool het, bool gains, bool perm, bool pipe, const AdjArgs& a, int grid_blocks,
                           hipStream_t stream) {
     void* args[] = {const_cast<AdjArgs*>(&a)};
     const size_t lds = adjoint_lds_bytes(het, a.n_types);
-    return hipLaunchKernel(adjoint_kernel(het, gains, perm), dim3((unsigned)grid_blocks), dim3((unsigned)block),
-                           args, lds, stream);
+    return hipLaunchKernel(adjoint_kernel(het, gains, perm, pipe), dim3((unsigned)grid_blocks),
+                           dim3((unsigned)(pipe ? kAdjPipeBlock : kAdjBlock)), args, lds, stream);
 }
 
 size_t rollout_lds_bytes(const Variant& v, int n_types) {

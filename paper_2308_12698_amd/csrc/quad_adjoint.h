@@ -563,4 +563,69 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
     }
 }
 
+/* Waypoint row of the current epoch (clamped to the last one), reloaded
+ * only when the epoch changes. */
+struct WaypointCache {
+    const float* wp;
+    int64_t cmd_ld;
+    int n_epochs;
+    uint32_t bo;
+    int64_t cur = -1;
+    float v[3] = {0.0f, 0.0f, 0.0f};
+    __device__ __forceinline__ void use(int64_t e) {
+        const int64_t ep = e < n_epochs - 1 ? e : (int64_t)n_epochs - 1;
+        if (ep != cur) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) v[i] = elem(uniform(wp + (ep * 3 + i) * cmd_ld), bo);
+            cur = ep;
+        }
+    }
+};
+
+/* The two halves of one segment of agent_backward, for a kernel that runs
+ * them on different waves: the forward recomputation of segment `seg` from
+ * its checkpoint into the tape, and the reverse sweep of a recomputed
+ * segment.  Same operations, in the same order, as agent_backward. */
+__device__ __forceinline__ void recompute_segment(const TypeConst& c, const Limits& L, const Gains& g,
+                                                  const float* ckpt, int64_t ld, uint32_t bo, int K, int seg,
+                                                  int steps, int64_t step0, int resample, WaypointCache& wc,
+                                                  float* tape, int64_t tape_step, uint32_t lb) {
+    const int64_t period = resample > 0 ? resample : INT64_MAX;
+    const int k_begin = seg * K;
+    const int len = steps - k_begin < K ? steps - k_begin : K;
+    const int64_t k0 = step0 + k_begin;
+    Agent a;
+    load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
+    int64_t e = resample > 0 ? k0 / resample : 0;
+    int64_t next = resample > 0 ? (e + 1) * period : INT64_MAX;
+    for (int s = 0; s < len; ++s) {
+        store_tape(tape + (int64_t)s * tape_step, lb, a);
+        if (k0 + s == next) { ++e; next += period; }
+        wc.use(e);
+        float dc[4];
+        controller(c, L, g, a, wc.v, dc);
+        rk4_step(c, L, a, dc);
+    }
+}
+
+__device__ __forceinline__ void reverse_segment(const TypeConst& c, const Limits& L, const Gains& g, int K,
+                                                int seg, int steps, int64_t step0, int resample,
+                                                WaypointCache& wc, const float* tape, int64_t tape_step,
+                                                uint32_t lb, AgentAdj& lam, float gk[9]) {
+    const int64_t period = resample > 0 ? resample : INT64_MAX;
+    const int k_begin = seg * K;
+    const int len = steps - k_begin < K ? steps - k_begin : K;
+    const int64_t k0 = step0 + k_begin;
+    int64_t e = resample > 0 ? (k0 + len - 1) / resample : 0;
+    int64_t first = resample > 0 ? e * period : INT64_MIN;
+    for (int s = K - 1; s >= 0; --s) {
+        if (s >= len) continue;
+        if (k0 + s < first) { --e; first -= period; }
+        Agent x;
+        load_tape(tape + (int64_t)s * tape_step, lb, x);
+        wc.use(e);
+        step_vjp(c, L, g, x, wc.v, lam, gk);
+    }
+}
+
 }  // namespace potato

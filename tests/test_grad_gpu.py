@@ -268,3 +268,52 @@ def test_adjoint_in_the_controller_limits(oracle, torch_dev):
                   f"(GPU there <= {d[cut].max() if cut.any() else 0.0:.1e})", flush=True)
             assert e.max() <= TOL
             assert not cut.any() or d[cut].max() == 0.0
+
+
+@pytest.mark.parametrize("het", [False, True], ids=["homogeneous", "heterogeneous"])
+def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
+    """Swarms too small to give every SIMD two waves take the pipelined
+    reverse sweep (one recomputing and one reversing wave per 64 agents),
+    larger ones one agent per thread.  An agent's gradient must not depend
+    on which: 4,096 agents alone (pipelined) against the same agents at the
+    front of a 262,144-agent swarm (one per thread), bit for bit; with step
+    budgets ending inside segments and the type order in the heterogeneous
+    case."""
+    torch, dev = torch_dev
+    import ctypes as C
+    from paper_2308_12698_amd import _lib as L
+    from paper_2308_12698_amd.sim import Simulator
+    K, n_steps = 50, 150
+    small = I.config4(n=4096, n_steps=n_steps)
+    types = [small.types[0]]
+    ti_small = None
+    if het:
+        types = [dict(t, budget=b) for t, b in zip(I.hetero_types(), (37, 150, 75, 120, 149, 50, 99, 1))]
+        ti_small = np.random.default_rng(7).integers(0, len(types), small.n).astype(np.uint8)
+    reps = 64
+    runs = []
+    for n in (small.n, small.n * reps):
+        sim = Simulator(types, small.glob, mode=1, form="fused", steps_per_launch=50)
+        tile = lambda a: np.ascontiguousarray(np.tile(a, (1,) * (a.ndim - 1) + (n // small.n,)))
+        x = torch.from_numpy(tile(small.state)).to(dev)
+        gains = torch.from_numpy(tile(small.gains)).to(dev)
+        wp = torch.from_numpy(tile(small.wp)).to(dev)
+        ti = perm = None
+        if het:
+            ti = torch.from_numpy(tile(ti_small)).to(dev)
+            perm = sim.order_by_type(ti)
+        ckpt = torch.empty((n_steps // K, 40, n), device=dev)
+        sim.step(x, n_steps, small.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K, type_idx=ti, perm=perm)
+        seed = torch.from_numpy(tile(np.random.default_rng(8).normal(size=(30, small.n)).astype(np.float32))).to(dev)
+        pp = L.Params(C.c_void_p(ti.data_ptr()) if het else None, C.c_void_p(perm.data_ptr()) if het else None,
+                      C.c_void_p(gains.data_ptr()), n, None)
+        ws = int(sim._lib.potato_backward_workspace_bytes(sim._h, C.byref(pp), n, K))
+        gx0, gg = sim.step_backward(ckpt, K, n_steps, small.dt, seed, gains=gains, wp=wp, type_idx=ti, perm=perm)
+        torch.cuda.synchronize()
+        runs.append((ws, gx0[:, :small.n].cpu().numpy(), gg[:, :small.n].cpu().numpy()))
+        sim.close()
+    tape_per_thread = K * 30 * 4
+    assert runs[0][0] == tape_per_thread * 128 * (small.n // 64)      # pipelined: 64 blocks of 2 waves
+    assert runs[1][0] % (tape_per_thread * 256) == 0                   # one agent per thread, 256-thread blocks
+    assert np.isfinite(runs[0][1]).all() and np.abs(runs[0][2]).max() > 0
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
