@@ -27,6 +27,15 @@
  * same source runs in double (values), in forward-mode dual numbers
  * (Jacobians of the rollout) and in an operation-counting scalar (the
  * algorithmic flop count per agent-step).
+ *
+ * Pins (tests/test_oracle_pins.py, tests/test_oracle_grad.py): closed
+ * forms of the dynamics, conservation laws, RK4 order, the allocation
+ * geometry, linearised closed-loop step responses, saturated regimes and an
+ * independent rotation-matrix formulation of large coupled manoeuvres;
+ * dual numbers against central differences.  Parity unpinned: the outer
+ * position and attitude loops as a definition (the paper delegates them to
+ * a cited work); the tests pin this implementation of the project's
+ * reading of them, not the reading.
  */
 #include <cmath>
 #include <cstdint>
