@@ -225,7 +225,9 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
  *   workspace: device scratch of potato_backward_workspace_bytes() bytes
  *   (per-thread recomputation tape of ckpt_every steps).
  * Each segment of ckpt_every steps is recomputed from its checkpoint, then
- * reversed.  Errors: POTATO_EINVAL as in potato_step, plus null ckpt,
+ * reversed; for swarms too small to give every SIMD two waves, one wave
+ * recomputes the next segment while another reverses the current one, with
+ * the same result bit for bit.  Errors: POTATO_EINVAL as in potato_step, plus null ckpt,
  * grad_final or grad_x0, ckpt_every < 1 or a workspace that is too small;
  * POTATO_EUNSUPPORTED in open-loop mode.  grad_x0 may alias grad_final.
  */
