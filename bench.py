@@ -332,11 +332,14 @@ def fwd_bwd_form(torch, dev, timed, N):
     for n_agents in (65536, N):
         dw = I.config4(n=n_agents)
         K = dw.extra["ckpt_every"]
-        dsim = Simulator(dw.types, dw.glob, mode=1, form="fused", steps_per_launch=100)
+        dsim = Simulator(dw.types, dw.glob, mode=1, form="fused")
         x0 = torch.from_numpy(dw.state).to(dev)
         x = x0.clone()
         gains = torch.from_numpy(dw.gains).to(dev)
         dwp = torch.from_numpy(dw.wp).to(dev)
+        # the forward's launch shape is the autotuner's, as for the other forms
+        tuned = dsim.autotune(x0, dw.dt, dw.n_steps, gains=gains, wp=dwp)
+        dsim.set_options(form="fused", **tuned)
         tgt = torch.from_numpy(dw.extra["target"]).to(dev)
         ckpt = torch.empty((dw.n_steps // K, 40, dw.n), device=dev)
         gfin = torch.empty((30, dw.n), device=dev)
@@ -365,7 +368,7 @@ def fwd_bwd_form(torch, dev, timed, N):
         bwd_bytes = dw.n * dw.n_steps * (2 * 30 * 4 + 40 * 4 / K)
         gbs = bwd_bytes / (ms_b * 1e-3) / 1e9
         res[key] = {"agent_steps_per_s": dw.n * dw.n_steps / (ms_fb * 1e-3), "n_agents": dw.n,
-                    "sim_steps": dw.n_steps, "ckpt_every": K, "fwd_ms": ms_f,
+                    "sim_steps": dw.n_steps, "ckpt_every": K, "fwd_launch_shape": tuned, "fwd_ms": ms_f,
                     "fwd_bwd_ms": ms_fb, "bwd_ms": ms_b,
                     "bwd_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                      "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
