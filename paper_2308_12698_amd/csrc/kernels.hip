@@ -15,6 +15,11 @@
  *   GAINS per-agent controller gains;
  *   CKPT  checkpoints every ckpt_every steps for the adjoint;
  *   PERM  processing order (agents grouped by type).
+ * k_adjoint: reverse sweep of a checkpointed rollout, one agent per lane,
+ * each segment recomputed into a per-wave tape and then reversed;
+ * k_adjoint_pipe: the same sweep for small swarms, a recomputing and a
+ * reversing wave per 64 agents.  k_block_hist / k_scatter: the processing
+ * order by type.  k_count_nonfinite: agents with a NaN or infinite row.
  * No MFMA: nothing in a quadrotor step is a dense contraction.
  */
 #include "kernels.h"
