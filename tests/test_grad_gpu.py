@@ -138,8 +138,9 @@ def test_adjoint_random_cotangent_all_rows(oracle, torch_dev):
 
 
 def test_checkpoint_interval_does_not_change_the_gradient(torch_dev):
-    """Recomputation from checkpoints is exact: K = 10, 50 and one segment of
-    all steps give bitwise the same gradient."""
+    """Recomputation from checkpoints is exact: K = 1, 7 (a short last
+    segment, an odd number of segments), 10, 50 and one segment of all steps
+    give bitwise the same gradient."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
     sw = I.config4(n=1000, n_steps=200)
@@ -147,10 +148,10 @@ def test_checkpoint_interval_does_not_change_the_gradient(torch_dev):
     wp = torch.from_numpy(sw.wp).to(dev)
     lam = torch.from_numpy(np.random.default_rng(1).normal(size=(30, sw.n)).astype(np.float32)).to(dev)
     outs = []
-    for K in (10, 50, 200):
+    for K in (10, 1, 7, 50, 200):
         sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
         x = torch.from_numpy(sw.state).to(dev)
-        ckpt = torch.empty((200 // K, 40, sw.n), device=dev)
+        ckpt = torch.empty((-(-200 // K), 40, sw.n), device=dev)
         sim.step(x, 200, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
         gx0, gg = sim.step_backward(ckpt, K, 200, sw.dt, lam, gains=gains, wp=wp)
         torch.cuda.synchronize()
