@@ -94,6 +94,18 @@ def test_open_loop_1000_agents_1000_steps(oracle, torch_dev, form):
     assert np.array_equal(got[36:], sw.state[36:].astype(np.float64))
 
 
+def test_open_loop_full_size_every_agent(oracle, torch_dev):
+    """The open-loop swarm at 1,048,576 agents, 1,000 steps, in the plain
+    form (1,000 launches) and the fused form: the two agree bit for bit and
+    every agent matches the oracle."""
+    sw = I.config0(n=1 << 20)
+    plain = gpu_rollout(torch_dev, sw, 1000, form="plain", block=128)
+    fused = gpu_rollout(torch_dev, sw, 1000, form="fused", steps_per_launch=250)
+    assert np.array_equal(plain, fused)
+    ref = oracle_rollout(oracle, sw, 1000)
+    assert_parity(fused, ref, sw, OPEN_LOOP_GROUPS)
+
+
 @pytest.mark.parametrize("form", ["plain", "fused"])
 def test_closed_loop_5000_agents_1000_steps(oracle, torch_dev, form):
     sw = I.config1()
