@@ -212,6 +212,27 @@ def test_heterogeneous_batch_matches_oracle(oracle, torch_dev):
         assert_parity(got, ref, sw)
 
 
+def test_heterogeneous_full_size_every_agent(oracle, torch_dev):
+    """The full heterogeneous swarm (1,007,616 agents, 8 types) for its
+    first 1,000 steps in the type order, one launch: every agent against the
+    oracle (about 1e9 FP64 agent-steps on the host)."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config3()
+    sim = Simulator(sw.types, sw.glob, mode=1, form="fused", steps_per_launch=1000)
+    st = _dev(torch, dev, sw.state)
+    ti = _dev(torch, dev, sw.type_idx)
+    perm = sim.order_by_type(ti)
+    sim.step(st, 1000, sw.dt, type_idx=ti, perm=perm, wp=_dev(torch, dev, sw.wp),
+             resample_every=sw.resample_every)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy().astype(np.float64)
+    sim.close()
+    assert np.isfinite(got).all()
+    ref = oracle_rollout(oracle, sw, 1000)
+    assert_parity(got[:30], ref, sw)
+
+
 def test_hover_fixed_point_on_gpu(torch_dev):
     """wp = p, level, at rest, rotors at the reference speed: nothing moves
     beyond FP32 rounding of the hover balance."""
