@@ -64,8 +64,10 @@ def sample(n, k=64, seed=4):
 
 
 def test_adjoint_matches_dual_number_gradient(oracle, diff_run):
+    """8,192 of the 65,536 agents against the reference's dual numbers
+    (a few seconds of host time for 39-direction duals)."""
     sw = diff_run["sw"]
-    idx = sample(sw.n)
+    idx = sample(sw.n, k=8192)
     sub = I.subset(sw, idx)
     fin, jac = oracle.jacobian(sub.state, sub.types, sub.glob, sub.dt, sub.n_steps, wp=sub.wp,
                                gains=sub.gains)
