@@ -280,8 +280,8 @@ def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
     larger ones one agent per thread.  An agent's gradient must not depend
     on which: 4,096 agents alone (pipelined) against the same agents at the
     front of a 262,144-agent swarm (one per thread), bit for bit; with step
-    budgets ending inside segments and the type order in the heterogeneous
-    case."""
+    budgets ending inside segments, the type order and dead agents in the
+    heterogeneous case."""
     torch, dev = torch_dev
     import ctypes as C
     from paper_2308_12698_amd import _lib as L
@@ -289,8 +289,9 @@ def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
     K, n_steps = 50, 150
     small = I.config4(n=4096, n_steps=n_steps)
     types = [small.types[0]]
-    ti_small = None
+    ti_small = alive_small = None
     if het:
+        alive_small = (np.random.default_rng(9).random(small.n) > 0.1).astype(np.uint8)
         types = [dict(t, budget=b) for t, b in zip(I.hetero_types(), (37, 150, 75, 120, 149, 50, 99, 1))]
         ti_small = np.random.default_rng(7).integers(0, len(types), small.n).astype(np.uint8)
     reps = 64
@@ -301,17 +302,20 @@ def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
         x = torch.from_numpy(tile(small.state)).to(dev)
         gains = torch.from_numpy(tile(small.gains)).to(dev)
         wp = torch.from_numpy(tile(small.wp)).to(dev)
-        ti = perm = None
+        ti = perm = alive = None
         if het:
             ti = torch.from_numpy(tile(ti_small)).to(dev)
             perm = sim.order_by_type(ti)
+            alive = torch.from_numpy(tile(alive_small)).to(dev)
         ckpt = torch.empty((n_steps // K, 40, n), device=dev)
-        sim.step(x, n_steps, small.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K, type_idx=ti, perm=perm)
+        sim.step(x, n_steps, small.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K, type_idx=ti, perm=perm,
+                 alive=alive)
         seed = torch.from_numpy(tile(np.random.default_rng(8).normal(size=(30, small.n)).astype(np.float32))).to(dev)
         pp = L.Params(C.c_void_p(ti.data_ptr()) if het else None, C.c_void_p(perm.data_ptr()) if het else None,
                       C.c_void_p(gains.data_ptr()), n, None)
         ws = int(sim._lib.potato_backward_workspace_bytes(sim._h, C.byref(pp), n, K))
-        gx0, gg = sim.step_backward(ckpt, K, n_steps, small.dt, seed, gains=gains, wp=wp, type_idx=ti, perm=perm)
+        gx0, gg = sim.step_backward(ckpt, K, n_steps, small.dt, seed, gains=gains, wp=wp, type_idx=ti, perm=perm,
+                                    alive=alive)
         torch.cuda.synchronize()
         runs.append((ws, gx0[:, :small.n].cpu().numpy(), gg[:, :small.n].cpu().numpy()))
         sim.close()
@@ -320,3 +324,8 @@ def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
     assert runs[1][0] % (tape_per_thread * 256) == 0                   # one agent per thread, 256-thread blocks
     assert np.isfinite(runs[0][1]).all() and np.abs(runs[0][2]).max() > 0
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    if het:
+        # dead agents: the cotangent passes through unchanged, no gain gradient
+        dead = alive_small == 0
+        seed0 = np.random.default_rng(8).normal(size=(30, small.n)).astype(np.float32)
+        assert np.array_equal(runs[0][1][:, dead], seed0[:, dead]) and not runs[0][2][:, dead].any()
