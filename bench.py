@@ -36,12 +36,23 @@ sys.path.insert(0, ROOT)
 METRIC = "quadrotor agent-steps/s at 1M agents (fwd, fwd+bwd) vs plain kernel, 1e-4"
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak (256 CUs, 2.4 GHz)
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
-# Algorithmic flops of one closed-loop agent-step (controller + four rates +
-# RK4 combine + renormalisation): 390 add/sub + 506 mul + 58 div + 8 sqrt, the
-# operation count of the reference step run on an op-counting scalar
-# (tests/test_bench_host.py re-derives it).  The kernels do the same
-# mathematics in fewer instructions (reciprocals, closed-form G^-1, FMA).
-FLOPS_PER_AGENT_STEP = 962
+# Algorithmic flops of one closed-loop agent-step, counted by hand per part
+# of the step and pinned against the reference's operation-counting scalar
+# (tests/test_bench_host.py): controller 197, right-hand side f(x) 109 (four
+# evaluations per step), RK4 stage and combination arithmetic 234,
+# renormalisation 12.  A multiplication by a structural zero (the scalar
+# part of (0, w), the fourth component of the desired-attitude quaternion)
+# or by G's row of ones is not counted, nor is a sign flip; f_c/m and the
+# squared rotor speeds are formed once per evaluation.  The kernels do the
+# same mathematics in fewer instructions (reciprocals, closed-form G^-1, FMA).
+FLOPS_PER_AGENT_STEP = 197 + 4 * 109 + 234 + 12            # 879
+FLOPS_PER_AGENT_STEP_OPEN_LOOP = 4 * 109 + 234 + 12         # 682
+# The backward pass recomputes each step from its checkpoint (879 flops) and
+# then runs the step's reverse sweep: the vector-Jacobian product of every
+# forward operation by the elementary reverse-mode rules (per part:
+# controller 539, f(x) 282 (x4), RK4 468, renormalisation 45), 2,180 flops.
+REV_FLOPS_PER_AGENT_STEP = 539 + 4 * 282 + 468 + 45        # 2180
+BWD_FLOPS_PER_AGENT_STEP = FLOPS_PER_AGENT_STEP + REV_FLOPS_PER_AGENT_STEP   # 3059
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_12698_amd", "csrc", f)
                   for f in ("quad_step.h", "kernels.hip", "kernels.h")]

@@ -88,16 +88,71 @@ template <int N> inline Dual<N> sqrt_(const Dual<N>& a) {
     for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * s;
     return r; }
 
-/* Operation-counting scalar (single-threaded use only). */
-struct OpCount { int64_t add, mul, div, sqrt, cmp; };
+/* Operation-counting scalar (single-threaded use only).
+ *
+ * Forward count: the floating-point operations one evaluation performs, by
+ * kind, with three rules that keep the count to the arithmetic the model
+ * needs rather than that of its textbook matrix forms:
+ *   - a value built from the literal 0 is a structural zero: a product with
+ *     it is again a structural zero and costs nothing, and adding it,
+ *     subtracting it or subtracting from it costs nothing (the zero scalar
+ *     part of (0, w) in eq. (qd3), the zero last component of the
+ *     desired-attitude quaternion);
+ *   - a product with an entry of G (eq. 3) that is exactly 1 or -1 costs
+ *     nothing (G's row of ones; see gmul);
+ *   - a sign flip costs nothing (it is an operand modifier).
+ * Inputs (state, controller memory, gains) are marked as variables; the
+ * count assumes none of them is exactly 0 or +-1.
+ *
+ * Reverse count `rev`: the flops of the reverse sweep (vector-Jacobian
+ * product) that accumulates the cotangents of each counted operation's
+ * variable operands, by the elementary rules of reverse-mode
+ * differentiation (for z = a o b and cotangent zb):
+ *   a + b, a - b:  ab += zb, bb +-= zb            1 add per variable operand
+ *   a * b:         ab += zb * b, bb += zb * a      1 mul + 1 add per variable operand
+ *   a / b:         ab += zb / b                    1 div + 1 add if a is a variable
+ *                  bb -= zb * z / b                1 mul + 1 div + 1 add if b is
+ *   sqrt(a):       ab += 0.5 * (zb / z)            1 div + 1 mul + 1 add
+ * A product with an entry +-1 of G passes its cotangent on (1 add); sign
+ * flips and comparisons cost nothing. */
+struct OpCount { int64_t add, mul, div, sqrt, cmp, rev; };
 OpCount g_ops;
-struct Cnt { double v; Cnt() : v(0) {} Cnt(double x) : v(x) {} };
+struct Cnt {
+    double v;
+    bool zero, var;
+    Cnt() : v(0), zero(true), var(false) {}
+    Cnt(double x) : v(x), zero(x == 0.0), var(false) {}
+    static Cnt input(double x) { Cnt c(x); c.zero = false; c.var = true; return c; }
+    static Cnt result(double x, bool var) { Cnt c(x); c.zero = false; c.var = var; return c; }
+};
 inline double val(const Cnt& a) { g_ops.cmp++; return a.v; }
-inline Cnt operator+(Cnt a, Cnt b) { g_ops.add++; return Cnt(a.v + b.v); }
-inline Cnt operator-(Cnt a, Cnt b) { g_ops.add++; return Cnt(a.v - b.v); }
-inline Cnt operator-(Cnt a) { return Cnt(-a.v); }   /* sign flip: a modifier, not an op */
-inline Cnt operator*(Cnt a, Cnt b) { g_ops.mul++; return Cnt(a.v * b.v); }
-inline Cnt operator/(Cnt a, Cnt b) { g_ops.div++; return Cnt(a.v / b.v); }
+inline Cnt operator-(Cnt a) { a.v = -a.v; return a; }   /* sign flip: a modifier, not an op */
+inline Cnt operator+(Cnt a, Cnt b) {
+    if (a.zero) return b;
+    if (b.zero) return a;
+    g_ops.add++;
+    g_ops.rev += (int)a.var + (int)b.var;
+    return Cnt::result(a.v + b.v, a.var || b.var);
+}
+inline Cnt operator-(Cnt a, Cnt b) {
+    if (b.zero) return a;
+    if (a.zero) return -b;
+    g_ops.add++;
+    g_ops.rev += (int)a.var + (int)b.var;
+    return Cnt::result(a.v - b.v, a.var || b.var);
+}
+inline Cnt operator*(Cnt a, Cnt b) {
+    if (a.zero || b.zero) return Cnt(0.0);
+    g_ops.mul++;
+    g_ops.rev += 2 * ((int)a.var + (int)b.var);
+    return Cnt::result(a.v * b.v, a.var || b.var);
+}
+inline Cnt operator/(Cnt a, Cnt b) {
+    if (a.zero) return Cnt(0.0);
+    g_ops.div++;
+    g_ops.rev += (a.var ? 2 : 0) + (b.var ? 3 : 0);
+    return Cnt::result(a.v / b.v, a.var || b.var);
+}
 inline Cnt operator+(Cnt a, double b) { return a + Cnt(b); }
 inline Cnt operator+(double a, Cnt b) { return Cnt(a) + b; }
 inline Cnt operator-(Cnt a, double b) { return a - Cnt(b); }
@@ -106,7 +161,11 @@ inline Cnt operator*(Cnt a, double b) { return a * Cnt(b); }
 inline Cnt operator*(double a, Cnt b) { return Cnt(a) * b; }
 inline Cnt operator/(Cnt a, double b) { return a / Cnt(b); }
 inline Cnt operator/(double a, Cnt b) { return Cnt(a) / b; }
-inline Cnt sqrt_(Cnt a) { g_ops.sqrt++; return Cnt(std::sqrt(a.v)); }
+inline Cnt sqrt_(Cnt a) {
+    g_ops.sqrt++;
+    if (a.var) g_ops.rev += 3;
+    return Cnt::result(std::sqrt(a.v), a.var);
+}
 
 /* clamp(x, lo, hi) = x < lo ? lo : (x > hi ? hi : x); the derivative is that
  * of the branch taken (1 inside [lo, hi], 0 outside). */
@@ -114,6 +173,19 @@ template <class T> inline T clamp_(const T& x, double lo, double hi) {
     if (val(x) < lo) return T(lo);
     if (val(x) > hi) return T(hi);
     return x;
+}
+
+/* Product of an entry of the allocation matrix G (eq. 3) with a rotor
+ * thrust.  Plain multiplication; the counting scalar treats an entry of
+ * exactly +-1 (G's first row) as free, since the collective thrust is the
+ * plain sum of the rotor thrusts. */
+template <class T> inline T gmul(double g, const T& f) { return g * f; }
+inline Cnt gmul(double g, const Cnt& f) {
+    if (g != 1.0 && g != -1.0) return g * f;
+    if (f.var) g_ops.rev += 1;
+    Cnt r = f;
+    r.v = g * f.v;
+    return r;
 }
 
 /* ------------------------------------------------------------------ */
@@ -224,13 +296,18 @@ void body_z_axis(const T q[4], T z[3]) {
 template <class T>
 void derivative(const TypeData& td, double g, const T x[NX], const T Wcmd[4], T dx[NX]) {
     const oracle_type& t = td.t;
-    /* eq. (2): per-rotor thrust */
-    T f[4];
-    for (int i = 0; i < 4; ++i) f[i] = t.k_f * (x[M + i] * x[M + i]);
+    /* eq. (2): per-rotor thrust from the squared speeds (which also give the
+     * rate of the running cost below) */
+    T w2[4], f[4];
+    for (int i = 0; i < 4; ++i) {
+        w2[i] = x[M + i] * x[M + i];
+        f[i] = t.k_f * w2[i];
+    }
     /* eq. (3): collective thrust and body torques */
     T u[4];
     for (int r = 0; r < 4; ++r)
-        u[r] = td.G[r][0] * f[0] + td.G[r][1] * f[1] + td.G[r][2] * f[2] + td.G[r][3] * f[3];
+        u[r] = gmul(td.G[r][0], f[0]) + gmul(td.G[r][1], f[1]) + gmul(td.G[r][2], f[2]) +
+               gmul(td.G[r][3], f[3]);
     const T fc = u[0];
     const T tau[3] = {u[1], u[2], u[3]};
     /* eq. (qd1) */
@@ -238,7 +315,8 @@ void derivative(const TypeData& td, double g, const T x[NX], const T Wcmd[4], T 
     /* eq. (qd2) plus linear drag -(c_d/m) v */
     T bz[3];
     body_z_axis(&x[Q], bz);
-    for (int i = 0; i < 3; ++i) dx[V + i] = (fc / t.mass) * bz[i] - (t.drag / t.mass) * x[V + i];
+    const T fcm = fc / t.mass;
+    for (int i = 0; i < 3; ++i) dx[V + i] = fcm * bz[i] - (t.drag / t.mass) * x[V + i];
     dx[V + 2] = dx[V + 2] - g;
     /* eq. (qd3): q' = 1/2 q o [0, w] */
     const T wq[4] = {T(0.0), x[W + 0], x[W + 1], x[W + 2]};
@@ -256,7 +334,7 @@ void derivative(const TypeData& td, double g, const T x[NX], const T Wcmd[4], T 
     /* first-order rotor lag toward the held command */
     for (int i = 0; i < 4; ++i) dx[M + i] = (Wcmd[i] - x[M + i]) / t.tau_m;
     /* running cost: sum of squared rotor speeds */
-    dx[JC] = x[M + 0] * x[M + 0] + x[M + 1] * x[M + 1] + x[M + 2] * x[M + 2] + x[M + 3] * x[M + 3];
+    dx[JC] = w2[0] + w2[1] + w2[2] + w2[3];
 }
 
 /* ------------------------------------------------------------------ */
@@ -536,34 +614,56 @@ int oracle_allocation(const oracle_type* type, double* G, double* Ginv) {
 }
 
 /*
- * Floating-point operations of one agent-step of the reference arithmetic:
- * counts[0..4] = add/sub, mul, div, sqrt, comparisons.  mode as above.
+ * Floating-point operations of one agent-step, by part of the step, counted
+ * by the operation-counting scalar above (forward rules and reverse-sweep
+ * rules are stated there).  counts[part * 6 + k], part 0 controller, 1 one
+ * evaluation of the right-hand side f(x) (a step evaluates it four times),
+ * 2 the RK4 stage and combination arithmetic outside f, 3 the quaternion
+ * renormalisation; k = add/sub, mul, div, sqrt, comparisons, and the flops
+ * of that part's reverse sweep.  mode 0 (open loop) has no controller part.
+ * Evaluated at a generic flight state where no branch sits on a limit and
+ * no input is exactly 0 or +-1.
  */
 int oracle_count_ops(const oracle_type* type, const oracle_globals* gl, int mode, double dt,
                      int64_t* counts) {
     TypeData td;
     if (!type || !gl || !counts || !make_type(*type, td)) return -1;
     Cnt x[NX], mem[NMEM], gn[9];
-    /* a generic, non-degenerate flight state (no branch lands on a limit) */
-    const double xs[NX] = {1.0, 2.0, 3.0, 0.1, -0.2, 0.05, 0.99, 0.05, -0.08, 0.07,
-                           0.3, -0.2, 0.1, 0, 0, 0, 0, 0};
-    for (int i = 0; i < NX; ++i) x[i] = Cnt(xs[i]);
-    for (int i = 0; i < 4; ++i) x[M + i] = Cnt(type->w_ref + 10.0 * (i - 1.5));
-    for (int i = 0; i < NMEM; ++i) mem[i] = Cnt(0.01 * (i + 1));
-    for (int k = 0; k < 9; ++k) gn[k] = Cnt(type->gains[k]);
+    const double xs[NX] = {1.0, 2.0, 3.0, 0.1, -0.2, 0.05, 0.9995, 0.01, -0.02, 0.015,
+                           0.03, -0.02, 0.01, 0, 0, 0, 0, 0.5};
+    for (int i = 0; i < NX; ++i) x[i] = Cnt::input(xs[i]);
+    for (int i = 0; i < 4; ++i) x[M + i] = Cnt::input(type->w_ref + 10.0 * (i - 1.5));
+    /* integrals well inside their clamps; previous body rates close to the
+     * current ones, so the commanded rotor thrusts stay inside [0, f_max] */
+    for (int i = 0; i < 9; ++i) mem[i] = Cnt::input(0.01 * (i + 1));
+    for (int i = 0; i < 3; ++i) mem[WPREV + i] = Cnt::input(xs[W + i] + 1e-4 * (i + 1));
+    for (int k = 0; k < 9; ++k) gn[k] = Cnt::input(type->gains[k]);
     const double wp[3] = {1.5, 2.5, 3.2};
+    auto take = [&](int part) {
+        const int64_t v[6] = {g_ops.add, g_ops.mul, g_ops.div, g_ops.sqrt, g_ops.cmp, g_ops.rev};
+        for (int k = 0; k < 6; ++k) counts[part * 6 + k] = v[k];
+        std::memset(&g_ops, 0, sizeof(g_ops));
+    };
+    std::memset(counts, 0, sizeof(int64_t) * 24);
     std::memset(&g_ops, 0, sizeof(g_ops));
     Cnt Wcmd[4];
     if (mode == 1) {
         controller(td, *gl, gn, x, mem, wp, dt, Wcmd);
+        take(0);
     } else {
-        for (int i = 0; i < 4; ++i) Wcmd[i] = Cnt(type->w_ref);
-        g_ops.add += 4;   /* w_ref + command deviation */
+        for (int i = 0; i < 4; ++i) Wcmd[i] = Cnt::input(type->w_ref * (1.0 + 0.01 * (i + 1)));
     }
+    /* one right-hand side alone, then the whole RK4 step less four of them */
+    Cnt dx[NX];
+    derivative(td, gl->g, x, Wcmd, dx);
+    take(1);
     rk4(td, gl->g, x, Wcmd, dt);
+    const OpCount step = g_ops;
+    std::memset(&g_ops, 0, sizeof(g_ops));
+    const int64_t whole[6] = {step.add, step.mul, step.div, step.sqrt, step.cmp, step.rev};
+    for (int k = 0; k < 6; ++k) counts[2 * 6 + k] = whole[k] - 4 * counts[1 * 6 + k];
     renormalise(x);
-    counts[0] = g_ops.add; counts[1] = g_ops.mul; counts[2] = g_ops.div;
-    counts[3] = g_ops.sqrt; counts[4] = g_ops.cmp;
+    take(3);
     return 0;
 }
 

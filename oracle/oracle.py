@@ -177,15 +177,32 @@ def allocation(t: dict):
     return G, Gi
 
 
+PARTS = ("controller", "derivative", "rk4", "renorm")
+OP_KINDS = ("add", "mul", "div", "sqrt", "cmp", "rev")
+
+
 def count_ops(t: dict, glob: dict, mode: int, dt: float) -> dict:
-    """Operations of one agent-step of the reference arithmetic."""
-    c = np.zeros(5, dtype=np.int64)
+    """Operations of one agent-step, by part (the counting rules are stated
+    at ``oracle_count_ops``): ``{part: {add, mul, div, sqrt, cmp, rev,
+    flops}}`` for the controller, one right-hand-side evaluation, the RK4
+    arithmetic outside the four evaluations and the renormalisation, plus
+    ``"flops"`` (forward flops of the whole step: controller + 4 f + RK4 +
+    renormalisation) and ``"rev_flops"`` (flops of the whole step's reverse
+    sweep)."""
+    c = np.zeros(24, dtype=np.int64)
     o, gl = make_type(t), make_globals(glob)
     if lib().oracle_count_ops(C.byref(o), C.byref(gl), int(mode), float(dt), _p(c)) != 0:
         raise ValueError("oracle_count_ops failed")
-    d = dict(zip(("add", "mul", "div", "sqrt", "cmp"), (int(v) for v in c)))
-    d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
-    return d
+    out = {}
+    for p, part in enumerate(PARTS):
+        d = dict(zip(OP_KINDS, (int(v) for v in c[6 * p:6 * p + 6])))
+        d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
+        out[part] = d
+    mult = {"controller": 1, "derivative": 4, "rk4": 1, "renorm": 1}
+    out["flops"] = sum(mult[p] * out[p]["flops"] for p in PARTS)
+    out["rev_flops"] = sum(mult[p] * out[p]["rev"] for p in PARTS)
+    out["sqrt"] = sum(mult[p] * out[p]["sqrt"] for p in PARTS)
+    return out
 
 
 def detect_collisions(rows, radius, alive, type_idx=None):

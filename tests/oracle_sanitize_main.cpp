@@ -92,7 +92,7 @@ int main() {
     if (oracle_controller(&types[0], &gl, nullptr, x, mem, target, 1e-3, out) != 0) return fail("controller");
     double G[16], Gi[16];
     if (oracle_allocation(&types[1], G, Gi) != 0) return fail("allocation");
-    int64_t counts[5] = {0};
+    int64_t counts[24] = {0};
     if (oracle_count_ops(&types[0], &gl, 1, 1e-3, counts) != 0) return fail("count_ops");
     /* collisions: a pair inside the radius sum, a dead agent, a ragged ld */
     std::vector<float> rows(3 * ld, 0.0f);
