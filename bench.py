@@ -53,6 +53,9 @@ FLOPS_PER_AGENT_STEP_OPEN_LOOP = 4 * 109 + 234 + 12         # 682
 # controller 539, f(x) 282 (x4), RK4 468, renormalisation 45), 2,180 flops.
 REV_FLOPS_PER_AGENT_STEP = 539 + 4 * 282 + 468 + 45        # 2180
 BWD_FLOPS_PER_AGENT_STEP = FLOPS_PER_AGENT_STEP + REV_FLOPS_PER_AGENT_STEP   # 3059
+# Rows per agent-step of the adjoint's recomputation tape (written once and
+# read once per agent-step).
+TAPE_ROWS = 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_12698_amd", "csrc", f)
                   for f in ("quad_step.h", "kernels.hip", "kernels.h")]
@@ -111,6 +114,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of known size (for scaling "
                          "HBM byte counters) and exit")
+    ap.add_argument("--shape", default="",
+                    help="block,steps_per_launch,grid_blocks of the headline rollout instead of "
+                         "autotuning (profiler runs at a fixed launch shape)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -140,15 +146,24 @@ def main():
     N, T = sw.n, args.sim_steps
     log(f"inputs: {N} agents, {T} steps, {sw.wp.shape[0]} waypoint epochs")
     state = torch.from_numpy(sw.state).to(dev)
+    # rounding carries of the compensated integrator (the 10,000-step parity
+    # bound needs them); they are read and written once per launch
+    carry = torch.zeros((10, N), dtype=torch.float32, device=dev)
     wp = torch.from_numpy(sw.wp).to(dev)
     sim = Simulator(sw.types, sw.glob, mode=1, form="fused", use_graph=True)
-    tuned = sim.autotune(state, sw.dt, min(1000, T), wp=wp, resample_every=sw.resample_every)
+    if args.shape:
+        b, s_, g = (int(v) for v in args.shape.split(","))
+        tuned = {"block": b, "steps_per_launch": s_, "grid_blocks": g}
+        log(f"launch shape given: {tuned}")
+    else:
+        tuned = sim.autotune(state, sw.dt, min(1000, T), wp=wp, resample_every=sw.resample_every,
+                             carry=carry)
+        log(f"autotuned launch shape: {tuned}")
     sim.set_options(form="fused", use_graph=True, **tuned)
-    log(f"autotuned launch shape: {tuned}")
     launches = -(-T // tuned["steps_per_launch"])
 
     def rollout():
-        sim.step(state, T, sw.dt, wp=wp, resample_every=sw.resample_every)
+        sim.step(state, T, sw.dt, wp=wp, resample_every=sw.resample_every, carry=carry)
 
     for _ in range(args.warmup):
         rollout()
@@ -181,7 +196,7 @@ def main():
     forms = {"fused_graph": {"agent_steps_per_s": value, "rollout_ms": float(np.mean(ev_ms)),
                              "rollout_ms_sd": float(np.std(ev_ms)), "rollouts": len(ev_ms)}}
     if not args.no_extra:
-        forms.update(extra_forms(torch, dev, stream, sim, state, wp, sw, T,
+        forms.update(extra_forms(torch, dev, stream, sim, state, carry, wp, sw, T,
                                  set(args.forms.split(","))))
     sim.close()
 
@@ -206,7 +221,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extra_forms(torch, dev, stream, sim, state, wp, sw, T, which):
+def extra_forms(torch, dev, stream, sim, state, carry, wp, sw, T, which):
     res = {}
     N = sw.n
 
@@ -223,12 +238,13 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, which):
 
     # plain: one launch per step, state round-trips HBM every step
     if "plain" in which:
-        res.update(plain_form(timed, sw, state, wp, N))
+        res.update(plain_form(timed, sw, state, carry, wp, N))
     # fused without the graph (host launches)
     sim.set_options(form="fused", use_graph=False, block=sim.opts.block,
                     steps_per_launch=sim.opts.steps_per_launch, grid_blocks=sim.opts.grid_blocks)
     if "fused_eager" in which:
-        ms = timed(lambda: sim.step(state, 2000, sw.dt, wp=wp, resample_every=sw.resample_every))
+        ms = timed(lambda: sim.step(state, 2000, sw.dt, wp=wp, resample_every=sw.resample_every,
+                                    carry=carry))
         res["fused_eager"] = {"agent_steps_per_s": N * 2000 / (ms * 1e-3), "steps_timed": 2000,
                               "roofline": alu_roofline(N * 2000 / (ms * 1e-3))}
         log(f"fused eager: {res['fused_eager']['agent_steps_per_s']:.4e} agent-steps/s")
@@ -245,26 +261,33 @@ def extra_forms(torch, dev, stream, sim, state, wp, sw, T, which):
     return res
 
 
-def plain_form(timed, sw, state, wp, N):
+def plain_form(timed, sw, state, carry, wp, N):
+    """One launch per step: the state round-trips HBM every step.  Without
+    carries a closed-loop agent-step moves the method's own bytes, 30 rows
+    in and out plus the 3 waypoint rows (252 B); with the compensated
+    integrator's 10 carry rows in and out as well, 332 B."""
     from paper_2308_12698_amd.sim import Simulator
     res = {}
     steps_plain = 1000
     plain = Simulator(sw.types, sw.glob, mode=1, form="plain", use_graph=True)
-    ms = timed(lambda: plain.step(state, steps_plain, sw.dt, wp=wp, resample_every=sw.resample_every))
-    plain.close()
-    bytes_step = (40 + 40 + 3) * 4      # state rows in and out + waypoint
-    launch_ms = ms / steps_plain
-    gbs = bytes_step * N / (launch_ms * 1e-3) / 1e9
-    res["plain"] = {"agent_steps_per_s": N * steps_plain / (ms * 1e-3), "steps_timed": steps_plain,
+    for key, c, bytes_step in (("plain", None, (30 + 30 + 3) * 4),
+                               ("plain_carry", carry, (40 + 40 + 3) * 4)):
+        ms = timed(lambda: plain.step(state, steps_plain, sw.dt, wp=wp, resample_every=sw.resample_every,
+                                      carry=c))
+        launch_ms = ms / steps_plain
+        gbs = bytes_step * N / (launch_ms * 1e-3) / 1e9
+        res[key] = {"agent_steps_per_s": N * steps_plain / (ms * 1e-3), "steps_timed": steps_plain,
                     "avg_launch_ms": launch_ms,
                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                  "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                                  "bytes_per_agent_step": bytes_step,
-                                 "traffic": measured_traffic("plain")}}
+                                 "traffic": measured_traffic(key)}}
+        log(f"{key}: {res[key]['agent_steps_per_s']:.4e} agent-steps/s, {gbs:.0f} GB/s "
+            f"({bytes_step} B per agent-step)")
+    plain.close()
     res["plain"]["hbm_reference"] = hbm_reference(timed, state)
-    log(f"plain: {res['plain']['agent_steps_per_s']:.4e} agent-steps/s, {gbs:.0f} GB/s "
-        f"(torch copy {res['plain']['hbm_reference']['torch_copy_GBps']:.0f}, "
-        f"triad {res['plain']['hbm_reference']['torch_triad_GBps']:.0f} GB/s)")
+    log(f"torch copy {res['plain']['hbm_reference']['torch_copy_GBps']:.0f}, "
+        f"triad {res['plain']['hbm_reference']['torch_triad_GBps']:.0f} GB/s")
     return res
 
 
@@ -298,8 +321,9 @@ def hetero_form(torch, dev, timed):
     work = sum(int(c) * hw.types[t]["budget"] for t, c in enumerate(hw.extra["counts"]))
     for label, perm in (("hetero_unordered", None), ("hetero", hsim.order_by_type(ti))):
         s0 = hs.clone()
+        c0 = torch.zeros((10, hw.n), dtype=torch.float32, device=dev)
         ms = timed(lambda: hsim.step(s0, hw.n_steps, hw.dt, type_idx=ti, perm=perm, wp=hwp,
-                                     resample_every=hw.resample_every), reps=1)
+                                     resample_every=hw.resample_every, carry=c0), reps=1)
         res[label] = {"agent_steps_per_s": work / (ms * 1e-3), "agent_steps": work,
                       "n_agents": hw.n, "rollout_ms": ms,
                       "roofline": alu_roofline(work / (ms * 1e-3))}
@@ -346,10 +370,11 @@ def fwd_bwd_form(torch, dev, timed, N):
         dsim = Simulator(dw.types, dw.glob, mode=1, form="fused")
         x0 = torch.from_numpy(dw.state).to(dev)
         x = x0.clone()
+        carry = torch.zeros((10, dw.n), dtype=torch.float32, device=dev)
         gains = torch.from_numpy(dw.gains).to(dev)
         dwp = torch.from_numpy(dw.wp).to(dev)
         # the forward's launch shape is the autotuner's, as for the other forms
-        tuned = dsim.autotune(x0, dw.dt, dw.n_steps, gains=gains, wp=dwp)
+        tuned = dsim.autotune(x0, dw.dt, dw.n_steps, gains=gains, wp=dwp, carry=carry)
         dsim.set_options(form="fused", **tuned)
         tgt = torch.from_numpy(dw.extra["target"]).to(dev)
         ckpt = torch.empty((dw.n_steps // K, 40, dw.n), device=dev)
@@ -358,7 +383,8 @@ def fwd_bwd_form(torch, dev, timed, N):
 
         def fwd():
             x.copy_(x0)
-            dsim.step(x, dw.n_steps, dw.dt, gains=gains, wp=dwp, ckpt=ckpt, ckpt_every=K)
+            carry.zero_()
+            dsim.step(x, dw.n_steps, dw.dt, gains=gains, wp=dwp, ckpt=ckpt, ckpt_every=K, carry=carry)
 
         def bwd():
             gfin.zero_()
@@ -372,18 +398,25 @@ def fwd_bwd_form(torch, dev, timed, N):
         ms_f = timed(fwd)
         ms_fb = timed(lambda: (fwd(), bwd()))
         key = "fwd_bwd" if n_agents == N else "fwd_bwd_65536"
-        # backward pass roofline: its algorithmic HBM traffic is the recomputation
-        # tape (30 rows written and read per agent-step) plus one 40-row
-        # checkpoint read per segment
+        # backward pass roofline: the algorithm is ALU bound (per agent-step a
+        # recomputation of the step from its checkpoint and the step's reverse
+        # sweep, BWD_FLOPS_PER_AGENT_STEP; its only algorithmic HBM traffic is
+        # one 40-row checkpoint read per segment and the cotangents).  The
+        # implementation's recomputation tape (TAPE_ROWS written and read per
+        # agent-step) is reported beside it.
         ms_b = ms_fb - ms_f
-        bwd_bytes = dw.n * dw.n_steps * (2 * 30 * 4 + 40 * 4 / K)
-        gbs = bwd_bytes / (ms_b * 1e-3) / 1e9
+        bwd_tf = BWD_FLOPS_PER_AGENT_STEP * dw.n * dw.n_steps / (ms_b * 1e-3) / 1e12
+        tape_bytes = 2 * TAPE_ROWS * 4 + 40 * 4 / K
+        gbs = dw.n * dw.n_steps * tape_bytes / (ms_b * 1e-3) / 1e9
         res[key] = {"agent_steps_per_s": dw.n * dw.n_steps / (ms_fb * 1e-3), "n_agents": dw.n,
                     "sim_steps": dw.n_steps, "ckpt_every": K, "fwd_launch_shape": tuned, "fwd_ms": ms_f,
                     "fwd_bwd_ms": ms_fb, "bwd_ms": ms_b,
-                    "bwd_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                                     "bytes_per_agent_step": round(2 * 30 * 4 + 40 * 4 / K, 1)}}
+                    "fwd_roofline": alu_roofline(dw.n * dw.n_steps / (ms_f * 1e-3)),
+                    "bwd_roofline": {"bound": "alu", "achieved": round(bwd_tf, 3), "peak": PEAK_FP32_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": round(bwd_tf / PEAK_FP32_TFLOPS, 4),
+                                     "flops_per_agent_step": BWD_FLOPS_PER_AGENT_STEP},
+                    "bwd_tape": {"GBps": round(gbs, 1), "frac_of_hbm": round(gbs / PEAK_HBM_GBS, 4),
+                                 "bytes_per_agent_step": round(tape_bytes, 1)}}
         log(f"{key}: {res[key]['agent_steps_per_s']:.4e} agent-steps/s (fwd {ms_f:.2f} ms, "
             f"fwd+bwd {ms_fb:.2f} ms)")
         dsim.close()
@@ -403,6 +436,7 @@ def pipeline_form(torch, dev, sim, sw, T, snap_every=500):
     per = es // snap_every
     x0 = torch.from_numpy(sw.state).to(dev)
     state = x0.clone()
+    carry = torch.zeros((10, N), dtype=torch.float32, device=dev)
     wp = torch.from_numpy(sw.wp).to(dev)
     pipe = Pipe(sim, N)
     snaps = torch.empty((E, per, 3, N), dtype=torch.float32, pin_memory=True)
@@ -410,10 +444,11 @@ def pipeline_form(torch, dev, sim, sw, T, snap_every=500):
 
     def pipelined():
         state.copy_(x0)
+        carry.zero_()
         base = pipe.n_snaps
         pipe.push(sw.wp[0])
         for e in range(E):
-            pipe.run(state, es, sw.dt, snap_every=snap_every, snaps=snaps[e])
+            pipe.run(state, es, sw.dt, snap_every=snap_every, snaps=snaps[e], carry=carry)
             if e + 1 == E:
                 break
             if e == 0:
@@ -427,7 +462,8 @@ def pipeline_form(torch, dev, sim, sw, T, snap_every=500):
 
     def resident():
         state.copy_(x0)
-        sim.step(state, E * es, sw.dt, wp=wp, resample_every=es)
+        carry.zero_()
+        sim.step(state, E * es, sw.dt, wp=wp, resample_every=es, carry=carry)
         torch.cuda.synchronize()
 
     out = {}
@@ -471,17 +507,20 @@ def sweep(sizes=SWEEP_SIZES, warm=500, rounds=2000, execs=3, cpu_budget_s=4.0):
         wp = torch.from_numpy(sw.wp).to(dev)
         for form in ("plain", "fused"):
             state = torch.from_numpy(sw.state).to(dev)
+            # the fused form keeps the rounding carries as the headline rollout
+            # does; the plain form moves the state rows only
+            carry = torch.zeros((10, n), dtype=torch.float32, device=dev) if form == "fused" else None
             sim = Simulator(sw.types, sw.glob, mode=1, form=form, use_graph=True)
             if form == "fused":
-                tuned = sim.autotune(state, sw.dt, 1000, wp=wp)
+                tuned = sim.autotune(state, sw.dt, 1000, wp=wp, carry=carry)
                 sim.set_options(form="fused", use_graph=True, **tuned)
-            sim.step(state, warm, sw.dt, wp=wp)
-            sim.step(state, rounds, sw.dt, wp=wp)     # captures the graph that is timed below
+            sim.step(state, warm, sw.dt, wp=wp, carry=carry)
+            sim.step(state, rounds, sw.dt, wp=wp, carry=carry)     # captures the graph timed below
             ms = []
             for e in range(execs):
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(stream)
-                sim.step(state, rounds, sw.dt, wp=wp)
+                sim.step(state, rounds, sw.dt, wp=wp, carry=carry)
                 b.record(stream)
                 torch.cuda.synchronize()
                 ms.append(a.elapsed_time(b) / rounds)
@@ -559,8 +598,10 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000):
-    """FP64 reference on the host cores, bounded sample of the same workload."""
+def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000, single_agents=16384, single_steps=1000):
+    """FP64 reference on the host cores, bounded samples of the same workload:
+    all threads (up to 16) on the first sample_agents agents x sample_steps
+    steps, and one thread on the first single_agents agents x single_steps."""
     from paper_2308_12698_amd import inputs as I
     threads = max(1, min(16, os.cpu_count() or 1))
     sub = I.subset(sw, np.arange(min(sample_agents, sw.n)))
@@ -569,10 +610,19 @@ def cpu_baseline(O, sw, sample_agents=262144, sample_steps=4000):
               resample_every=sub.resample_every, threads=threads)
     dt = time.perf_counter() - t0
     v = sub.n * sample_steps / dt
-    log(f"cpu baseline: {v:.4e} agent-steps/s on {threads} threads ({dt:.1f} s)")
+    one = I.subset(sw, np.arange(min(single_agents, sw.n)))
+    t0 = time.perf_counter()
+    O.rollout(one.state, one.types, one.glob, 1, one.dt, single_steps, wp=one.wp,
+              resample_every=one.resample_every, threads=1)
+    dt1 = time.perf_counter() - t0
+    v1 = one.n * single_steps / dt1
+    log(f"cpu baseline: {v:.4e} agent-steps/s on {threads} threads ({dt:.1f} s), "
+        f"{v1:.4e} on 1 thread ({dt1:.1f} s)")
     return {"value": v, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sub.n} agents of the same swarm x {sample_steps} steps, FP64, "
                       f"{dt:.1f} s wall",
+            "single_thread": {"value": v1, "cores": 1,
+                              "sample": f"first {one.n} agents x {single_steps} steps, FP64, {dt1:.1f} s wall"},
             "host": host_cpu()}
 
 

@@ -39,7 +39,7 @@ class Options(C.Structure):
 
 
 class State(C.Structure):
-    _fields_ = [("rows", C.c_void_p), ("ld", C.c_int64)]
+    _fields_ = [("rows", C.c_void_p), ("ld", C.c_int64), ("carry", C.c_void_p), ("carry_ld", C.c_int64)]
 
 
 class Params(C.Structure):
@@ -100,7 +100,7 @@ def load():
     L.potato_pipe_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64)]
     L.potato_pipe_destroy.argtypes = [P]
     L.potato_count_nonfinite.argtypes = [P, P, I64, P, P]
-    L.potato_last_error.argtypes = []
+    L.potato_last_error.argtypes = [P]
     L.potato_last_error.restype = C.c_char_p
     L.potato_version.argtypes = []
     L.potato_version.restype = C.c_char_p
@@ -116,7 +116,7 @@ def load():
 
 def check(status: int):
     if status != OK:
-        raise PotatoError(status, load().potato_last_error().decode())
+        raise PotatoError(status, load().potato_last_error(None).decode())
 
 
 def make_type_params(types) -> C.Array:

@@ -187,6 +187,8 @@ potato_status validate_step(const potato_ctx* ctx, const potato_state* st, const
     if (n < 1) return fail(POTATO_EINVAL, "n_agents must be >= 1");
     if (n > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be <= 2^30");
     if (st->ld < n) return fail(POTATO_EINVAL, "state.ld (%lld) < n_agents (%lld)", (long long)st->ld, (long long)n);
+    if (st->carry && st->carry_ld < n)
+        return fail(POTATO_EINVAL, "state.carry_ld (%lld) < n_agents (%lld)", (long long)st->carry_ld, (long long)n);
     if (n_steps < 0) return fail(POTATO_EINVAL, "n_steps must be >= 0");
     if (!std::isfinite(dt) || !(dt > 0.0f)) return fail(POTATO_EINVAL, "dt must be finite and > 0");
     if (cm->ld < n) return fail(POTATO_EINVAL, "cmds.ld < n_agents");
@@ -199,6 +201,9 @@ potato_status validate_step(const potato_ctx* ctx, const potato_state* st, const
     }
     if (pp->gains && pp->gains_ld < n) return fail(POTATO_EINVAL, "params.gains_ld < n_agents");
     if (ckpt && ckpt_every < 1) return fail(POTATO_EINVAL, "ckpt_every must be >= 1 when ckpt is given");
+    if (ckpt && !st->carry)
+        return fail(POTATO_EINVAL, "checkpoints need the rounding carries (state.carry): the adjoint replays the "
+                                   "compensated integrator");
     if (ckpt && ctx->opts.form == POTATO_FORM_PLAIN)
         return fail(POTATO_EUNSUPPORTED, "checkpoints need the fused form");
     if (pp->type == nullptr && pp->perm != nullptr)
@@ -214,8 +219,10 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     P.v.gains = ctx->opts.mode == POTATO_CLOSED_LOOP && pp->gains != nullptr;
     P.v.ckpt = ckpt != nullptr;
     P.v.perm = P.v.het && pp->perm != nullptr;
+    P.v.carry = st->carry != nullptr;
     StepArgs& a = P.a;
     a.rows = st->rows; a.ld = st->ld; a.n = n;
+    a.carry = st->carry; a.carry_ld = st->carry ? st->carry_ld : 0;
     a.type = pp->type; a.perm = P.v.perm ? pp->perm : nullptr;
     a.gains = P.v.gains ? pp->gains : nullptr; a.gains_ld = pp->gains_ld;
     a.motor_cmd = cm->motor_cmd; a.wp = cm->wp; a.cmd_ld = cm->ld;
@@ -267,7 +274,8 @@ std::vector<int64_t> graph_key(const Plan& P, int32_t n_steps, float dt) {
     std::memcpy(&dtbits, &dt, 4);
     return {(int64_t)a.rows, a.ld, a.n, (int64_t)a.type, (int64_t)a.perm, (int64_t)a.gains, a.gains_ld,
             (int64_t)a.motor_cmd, (int64_t)a.wp, a.cmd_ld, a.n_epochs, a.resample, a.step0, n_steps,
-            dtbits, (int64_t)a.ckpt, a.ckpt_every, P.block, P.steps, P.grid, P.v.mode, (int64_t)a.alive};
+            dtbits, (int64_t)a.ckpt, a.ckpt_every, P.block, P.steps, P.grid, P.v.mode, (int64_t)a.alive,
+            (int64_t)a.carry, a.carry_ld};
 }
 
 }  // namespace
@@ -423,15 +431,19 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
     if (probe_steps < 1) return fail(POTATO_EINVAL, "probe_steps must be >= 1");
     std::lock_guard<std::mutex> g(ctx->mu);
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    /* scratch copy of the state rows and, if given, of the carries */
     const size_t bytes = sizeof(float) * kRows * (size_t)state->ld;
+    const size_t cbytes = state->carry ? sizeof(float) * kCarryRows * (size_t)state->carry_ld : 0;
     float* scratch = nullptr;
-    hipError_t e = hipMalloc(&scratch, bytes);
+    hipError_t e = hipMalloc(&scratch, bytes + cbytes);
     if (e != hipSuccess) return fail(POTATO_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
     e = hipMemcpyAsync(scratch, state->rows, bytes, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess && cbytes)
+        e = hipMemcpyAsync(scratch + kRows * state->ld, state->carry, cbytes, hipMemcpyDeviceToDevice, hs);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
-    potato_state ss{scratch, state->ld};
+    potato_state ss{scratch, state->ld, state->carry ? scratch + kRows * state->ld : nullptr, state->carry_ld};
     int n_cu = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
     Tuned win{256, 100, 0};
@@ -670,7 +682,7 @@ potato_status potato_count_nonfinite(potato_ctx* ctx, const potato_state* state,
     return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_count_nonfinite launch");
 }
 
-const char* potato_last_error(void) { return g_err.c_str(); }
+const char* potato_last_error(const potato_ctx*) { return g_err.c_str(); }
 
 const char* potato_version(void) { return "potato-mi355x 0.1 (gfx950)"; }
 

@@ -11,7 +11,9 @@
 
 namespace potato {
 
-constexpr int kRows = 40;   /* state rows per agent, see include/potato.h */
+constexpr int kRows = 30;       /* state rows per agent, see include/potato.h */
+constexpr int kCarryRows = 10;  /* rounding-carry rows per agent */
+constexpr int kCkptRows = 40;   /* checkpoint slot: the state, then its carries */
 
 /* Largest agent count: agent index times 4 (a byte offset into a row) must
  * fit 32 bits, which the kernels' row addressing relies on. */
@@ -22,6 +24,8 @@ constexpr int64_t kMaxAgents = int64_t(1) << 30;
 struct StepArgs {
     float* rows;                 /* [kRows][ld] */
     int64_t ld;
+    float* carry;                /* [kCarryRows][carry_ld] or null (uncompensated) */
+    int64_t carry_ld;
     int64_t n;                   /* agents (lanes) */
     const uint8_t* type;         /* [ld] or null */
     const int32_t* perm;         /* [n] or null */
@@ -35,7 +39,7 @@ struct StepArgs {
     int64_t step0;               /* global index of this launch's first step */
     int32_t n_steps;             /* steps in this launch */
     int32_t k0;                  /* call-relative index of this launch's first step */
-    float* ckpt;                 /* [slots][kRows][ld] or null */
+    float* ckpt;                 /* [slots][kCkptRows][ld] or null (needs carry) */
     int32_t ckpt_every;
     int32_t n_types;
     const TypeConst* table;      /* device [n_types] */
@@ -51,11 +55,12 @@ struct Variant {
     bool gains;      /* per-agent gains */
     bool ckpt;       /* write checkpoints */
     bool perm;       /* processing order */
+    bool carry;      /* rounding carries kept in a carry buffer */
 };
 
 /* Arguments of the adjoint (reverse sweep) launch. */
 struct AdjArgs {
-    const float* ckpt;           /* [slots][kRows][ld] from the forward call */
+    const float* ckpt;           /* [slots][kCkptRows][ld] from the forward call */
     int64_t ld;
     int64_t n;
     const uint8_t* type;

@@ -1,9 +1,9 @@
 /*
  * kernels.hip -- gfx950 kernels of the batched quadrotor step.
  *
- * k_rollout: one agent per lane, its 40-float state loaded once into
- * registers (coalesced structure-of-arrays rows), advanced n_steps time
- * steps, stored once.  With n_steps = 1 and one agent per thread this is
+ * k_rollout: one agent per lane, its 30-float state (and, with CARRY, its
+ * 10 rounding carries) loaded once into registers (coalesced
+ * structure-of-arrays rows), advanced n_steps time steps, stored once.  With n_steps = 1 and one agent per thread this is
  * the plain per-step form (HBM bound: the state round-trips every step);
  * with many steps per launch it is the fused form (VALU bound).  A
  * grid-stride loop lets a launch use a persistent grid.  Optional pieces
@@ -13,8 +13,11 @@
  *         paper runs one process per type, Sec. II-A; here all types share
  *         one launch);
  *   GAINS per-agent controller gains;
- *   CKPT  checkpoints every ckpt_every steps for the adjoint;
- *   PERM  processing order (agents grouped by type).
+ *   CKPT  checkpoints every ckpt_every steps for the adjoint (always with
+ *         CARRY: the adjoint replays the compensated integrator);
+ *   PERM  processing order (agents grouped by type);
+ *   CARRY rounding carries of p, v, J and the position-loop integral kept
+ *         in the caller's carry rows (without: uncompensated updates).
  * k_adjoint: reverse sweep of a checkpointed rollout, one agent per lane,
  * each segment recomputed into a per-wave tape and then reversed;
  * k_adjoint_pipe: the same sweep for small swarms, a recomputing and a
@@ -70,8 +73,9 @@ __device__ __forceinline__ void stage_constants(const TypeConst* table, int n_ty
     __syncthreads();
 }
 
-template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
+template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY>
 __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
+    static_assert(CARRY || !CKPT, "checkpoints hold the carries");
     extern __shared__ float4 lds_raw[];
     Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
     TypeConst* tab = reinterpret_cast<TypeConst*>(lds_raw + (sizeof(Limits) + 15) / 16);
@@ -95,6 +99,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         const TypeConst& c = HET ? tab[type_entry(A.type, i, A.n_types)] : tab[0];
         float* const R = A.rows;
         auto row = [&](int k) -> float& { return elem(uniform(R + k * ld), bo); };
+        auto crow = [&](int k) -> float& { return elem(uniform(A.carry + k * A.carry_ld), bo); };
         /* position snapshot (rows 0-2, [3][n]) written straight to mapped host
          * memory; never requested together with checkpoints, and left out of
          * those variants (whose step loop has no scalar registers to spare) */
@@ -126,7 +131,10 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 #pragma unroll
         for (int k = 0; k < 4; ++k) { a.q[k] = row(6 + k); a.d[k] = row(13 + k); }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { a.p_lo[k] = row(30 + k); a.v_lo[k] = row(33 + k); }
+        for (int k = 0; k < 3; ++k) {
+            a.p_lo[k] = CARRY ? crow(k) : 0.0f;
+            a.v_lo[k] = CARRY ? crow(3 + k) : 0.0f;
+        }
         if (MODE == 1) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -134,9 +142,9 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
                 a.ir[k] = row(23 + k); a.wprev[k] = row(26 + k);
             }
             a.J = row(29);
-            a.J_lo = row(36);
+            a.J_lo = CARRY ? crow(6) : 0.0f;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) a.ip_lo[k] = row(37 + k);
+            for (int k = 0; k < 3; ++k) a.ip_lo[k] = CARRY ? crow(7 + k) : 0.0f;
         } else {
 #pragma unroll
             for (int k = 0; k < 3; ++k) { a.ip[k] = a.ia[k] = a.ir[k] = a.wprev[k] = a.ip_lo[k] = 0.0f; }
@@ -179,7 +187,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 
         for (int s = 0; s < steps; ++s) {
             if (CKPT && s == ck_next) {
-                float* const O = A.ckpt + (int64_t)ck_slot * kRows * ld;
+                float* const O = A.ckpt + (int64_t)ck_slot * kCkptRows * ld;
                 auto out = [&](int k) -> float& { return elem(uniform(O + k * ld), bo); };
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -204,17 +212,19 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
                         wp[k] = elem(uniform(A.wp + ((int64_t)epoch * 3 + k) * A.cmd_ld), bo);
                     next_epoch_step = epoch < A.n_epochs - 1 ? next_epoch_step + A.resample : INT64_MAX;
                 }
-                controller(c, lim, g, a, wp, dc);
+                controller<CARRY>(c, lim, g, a, wp, dc);
             }
-            rk4_step(c, lim, a, dc);
+            rk4_step<CARRY>(c, lim, a, dc);
         }
 
 #pragma unroll
         for (int k = 0; k < 3; ++k) { row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k]; }
 #pragma unroll
         for (int k = 0; k < 4; ++k) { row(6 + k) = a.q[k]; row(13 + k) = a.d[k]; }
+        if (CARRY) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { row(30 + k) = a.p_lo[k]; row(33 + k) = a.v_lo[k]; }
+            for (int k = 0; k < 3; ++k) { crow(k) = a.p_lo[k]; crow(3 + k) = a.v_lo[k]; }
+        }
         if (MODE == 1) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -222,9 +232,11 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
                 row(23 + k) = a.ir[k]; row(26 + k) = a.wprev[k];
             }
             row(29) = a.J;
-            row(36) = a.J_lo;
+            if (CARRY) {
+                crow(6) = a.J_lo;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) row(37 + k) = a.ip_lo[k];
+                for (int k = 0; k < 3; ++k) crow(7 + k) = a.ip_lo[k];
+            }
         }
         if (snapshot) {
 #pragma unroll
@@ -431,9 +443,18 @@ __global__ void __launch_bounds__(256) k_count_nonfinite(const float* rows, int6
         atomicAdd(count, (unsigned long long)__popcll(mask));
 }
 
-template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM>
+template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY>
 const void* kfn() {
-    return reinterpret_cast<const void*>(&k_rollout<MODE, HET, GAINS, CKPT, PERM>);
+    return reinterpret_cast<const void*>(&k_rollout<MODE, HET, GAINS, CKPT, PERM, CARRY>);
+}
+
+/* Checkpoints are only written with carries (the host refuses the other
+ * combination), so a variant with ckpt maps to the checkpointing kernel,
+ * which reads and writes the carries. */
+template <int MODE, bool HET, bool GAINS, bool PERM>
+const void* kfn_carry(const Variant& v) {
+    if (MODE == 1 && v.ckpt) return kfn<MODE, HET, GAINS, MODE == 1, PERM, true>();
+    return v.carry ? kfn<MODE, HET, GAINS, false, PERM, true>() : kfn<MODE, HET, GAINS, false, PERM, false>();
 }
 
 }  // namespace
@@ -441,12 +462,10 @@ const void* kfn() {
 const void* rollout_kernel(const Variant& v) {
     /* open loop: gains and checkpoints do not apply */
     if (v.mode == 0) {
-        if (!v.het) return kfn<0, false, false, false, false>();
-        return v.perm ? kfn<0, true, false, false, true>() : kfn<0, true, false, false, false>();
+        if (!v.het) return kfn_carry<0, false, false, false>(v);
+        return v.perm ? kfn_carry<0, true, false, true>(v) : kfn_carry<0, true, false, false>(v);
     }
-#define POTATO_PICK(H, P)                                                                   \
-    if (v.gains) return v.ckpt ? kfn<1, H, true, true, P>() : kfn<1, H, true, false, P>(); \
-    return v.ckpt ? kfn<1, H, false, true, P>() : kfn<1, H, false, false, P>();
+#define POTATO_PICK(H, P) return v.gains ? kfn_carry<1, H, true, P>(v) : kfn_carry<1, H, false, P>(v);
     if (!v.het) { POTATO_PICK(false, false) }
     if (v.perm) { POTATO_PICK(true, true) }
     POTATO_PICK(true, false)

@@ -16,6 +16,7 @@
  */
 #pragma once
 
+#include "kernels.h"
 #include "quad_step.h"
 
 namespace potato {
@@ -493,8 +494,9 @@ __device__ __forceinline__ void load_tape(const float* slot, uint32_t lb, Agent&
 
 /*
  * Reverse sweep of one agent's closed-loop rollout of `steps` steps from
- * global step step0.  Checkpoint slot s (40 rows of stride ld, this agent's
- * column at byte offset bo) holds the state before call-relative step s*K.
+ * global step step0.  Checkpoint slot s (kCkptRows rows of stride ld: the
+ * state, then its rounding carries; this agent's column at byte offset bo)
+ * holds the state before call-relative step s*K.
  * Each segment is recomputed forward from its checkpoint with the
  * step-start states written to this wave's tape blocks (`tape` is the
  * wave's block of step 0, consecutive steps tape_step floats apart; lane
@@ -538,7 +540,7 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         const int len = steps - k_begin < K ? steps - k_begin : K;
         const int64_t k0 = step0 + k_begin;        /* global index of the segment's first step */
         Agent a;
-        load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
+        load_rows(ckpt + (int64_t)seg * kCkptRows * ld, ld, bo, a, true);
         int64_t e = resample > 0 ? k0 / resample : 0;
         int64_t next = resample > 0 ? (e + 1) * period : INT64_MAX;   /* first step of epoch e + 1 */
         for (int s = 0; s < len; ++s) {
@@ -595,7 +597,7 @@ __device__ __forceinline__ void recompute_segment(const TypeConst& c, const Limi
     const int len = steps - k_begin < K ? steps - k_begin : K;
     const int64_t k0 = step0 + k_begin;
     Agent a;
-    load_rows(ckpt + (int64_t)seg * 40 * ld, ld, bo, a, true);
+    load_rows(ckpt + (int64_t)seg * kCkptRows * ld, ld, bo, a, true);
     int64_t e = resample > 0 ? k0 / resample : 0;
     int64_t next = resample > 0 ? (e + 1) * period : INT64_MAX;
     for (int s = 0; s < len; ++s) {

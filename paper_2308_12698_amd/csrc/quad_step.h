@@ -134,13 +134,19 @@ constexpr int kTapeRows = 30;
 #define POTATO_FMA(a, b, c) __builtin_fmaf((a), (b), (c))
 
 /* x += inc with the rounding error carried in lo (Fast2Sum, Dekker 1971):
- * the low part is added back into the next increment. */
+ * the low part is added back into the next increment.  Without CARRY the
+ * update is the plain rounded sum and lo is left alone. */
+template <bool CARRY>
 __device__ __forceinline__ void add_carry(float& x, float& lo, float inc) {
 #pragma clang fp contract(off)
-    const float y = inc + lo;
-    const float s = x + y;
-    lo = y - (s - x);
-    x = s;
+    if (CARRY) {
+        const float y = inc + lo;
+        const float s = x + y;
+        lo = y - (s - x);
+        x = s;
+    } else {
+        x = x + inc;
+    }
 }
 
 /* clamp(x, lo, hi) for lo <= hi (one v_med3_f32). */
@@ -212,7 +218,9 @@ __device__ __forceinline__ void derivative(const TypeConst& c, const float v[3],
 
 /* Position -> attitude -> body-rate PID cascade and mixer, evaluated once
  * per step on the step-start state; returns rotor commands relative to
- * w_ref and updates the controller memory. */
+ * w_ref and updates the controller memory.  CARRY: the position-loop
+ * integral keeps its rounding carry in a.ip_lo. */
+template <bool CARRY = true>
 __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, const Gains& k,
                                            Agent& a, const float wp[3], float dc[4]) {
 #pragma clang fp contract(off)
@@ -225,11 +233,13 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
     for (int i = 0; i < 3; ++i) {
         e[i] *= sc;
         /* integral with carried rounding error, clamped (carry cleared at a bound) */
-        const float y = POTATO_FMA(e[i], L.dt, a.ip_lo[i]);
+        const float y = CARRY ? POTATO_FMA(e[i], L.dt, a.ip_lo[i]) : e[i] * L.dt;
         const float s = a.ip[i] + y;
-        const float lo = y - (s - a.ip[i]);
         const float cl = clampf_(s, -L.ipos_max, L.ipos_max);
-        a.ip_lo[i] = cl == s ? lo : 0.0f;
+        if (CARRY) {
+            const float lo = y - (s - a.ip[i]);
+            a.ip_lo[i] = cl == s ? lo : 0.0f;
+        }
         a.ip[i] = cl;
         acc[i] = POTATO_FMA(-k.kdp, a.v[i], POTATO_FMA(k.kip, cl, k.kpp * e[i]));
     }
@@ -285,7 +295,9 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
     }
 }
 
-/* Classical RK4 with the command held, then quaternion renormalisation. */
+/* Classical RK4 with the command held, then quaternion renormalisation.
+ * CARRY: p, v and J keep their rounding carries in a.p_lo, a.v_lo, a.J_lo. */
+template <bool CARRY = true>
 __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Agent& a,
                                          const float dc[4]) {
 #pragma clang fp contract(off)
@@ -363,8 +375,8 @@ __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Ag
      * (dt/12 for q, whose stage rates are doubled) */
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        add_carry(a.p[i], a.p_lo[i], POTATO_FMA(L.dt2_6, A3[i], L.dt * a.v[i]));
-        add_carry(a.v[i], a.v_lo[i], L.dt6 * (av[i] + kv[i]));
+        add_carry<CARRY>(a.p[i], a.p_lo[i], POTATO_FMA(L.dt2_6, A3[i], L.dt * a.v[i]));
+        add_carry<CARRY>(a.v[i], a.v_lo[i], L.dt6 * (av[i] + kv[i]));
         a.w[i] = POTATO_FMA(L.dt6, aw[i] + kw[i], a.w[i]);
     }
 #pragma unroll
@@ -372,7 +384,7 @@ __device__ __forceinline__ void rk4_step(const TypeConst& c, const Limits& L, Ag
         a.q[i] = POTATO_FMA(L.dt12, aq[i] + kq[i], a.q[i]);
         a.d[i] = POTATO_FMA(e[i], cR, dc[i]);
     }
-    add_carry(a.J, a.J_lo, POTATO_FMA(L.dt6, ass, L.dt * c.four_w2));
+    add_carry<CARRY>(a.J, a.J_lo, POTATO_FMA(L.dt6, ass, L.dt * c.four_w2));
 
     const float r = rsq(POTATO_FMA(a.q[3], a.q[3],
                         POTATO_FMA(a.q[2], a.q[2], POTATO_FMA(a.q[1], a.q[1], a.q[0] * a.q[0]))));

@@ -11,7 +11,7 @@ The paper benchmarks a batch of identical nonlinear quadrotors flying under
 a PID body-rate controller (Sec. III, Table I and Fig. "run_time"); it
 publishes no dataset, so every workload here is synthetic.
 
-State layout (structure of arrays, ``float32[40][ld]``, one column per agent):
+State layout (structure of arrays, ``float32[30][ld]``, one column per agent):
 
 ====== ===================================================================
 rows   meaning
@@ -27,9 +27,10 @@ rows   meaning
 23-25  rate-loop integral
 26-28  body rates at the previous control step (rate-loop derivative)
 29     running cost J = integral of the sum of squared rotor speeds
-30-39  rounding carries of position, velocity, J and the position-loop
-       integral (zero in a fresh state)
 ====== ===================================================================
+
+The simulator's optional rounding carries (a separate ``[10][ld]`` buffer)
+are zero for every state generated here.
 """
 from __future__ import annotations
 
@@ -38,8 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-N_ROWS = 40
-N_PHYS_ROWS = 30   # rows with a physical meaning; the rest are FP32 carries
+N_ROWS = 30
 N_GAINS = 9
 SEED_BASE = 12698
 
@@ -76,7 +76,7 @@ class Swarm:
     mode: int                      # 0 open loop (motor commands), 1 closed loop
     dt: float
     n_steps: int
-    state: np.ndarray              # [40, N]
+    state: np.ndarray              # [30, N]
     types: list                    # list of dicts, float32 scalars + gains + budget
     glob: dict                     # controller limits, float32 scalars
     type_idx: np.ndarray | None = None     # uint8 [N]

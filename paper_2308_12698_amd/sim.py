@@ -16,11 +16,20 @@ import torch
 
 from . import _lib as L
 
-N_ROWS = 40            # state rows per agent (include/potato.h)
+N_ROWS = 30            # state rows per agent (include/potato.h)
+N_CARRY = 10           # rounding-carry rows per agent
+N_CKPT = 40            # rows of a checkpoint slot: the state, then its carries
 
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _state(state, carry):
+    """potato_state of a [30, ld] state and an optional [10, carry_ld] carry."""
+    return L.State(C.c_void_p(state.data_ptr()), state.stride(0),
+                   None if carry is None else C.c_void_p(carry.data_ptr()),
+                   0 if carry is None else carry.stride(0))
 
 
 def _stream_handle(stream=None) -> C.c_void_p:
@@ -133,8 +142,9 @@ class Simulator:
             raise ValueError(f"{name} must be a contiguous device uint8 tensor of length >= n")
 
     def _structs(self, state, n, type_idx, perm, gains, motor_cmd, wp, resample_every, step0,
-                 alive=None):
+                 alive=None, carry=None):
         _check_rows("state", state, N_ROWS, n)
+        _check_rows("carry", carry, N_CARRY, n)
         ld = state.stride(0)
         if type_idx is not None:
             if not type_idx.is_cuda or type_idx.dtype != torch.uint8 or type_idx.dim() != 1 \
@@ -166,7 +176,7 @@ class Simulator:
             if motor_cmd is not None and motor_cmd.stride(0) != wp.shape[2]:
                 raise ValueError("motor_cmd and wp must share their row stride")
             cmd_ld = wp.shape[2]
-        st = L.State(C.c_void_p(state.data_ptr()), ld)
+        st = _state(state, carry)
         self._check_mask("alive", alive, n)
         pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains), gains.stride(0) if gains is not None else 0,
                       _ptr(alive))
@@ -175,26 +185,31 @@ class Simulator:
 
     def step(self, state, n_steps, dt, *, n_agents=None, type_idx=None, perm=None, gains=None,
              motor_cmd=None, wp=None, resample_every=0, step0=0, ckpt=None, ckpt_every=0,
-             alive=None, stream=None):
-        """Advance ``state`` ([40, ld] float32, in place) by n_steps steps.
-        ``alive`` (uint8 [n], optional): agents with 0 are not advanced."""
+             alive=None, carry=None, stream=None):
+        """Advance ``state`` ([30, ld] float32, in place) by n_steps steps.
+        ``carry`` ([10, ld] float32, in place, optional): the rounding carries
+        of position, velocity, cost and position-loop integral (zeros for a
+        fresh state); without it the updates are uncompensated.  ``alive``
+        (uint8 [n], optional): agents with 0 are not advanced.  ``ckpt``
+        ([slots, 40, ld], needs ``carry``) receives the state and carries
+        every ``ckpt_every`` steps."""
         n = int(n_agents if n_agents is not None else state.shape[1])
         st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
-                                   resample_every, step0, alive)
+                                   resample_every, step0, alive, carry)
         if ckpt is not None:
             slots = -(-int(n_steps) // int(ckpt_every)) if ckpt_every > 0 else 0
             if not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous() \
-                    or ckpt.numel() < slots * N_ROWS * st.ld:
+                    or ckpt.numel() < slots * N_CKPT * st.ld:
                 raise ValueError(f"ckpt must be a contiguous device float32 tensor of >= "
-                                 f"{slots} x {N_ROWS} x {st.ld} elements")
+                                 f"{slots} x {N_CKPT} x {st.ld} elements")
         L.check(self._lib.potato_step(self._h, C.byref(st), C.byref(pp), C.byref(cm), float(dt),
                                       n, int(n_steps), _ptr(ckpt), int(ckpt_every),
                                       _stream_handle(stream)))
         return state
 
     def autotune(self, state, dt, probe_steps=200, *, n_agents=None, type_idx=None, perm=None,
-                 gains=None, motor_cmd=None, wp=None, resample_every=0, step0=0, stream=None,
-                 cache=None):
+                 gains=None, motor_cmd=None, wp=None, resample_every=0, step0=0, carry=None,
+                 stream=None, cache=None):
         """Time the fused form's launch shapes on a scratch copy; keep the best.
 
         ``cache`` (default: the POTATO_AUTOTUNE_CACHE environment variable) is
@@ -202,7 +217,7 @@ class Simulator:
         variant, agent count and probe length; a hit skips the timing."""
         n = int(n_agents if n_agents is not None else state.shape[1])
         st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
-                                   resample_every, step0)
+                                   resample_every, step0, carry=carry)
 
         def run():
             best = L.Options()
@@ -218,7 +233,8 @@ class Simulator:
         props = torch.cuda.get_device_properties(state.device)
         key = "|".join(str(x) for x in (
             getattr(props, "gcnArchName", props.name), _library_digest(), self.mode, self.n_types,
-            type_idx is not None, gains is not None, perm is not None, n, int(probe_steps)))
+            type_idx is not None, gains is not None, perm is not None, carry is not None, n,
+            int(probe_steps)))
         return autotune_cached(path, key, run)
 
     def step_backward(self, ckpt, ckpt_every, n_steps, dt, grad_final, *, n_agents=None,
@@ -238,8 +254,8 @@ class Simulator:
         if not ckpt.is_cuda or ckpt.dtype != torch.float32 or not ckpt.is_contiguous():
             raise ValueError("ckpt must be a contiguous device float32 tensor")
         slots = -(-int(n_steps) // int(ckpt_every))
-        if ckpt.numel() < slots * N_ROWS * ld:
-            raise ValueError(f"ckpt must hold {slots} x {N_ROWS} x {ld} floats")
+        if ckpt.numel() < slots * N_CKPT * ld:
+            raise ValueError(f"ckpt must hold {slots} x {N_CKPT} x {ld} floats")
         self._check_mask("alive", alive, n)
         pp = L.Params(_ptr(type_idx), _ptr(perm), _ptr(gains),
                       gains.stride(0) if gains is not None else 0, _ptr(alive))
@@ -274,7 +290,7 @@ class Simulator:
             raise ValueError("invalid agent count")
         if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=state.device)
-        st = L.State(C.c_void_p(state.data_ptr()), state.stride(0))
+        st = _state(state, None)
         pp = L.Params(_ptr(type_idx), None, None, 0, None)
         L.check(self._lib.potato_detect_collisions(self._h, C.byref(st), C.byref(pp), n, _ptr(alive),
                                                    _ptr(died), _ptr(workspace), nbytes,
@@ -290,7 +306,7 @@ class Simulator:
             count = torch.zeros(1, dtype=torch.int64, device=state.device)
         elif not count.is_cuda or count.dtype != torch.int64 or count.numel() < 1:
             raise ValueError("count must be a device int64 tensor")
-        st = L.State(C.c_void_p(state.data_ptr()), state.stride(0))
+        st = _state(state, None)
         L.check(self._lib.potato_count_nonfinite(self._h, C.byref(st), n, _ptr(count), _stream_handle(stream)))
         return count
 
@@ -338,14 +354,15 @@ class Pipe:
         L.check(self._lib.potato_pipe_push(self._h, a.ctypes.data_as(C.c_void_p)))
 
     def run(self, state, n_steps, dt, *, snap_every=0, snaps=None, type_idx=None, perm=None,
-            gains=None, alive=None, stream=None):
+            gains=None, alive=None, carry=None, stream=None):
         _check_rows("state", state, N_ROWS, self.n)
         due = int(n_steps) // int(snap_every) if snap_every > 0 else 0
         if due:
             if snaps is None or snaps.is_cuda or snaps.dtype != torch.float32 \
                     or not snaps.is_contiguous() or snaps.numel() < due * 3 * self.n:
                 raise ValueError(f"snaps must be a contiguous host float32 tensor of >= {due} x 3 x {self.n}")
-        st, pp, _ = self.sim._structs(state, self.n, type_idx, perm, gains, None, None, 0, 0, alive)
+        st, pp, _ = self.sim._structs(state, self.n, type_idx, perm, gains, None, None, 0, 0, alive,
+                                      carry)
         L.check(self._lib.potato_pipe_run(self._h, C.byref(st), C.byref(pp), float(dt), int(n_steps),
                                           int(snap_every), _ptr(snaps) if due else None,
                                           _stream_handle(stream)))

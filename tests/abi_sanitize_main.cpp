@@ -19,7 +19,7 @@ int failures = 0;
 
 void expect(bool ok, const char* what) {
     if (!ok) {
-        std::fprintf(stderr, "FAILED: %s (last error: %s)\n", what, potato_last_error());
+        std::fprintf(stderr, "FAILED: %s (last error: %s)\n", what, potato_last_error(nullptr));
         ++failures;
     }
 }
@@ -72,7 +72,7 @@ int main() {
     expect(made == POTATO_OK ? ctx != nullptr : ctx == nullptr, "create: handle matches status");
 
     /* every other entry point on null handles */
-    potato_state st{nullptr, 10};
+    potato_state st{nullptr, 10, nullptr, 0};
     potato_params pp{};
     potato_cmds cm{};
     expect(potato_destroy(nullptr) == POTATO_OK, "destroy null");
@@ -108,7 +108,7 @@ int main() {
         expect(potato_pipe_create(ctx, 0, &pipe) == POTATO_EINVAL, "pipe create: zero agents");
         expect(potato_destroy(ctx) == POTATO_OK, "destroy");
     }
-    expect(std::strlen(potato_last_error()) > 0, "last error kept");
+    expect(std::strlen(potato_last_error(nullptr)) > 0, "last error kept");
     if (failures) return 1;
     std::printf("abi sanitizer run: ok\n");
     return 0;

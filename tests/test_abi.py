@@ -42,7 +42,7 @@ def test_library_is_built_for_gfx950():
 
 def test_version_and_empty_error(lib):
     assert b"gfx950" in lib.potato_version()
-    assert isinstance(lib.potato_last_error(), bytes)
+    assert isinstance(lib.potato_last_error(None), bytes)
 
 
 def _create(lib, types, glob=None, opts=None):
@@ -62,7 +62,7 @@ def test_create_rejects_invalid_types(lib, bad):
     t.update({k: v for k, v in bad.items()})
     st, h = _create(lib, [t])
     assert st == L.EINVAL and not h.value
-    assert len(lib.potato_last_error()) > 0
+    assert len(lib.potato_last_error(None)) > 0
 
 
 def test_create_rejects_invalid_counts_limits_options(lib):

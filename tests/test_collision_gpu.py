@@ -147,12 +147,13 @@ def test_dead_agents_pass_the_cotangent_through(torch_dev):
     gains = torch.from_numpy(sw.gains).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
     ckpt = torch.empty((2, 40, sw.n), device=dev)
-    sim.step(x, 100, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=50, alive=at)
+    sim.step(x, 100, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=50, alive=at,
+             carry=torch.zeros_like(x[:10]))
     lam = torch.randn(30, sw.n, device=dev)
     gx0, gg = sim.step_backward(ckpt, 50, 100, sw.dt, lam, gains=gains, wp=wp, alive=at)
     x2 = torch.from_numpy(sw.state).to(dev)
     ck2 = torch.empty((2, 40, sw.n), device=dev)
-    sim.step(x2, 100, sw.dt, gains=gains, wp=wp, ckpt=ck2, ckpt_every=50)
+    sim.step(x2, 100, sw.dt, gains=gains, wp=wp, ckpt=ck2, ckpt_every=50, carry=torch.zeros_like(x2[:10]))
     gx2, gg2 = sim.step_backward(ck2, 50, 100, sw.dt, lam, gains=gains, wp=wp)
     torch.cuda.synchronize()
     dead = torch.from_numpy(alive == 0).to(dev)

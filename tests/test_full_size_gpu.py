@@ -44,10 +44,11 @@ def test_scale_swarm_10000_steps_bench_configuration(oracle, torch_dev):
     print(f"scale swarm: {sw.n} agents x {sw.n_steps} steps", flush=True)
     st = torch.from_numpy(sw.state).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
+    carry = torch.zeros((10, sw.n), device=dev)
     sim = Simulator(sw.types, sw.glob, mode=1, form="fused", use_graph=True)
-    tuned = sim.autotune(st, sw.dt, 1000, wp=wp, resample_every=sw.resample_every)
+    tuned = sim.autotune(st, sw.dt, 1000, wp=wp, resample_every=sw.resample_every, carry=carry)
     sim.set_options(form="fused", use_graph=True, **tuned)
-    sim.step(st, sw.n_steps, sw.dt, wp=wp, resample_every=sw.resample_every)
+    sim.step(st, sw.n_steps, sw.dt, wp=wp, resample_every=sw.resample_every, carry=carry)
     torch.cuda.synchronize()
     got = st.cpu().numpy().astype(np.float64)
     sim.close()
@@ -66,7 +67,7 @@ def test_heterogeneous_swarm_full_size(oracle, torch_dev):
     ti = torch.from_numpy(sw.type_idx).to(dev)
     perm = sim.order_by_type(ti)
     sim.step(st, sw.n_steps, sw.dt, type_idx=ti, perm=perm, wp=torch.from_numpy(sw.wp).to(dev),
-             resample_every=sw.resample_every)
+             resample_every=sw.resample_every, carry=torch.zeros((10, sw.n), device=dev))
     torch.cuda.synchronize()
     got = st.cpu().numpy().astype(np.float64)
     sim.close()
@@ -85,7 +86,8 @@ def test_adjoint_at_one_million_agents(oracle, torch_dev):
     gains = torch.from_numpy(sw.gains).to(dev)
     wp = torch.from_numpy(sw.wp).to(dev)
     ckpt = torch.empty((sw.n_steps // K, 40, sw.n), device=dev)
-    sim.step(x, sw.n_steps, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
+    sim.step(x, sw.n_steps, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K,
+             carry=torch.zeros((10, sw.n), device=dev))
     tgt = torch.from_numpy(sw.extra["target"]).to(dev)
     gfin = torch.zeros((30, sw.n), device=dev)
     gfin[0:3] = 2.0 * (x[0:3] - tgt)

@@ -1,7 +1,7 @@
 """The largest sizes the library accepts, on one MI355X.
 
 The ABI takes at most 2^30 agents (a byte offset within one state row then
-fits 32 bits).  At that count the state alone is 40 x 2^30 x 4 B = 160 GiB,
+fits 32 bits).  At that count the state and its carries are 40 x 2^30 x 4 B = 160 GiB,
 which the MI355X's HBM holds.  Each case repeats a small seeded swarm over
 the whole range: an agent's arithmetic does not depend on where it sits, so
 every copy must come out bit for bit equal to the first, and sampled agents
@@ -75,16 +75,18 @@ def test_closed_loop_rollout_at_max_agents(oracle, torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
     n, n_steps = MAX_AGENTS, 20
-    need_memory(torch, (40 + 3) * 4 * n + 4 * GiB)
+    # state, its rounding carries, waypoints
+    need_memory(torch, (30 + 10 + 3) * 4 * n + 4 * GiB)
     base = I.config2(n=1 << 20, n_steps=n_steps)
     b = base.n
     print(f"closed loop: {n} agents ({n // b} copies of {b}) x {n_steps} steps", flush=True)
-    st = torch.empty((40, n), dtype=torch.float32, device=dev)
+    st = torch.empty((30, n), dtype=torch.float32, device=dev)
+    carry = torch.zeros((10, n), dtype=torch.float32, device=dev)
     wp = torch.empty((1, 3, n), dtype=torch.float32, device=dev)
     tile(st, torch.from_numpy(base.state).to(dev), n)
     tile(wp, torch.from_numpy(base.wp[:1]).to(dev), n)
     sim = Simulator(base.types, base.glob, mode=1, form="fused", steps_per_launch=n_steps)
-    sim.step(st, n_steps, base.dt, wp=wp, resample_every=base.resample_every)
+    sim.step(st, n_steps, base.dt, wp=wp, resample_every=base.resample_every, carry=carry)
     bad = int(sim.count_nonfinite(st).item())
     torch.cuda.synchronize()
     assert bad == 0
@@ -92,8 +94,9 @@ def test_closed_loop_rollout_at_max_agents(oracle, torch_dev):
     j = np.sort(np.random.default_rng(31).choice(b, 16, replace=False))
     g = (n // b - 1) * b + j
     got = st[:30, torch.from_numpy(g).to(dev)].cpu().numpy()
+    assert_copies_equal(torch, carry, b, n, 10)
     sim.close()
-    del st, wp
+    del st, wp, carry
     sub = I.subset(base, j)
     ref = oracle.rollout(sub.state, sub.types, sub.glob, 1, sub.dt, n_steps, wp=sub.wp,
                          resample_every=sub.resample_every)
@@ -106,15 +109,16 @@ def test_heterogeneous_type_order_at_max_agents(oracle, torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
     n, n_steps = MAX_AGENTS, 20
-    # state and waypoints (FP32 rows), types, order, its workspace, the check's int64 copy
-    need_memory(torch, (40 + 3) * 4 * n + (1 + 4 + 8 + 8) * n + 4 * GiB)
+    # state and waypoints (FP32 rows; no carries: uncompensated updates), types,
+    # order, its workspace, the check's int64 copy
+    need_memory(torch, (30 + 3) * 4 * n + (1 + 4 + 8 + 8) * n + 4 * GiB)
     base = I.config3(scale=16)
     # budgets of 4, 8, ..., 32 steps: half the types stop inside the rollout
     types = [dict(t, budget=4 * (k + 1)) for k, t in enumerate(base.types)]
     b = base.n
     print(f"heterogeneous: {n} agents ({n // b} copies of {b}, cut short), {len(types)} types, "
           f"budgets 4-32, {n_steps} steps", flush=True)
-    st = torch.empty((40, n), dtype=torch.float32, device=dev)
+    st = torch.empty((30, n), dtype=torch.float32, device=dev)
     wp = torch.empty((1, 3, n), dtype=torch.float32, device=dev)
     ti = torch.empty(n, dtype=torch.uint8, device=dev)
     tile(st, torch.from_numpy(base.state).to(dev), n)
@@ -153,12 +157,13 @@ def test_adjoint_two_checkpoint_slots_at_2_27_agents(oracle, torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
     n, n_steps, K = 1 << 27, 20, 10
-    # state, 2 checkpoint slots, gains, waypoint, cotangent, both gradients
+    # state and carries, 2 checkpoint slots, gains, waypoint, cotangent, both gradients
     need_memory(torch, (40 + 80 + 9 + 3 + 30 + 30 + 9) * 4 * n + 4 * GiB)
     base = I.config4(n=1 << 16, n_steps=n_steps)
     b = base.n
     print(f"adjoint: {n} agents ({n // b} copies of {b}) x {n_steps} steps, K = {K}", flush=True)
-    x = torch.empty((40, n), dtype=torch.float32, device=dev)
+    x = torch.empty((30, n), dtype=torch.float32, device=dev)
+    carry = torch.zeros((10, n), dtype=torch.float32, device=dev)
     gains = torch.empty((9, n), dtype=torch.float32, device=dev)
     wp = torch.empty((1, 3, n), dtype=torch.float32, device=dev)
     tile(x, torch.from_numpy(base.state).to(dev), n)
@@ -166,7 +171,7 @@ def test_adjoint_two_checkpoint_slots_at_2_27_agents(oracle, torch_dev):
     tile(wp, torch.from_numpy(base.wp).to(dev), n)
     sim = Simulator(base.types, base.glob, mode=1, form="fused", steps_per_launch=n_steps)
     ckpt = torch.empty((n_steps // K, 40, n), dtype=torch.float32, device=dev)
-    sim.step(x, n_steps, base.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K)
+    sim.step(x, n_steps, base.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K, carry=carry)
     gfin = torch.zeros((30, n), dtype=torch.float32, device=dev)
     tgt = torch.empty((3, n), dtype=torch.float32, device=dev)
     tile(tgt, torch.from_numpy(base.extra["target"]).to(dev), n)
@@ -181,7 +186,7 @@ def test_adjoint_two_checkpoint_slots_at_2_27_agents(oracle, torch_dev):
     g = torch.from_numpy((n // b - 1) * b + j).to(dev)
     got = torch.cat([gx0[:, g], gg[:, g]]).T.cpu().numpy()
     sim.close()
-    del x, gains, wp, ckpt, gfin, gx0, gg
+    del x, carry, gains, wp, ckpt, gfin, gx0, gg
     sub = I.subset(base, j)
     fin, jac = oracle.jacobian(sub.state, sub.types, sub.glob, sub.dt, n_steps, wp=sub.wp, gains=sub.gains)
     seed = np.zeros((30, sub.n))

@@ -30,8 +30,12 @@ def _dev(torch, dev, a):
 
 
 def gpu_rollout(torch_dev, sw, n_steps, form="fused", state=None, sim=None, step0=0, ld=None,
-                **opts):
-    """Run the workload on the GPU; returns the final state as float64 [40, N]."""
+                carry=True, **opts):
+    """Run the workload on the GPU.  ``state`` (default the workload's) has
+    30 rows, or 40 with its rounding carries in rows 30-39.  With ``carry``
+    the call keeps the carries in a buffer and the result is float64 [40, N]
+    (state, then carries); without, the updates are uncompensated and the
+    result is [30, N].  ``ld`` > N pads both buffers with columns of 7.0."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
     own = sim is None
@@ -39,19 +43,33 @@ def gpu_rollout(torch_dev, sw, n_steps, form="fused", state=None, sim=None, step
         sim = Simulator(sw.types, sw.glob, mode=sw.mode, form=form, debug=True, **opts)
     s0 = sw.state if state is None else state
     n = s0.shape[1]
+    c0 = s0[30:40] if s0.shape[0] == 40 else np.zeros((10, n), dtype=np.float32)
+    s0 = s0[:30]
     if ld is not None and ld > n:
-        buf = np.full((s0.shape[0], ld), 7.0, dtype=np.float32)
+        buf = np.full((30, ld), 7.0, dtype=np.float32)
         buf[:, :n] = s0
         s0 = buf
+        cbuf = np.full((10, ld), 7.0, dtype=np.float32)
+        cbuf[:, :n] = c0
+        c0 = cbuf
     st = _dev(torch, dev, s0)
+    ct = _dev(torch, dev, c0) if carry else None
     sim.step(st, n_steps, sw.dt, n_agents=n, type_idx=_dev(torch, dev, sw.type_idx),
              gains=_dev(torch, dev, sw.gains), motor_cmd=_pad(torch, dev, sw.motor_cmd, st.shape[1]),
-             wp=_pad3(torch, dev, sw.wp, st.shape[1]), resample_every=sw.resample_every, step0=step0)
+             wp=_pad3(torch, dev, sw.wp, st.shape[1]), resample_every=sw.resample_every, step0=step0,
+             carry=ct)
     torch.cuda.synchronize()
     out = st.cpu().numpy()
+    if carry:
+        out = np.concatenate([out, ct.cpu().numpy()])
     if own:
         sim.close()
     return out.astype(np.float64)
+
+
+def carry_zeros(torch_dev, n):
+    torch, dev = torch_dev
+    return torch.zeros((10, n), dtype=torch.float32, device=dev)
 
 
 def _pad(torch, dev, a, ld):
@@ -89,9 +107,10 @@ def test_open_loop_1000_agents_1000_steps(oracle, torch_dev, form):
     got = gpu_rollout(torch_dev, sw, 1000, form=form, steps_per_launch=128)
     ref = oracle_rollout(oracle, sw, 1000)
     assert_parity(got, ref, sw, OPEN_LOOP_GROUPS)
-    # rows the open loop does not own are left alone
+    # rows the open loop does not own are left alone (state rows 17-29, the
+    # carries of J and of the position-loop integral)
     assert np.array_equal(got[17:30], sw.state[17:30].astype(np.float64))
-    assert np.array_equal(got[36:], sw.state[36:].astype(np.float64))
+    assert not got[36:].any()
 
 
 def test_open_loop_full_size_every_agent(oracle, torch_dev):
@@ -180,9 +199,10 @@ def test_scale_workload_full_size_every_agent(oracle, torch_dev):
     sw = I.config2()
     sim = Simulator(sw.types, sw.glob, mode=1, form="fused", use_graph=True)
     st = _dev(torch, dev, sw.state)
+    ct = carry_zeros(torch_dev, sw.n)
     wp = _dev(torch, dev, sw.wp)
-    sim.autotune(st, sw.dt, 200, wp=wp, resample_every=sw.resample_every)
-    sim.step(st, 1000, sw.dt, wp=wp, resample_every=sw.resample_every)
+    sim.autotune(st, sw.dt, 200, wp=wp, resample_every=sw.resample_every, carry=ct)
+    sim.step(st, 1000, sw.dt, wp=wp, resample_every=sw.resample_every, carry=ct)
     torch.cuda.synchronize()
     got = st.cpu().numpy().astype(np.float64)
     sim.close()
@@ -205,7 +225,7 @@ def test_heterogeneous_batch_matches_oracle(oracle, torch_dev):
         ti = _dev(torch, dev, sw.type_idx)
         perm = sim.order_by_type(ti) if use_perm else None
         sim.step(st, sw.n_steps, sw.dt, type_idx=ti, perm=perm, wp=_dev(torch, dev, sw.wp),
-                 resample_every=sw.resample_every)
+                 resample_every=sw.resample_every, carry=carry_zeros(torch_dev, sw.n))
         torch.cuda.synchronize()
         got = st.cpu().numpy().astype(np.float64)
         sim.close()
@@ -224,7 +244,7 @@ def test_heterogeneous_full_size_every_agent(oracle, torch_dev):
     ti = _dev(torch, dev, sw.type_idx)
     perm = sim.order_by_type(ti)
     sim.step(st, 1000, sw.dt, type_idx=ti, perm=perm, wp=_dev(torch, dev, sw.wp),
-             resample_every=sw.resample_every)
+             resample_every=sw.resample_every, carry=carry_zeros(torch_dev, sw.n))
     torch.cuda.synchronize()
     got = st.cpu().numpy().astype(np.float64)
     sim.close()
@@ -244,6 +264,55 @@ def test_hover_fixed_point_on_gpu(torch_dev):
     assert np.abs(got[10:13]).max() <= 1e-5
     assert np.abs(got[13:17]).max() <= 1e-3                        # rad/s around ~634
     assert np.abs(got[6] - 1.0).max() <= 1e-6
+
+
+@pytest.mark.parametrize("mode,form", [(1, "plain"), (1, "fused"), (0, "fused")])
+def test_nothing_is_written_past_the_state_and_carry_rows(oracle, torch_dev, mode, form):
+    """The state is 30 rows and the carries 10: both sit at the top of
+    larger buffers whose extra rows are guard rows holding a sentinel; after
+    the rollout (10,000 steps closed loop) every guard element is the
+    sentinel bit for bit and the state matches the oracle."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.subset(I.config1(), np.arange(0, 5000, 10)) if mode == 1 else I.config0(n=500)
+    n_steps = 10000 if mode == 1 else 1000
+    n, guard, sentinel = sw.n, 6, -12345.678
+    buf = torch.full((30 + guard, n), sentinel, dtype=torch.float32, device=dev)
+    cbuf = torch.full((10 + guard, n), sentinel, dtype=torch.float32, device=dev)
+    buf[:30] = _dev(torch, dev, sw.state)
+    cbuf[:10] = 0.0
+    st, ct = buf[:30], cbuf[:10]
+    assert st.is_contiguous() and ct.is_contiguous()
+    sim = Simulator(sw.types, sw.glob, mode=mode, form=form, steps_per_launch=500)
+    sim.step(st, n_steps, sw.dt, wp=_dev(torch, dev, sw.wp), motor_cmd=_dev(torch, dev, sw.motor_cmd),
+             carry=ct)
+    torch.cuda.synchronize()
+    sim.close()
+    assert bool((buf[30:] == sentinel).all()) and bool((cbuf[10:] == sentinel).all())
+    ref = oracle_rollout(oracle, sw, n_steps)
+    assert_parity(buf[:30].cpu().numpy().astype(np.float64), ref, sw,
+                  None if mode == 1 else OPEN_LOOP_GROUPS)
+
+
+def test_uncompensated_updates_without_a_carry_buffer(oracle, torch_dev):
+    """Without a carry buffer the integrator's updates are plain FP32 sums
+    (the documented accuracy of that mode: ~1e-4 relative after 1,000 steps
+    of the closed-loop swarm, ~2e-3 after 10,000); with carries the same
+    runs stay near 1e-6.  Both results are printed."""
+    sw = I.config1()
+    ref = oracle_rollout(oracle, sw, 1000)
+    plain = gpu_rollout(torch_dev, sw, 1000, carry=False, steps_per_launch=250)
+    comp = gpu_rollout(torch_dev, sw, 1000, carry=True, steps_per_launch=250)
+    e_plain = max(v[0] for v in rel_errors(plain, ref, sw.types).values())
+    e_comp = max(v[0] for v in rel_errors(comp, ref, sw.types).values())
+    sub = I.subset(sw, np.arange(0, 5000, 10))
+    ref10 = oracle_rollout(oracle, sub, 10000)
+    e10 = max(v[0] for v in rel_errors(gpu_rollout(torch_dev, sub, 10000, carry=False, steps_per_launch=500),
+                                      ref10, sub.types).values())
+    print(f"without carries: {e_plain:.2e} (1,000 steps), {e10:.2e} (10,000 steps); "
+          f"with: {e_comp:.2e} (1,000 steps)", flush=True)
+    assert e_comp <= TOL and e_plain <= 1e-3 and e10 <= 2e-2
+    assert e_comp < e_plain
 
 
 # --- GPU-side invariants and decompositions -------------------------------------
@@ -276,11 +345,12 @@ def test_graph_replay_matches_eager(torch_dev):
     graph = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=40, use_graph=True)
     a = _dev(torch, dev, sw.state)
     b = _dev(torch, dev, sw.state)
+    ca, cb = carry_zeros(torch_dev, sw.n), carry_zeros(torch_dev, sw.n)
     for _ in range(4):
-        eager.step(a, 200, sw.dt, wp=wp)
-        graph.step(b, 200, sw.dt, wp=wp)
+        eager.step(a, 200, sw.dt, wp=wp, carry=ca)
+        graph.step(b, 200, sw.dt, wp=wp, carry=cb)
         torch.cuda.synchronize()
-        assert torch.equal(a, b)
+        assert torch.equal(a, b) and torch.equal(ca, cb)
         a.mul_(1.0)                    # eager work between replays
     eager.close(); graph.close()
 
@@ -368,7 +438,8 @@ def test_budget_zero_and_nan_agents(torch_dev):
     bad[3, 5] = np.nan
     got = gpu_rollout(torch_dev, sw, 300, state=bad)
     frozen = sw.type_idx == 1
-    assert np.array_equal(got[:, frozen], bad[:, frozen].astype(np.float64))
+    assert np.array_equal(got[:30, frozen], bad[:, frozen].astype(np.float64))
+    assert not got[30:, frozen].any()
     clean = gpu_rollout(torch_dev, sw, 300)
     keep = np.arange(700) != 5
     assert np.array_equal(got[:, keep], clean[:, keep])
@@ -386,11 +457,12 @@ def test_count_nonfinite_agents(torch_dev):
     bad[0, 3] = np.nan           # position
     bad[15, 700] = np.inf        # rotor
     bad[29, 1036] = -np.inf      # cost (last agent, ragged tail)
-    bad[35, 10] = np.nan         # a rounding-carry row: not counted ...
+    carry = np.zeros((10, n), dtype=np.float32)
+    carry[5, 10] = np.nan        # a rounding carry (of v_z): not a state row, not counted ...
     closed = Simulator(sw.types, sw.glob, mode=1)
     st = _dev(torch, dev, bad)
     assert int(closed.count_nonfinite(st).item()) == 3
-    closed.step(st, 200, sw.dt, wp=_dev(torch, dev, sw.wp))
+    closed.step(st, 200, sw.dt, wp=_dev(torch, dev, sw.wp), carry=_dev(torch, dev, carry))
     torch.cuda.synchronize()
     got = st.cpu().numpy()
     # ... but the integrator adds it to the velocity, so agent 10 diverges too
@@ -409,7 +481,8 @@ def test_count_nonfinite_agents(torch_dev):
 
 def test_zero_steps_and_single_agent(oracle, torch_dev):
     sw = I.config1(n=1)
-    assert np.array_equal(gpu_rollout(torch_dev, sw, 0), sw.state.astype(np.float64))
+    zero = gpu_rollout(torch_dev, sw, 0)
+    assert np.array_equal(zero[:30], sw.state.astype(np.float64)) and not zero[30:].any()
     got = gpu_rollout(torch_dev, sw, 500)
     assert_parity(got, oracle_rollout(oracle, sw, 500), sw)
 
@@ -436,12 +509,20 @@ def test_step_rejects_invalid_arguments(torch_dev):
     assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 1e-3, 64, 10, C.c_void_p(st.data_ptr()), 0, None) == L.EINVAL
     Cm0 = L.Cmds(None, None, 0, 0, 64, 0)
     assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm0), 1e-3, 64, 10, None, 0, None) == L.EINVAL
+    # checkpoints without a carry buffer; a carry buffer narrower than the swarm
+    ck = torch.empty((1, 40, 64), device=dev)
+    assert lib.potato_step(h, C.byref(S), C.byref(P), C.byref(Cm), 1e-3, 64, 10, C.c_void_p(ck.data_ptr()),
+                           10, None) == L.EINVAL
+    assert b"carr" in lib.potato_last_error(None)
+    carry = torch.zeros((10, 64), device=dev)
+    Sc = L.State(C.c_void_p(st.data_ptr()), 64, C.c_void_p(carry.data_ptr()), 63)
+    assert lib.potato_step(h, C.byref(Sc), C.byref(P), C.byref(Cm), 1e-3, 64, 10, None, 0, None) == L.EINVAL
     # more than 2^30 agents: rejected before any device access (byte offsets are 32-bit)
     big = (1 << 30) + 1
     Sb = L.State(C.c_void_p(st.data_ptr()), big)
     Cb = L.Cmds(None, C.c_void_p(wp.data_ptr()), 1, 0, big, 0)
     assert lib.potato_step(h, C.byref(Sb), C.byref(P), C.byref(Cb), 1e-3, big, 10, None, 0, None) == L.EINVAL
-    assert b"2^30" in lib.potato_last_error()
+    assert b"2^30" in lib.potato_last_error(None)
     torch.cuda.synchronize()
     assert torch.equal(st, before)
     with pytest.raises(ValueError):
@@ -460,7 +541,7 @@ def test_checkpoints_are_the_intermediate_states(torch_dev):
     st = _dev(torch, dev, sw.state)
     ck = torch.full((5, 40, 1000), float("nan"), device=dev)
     sim.step(st, 230, sw.dt, wp=_dev(torch, dev, sw.wp), gains=_dev(torch, dev, sw.gains),
-             ckpt=ck, ckpt_every=K)
+             ckpt=ck, ckpt_every=K, carry=carry_zeros(torch_dev, 1000))
     torch.cuda.synchronize()
     ck = ck.cpu().numpy()
     sim.close()

@@ -6,8 +6,12 @@ A host decision loop sees the positions streamed out of the GPU one epoch
 late and pushes the next waypoints while the GPU keeps simulating.  The
 pushed command sequence is then replayed as one resident rollout: the final
 state and every snapshot must be bitwise equal (same kernels, same
-arithmetic; only the data movement differs), and the final state must match
-the FP64 reference within the 1e-4 parity bound.
+arithmetic; only the data movement differs).  Independently of the GPU,
+the FP64 reference is rolled over the same pushed commands in chunks of
+snap_every steps (with the global step index, so waypoint epochs and step
+budgets fall where they did on the GPU): every snapshot's positions must
+match the reference's positions at that step, and the final state the
+reference's final state, within the 1e-4 parity bound.
 """
 import ctypes as C
 
@@ -36,6 +40,26 @@ def padded(state, ld):
     return buf
 
 
+def oracle_snapshots(oracle, sw, n_steps, snap_every, **kw):
+    """The reference rolled in chunks of snap_every steps from global step 0:
+    (positions after each chunk [k, 3, n], final state [30, n])."""
+    x = sw.state
+    out = []
+    for k in range(n_steps // snap_every):
+        x = oracle.rollout(x, sw.types, sw.glob, sw.mode, sw.dt, snap_every, step0=k * snap_every, **kw)
+        out.append(x[0:3].copy())
+    return np.stack(out), x
+
+
+def assert_snapshots_match(snaps, ref, floor=1.0, tol=TOL):
+    """Per snapshot and agent ||p_gpu - p_ref|| / max(||p_ref||, floor)."""
+    snaps = np.asarray(snaps, dtype=np.float64)
+    assert snaps.shape == ref.shape, (snaps.shape, ref.shape)
+    e = np.linalg.norm(snaps - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), floor)
+    print(f"snapshots vs reference: {snaps.shape[0]} x {snaps.shape[2]}, worst {e.max():.2e}", flush=True)
+    assert np.isfinite(e).all() and e.max() <= tol
+
+
 def decide(observed, epoch, n):
     """The host's decision: next waypoint = last observed position + a seeded offset."""
     r = np.random.default_rng(4242 + epoch)
@@ -52,12 +76,13 @@ def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld, pinned=T
     sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
     pipe = Pipe(sim, n)
     st = torch.from_numpy(padded(sw.state, ld)).to(dev)
+    ct = torch.from_numpy(padded(np.zeros((10, n), np.float32), ld)).to(dev)
     per = epoch_steps // snap_every
     snaps = [torch.full((per, 3, n), -1.0, dtype=torch.float32, pin_memory=pinned) for _ in range(n_epochs)]
     wps = [sw.wp[0]]
     pipe.push(wps[0])
     for e in range(n_epochs):
-        pipe.run(st, epoch_steps, sw.dt, snap_every=snap_every, snaps=snaps[e])
+        pipe.run(st, epoch_steps, sw.dt, snap_every=snap_every, snaps=snaps[e], carry=ct)
         if e + 1 == n_epochs:
             break
         if e == 0:
@@ -69,7 +94,7 @@ def decision_loop(torch_dev, sw, n_epochs, epoch_steps, snap_every, ld, pinned=T
         pipe.push(wps[-1])
     pipe.sync()
     torch.cuda.synchronize()
-    out = st.cpu().numpy()
+    out = np.concatenate([st.cpu().numpy(), ct.cpu().numpy()])
     total, direct = pipe.stats()
     assert total == n_epochs * per
     assert direct == (total if pinned else 0), (total, direct)
@@ -86,6 +111,7 @@ def resident_replay(torch_dev, sw, wps, epoch_steps, snap_every, ld):
     n = sw.state.shape[1]
     sim = Simulator(sw.types, sw.glob, mode=1, steps_per_launch=64)
     st = torch.from_numpy(padded(sw.state, ld)).to(dev)
+    ct = torch.from_numpy(padded(np.zeros((10, n), np.float32), ld)).to(dev)
     wp = torch.from_numpy(np.ascontiguousarray(wps)).to(dev)
     snaps = []
     k = 0
@@ -93,13 +119,13 @@ def resident_replay(torch_dev, sw, wps, epoch_steps, snap_every, ld):
         done = 0
         while done < epoch_steps:
             seg = min(snap_every, epoch_steps - done)
-            sim.step(st, seg, sw.dt, n_agents=n, wp=wp, resample_every=epoch_steps, step0=k)
+            sim.step(st, seg, sw.dt, n_agents=n, wp=wp, resample_every=epoch_steps, step0=k, carry=ct)
             k += seg
             done += seg
             if seg == snap_every:
                 snaps.append(st[0:3, :n].cpu().numpy())
     torch.cuda.synchronize()
-    out = st.cpu().numpy()
+    out = np.concatenate([st.cpu().numpy(), ct.cpu().numpy()])
     sim.close()
     return out, snaps
 
@@ -122,8 +148,9 @@ def test_decision_loop_matches_resident_rollout_and_oracle(oracle, torch_dev, n,
         assert np.array_equal(a, b), f"snapshot {k}"
     # the decision really used streamed positions: epoch 2 waypoints follow snapshot data
     assert not np.array_equal(wps[2], wps[1])
-    exact = oracle.rollout(sw.state, sw.types, sw.glob, 1, sw.dt, n_epochs * epoch_steps, wp=wps,
-                           resample_every=epoch_steps)
+    ref_pos, exact = oracle_snapshots(oracle, sw, n_epochs * epoch_steps, snap_every, wp=wps,
+                                      resample_every=epoch_steps)
+    assert_snapshots_match(np.stack(flat)[:, :, :n], ref_pos)
     errs = rel_errors(got[:30, :n], exact, sw.types)
     print("pipe parity", {k: f"{v[0]:.2e}" for k, v in errs.items()}, flush=True)
     assert max(v[0] for v in errs.values()) <= TOL
@@ -140,38 +167,46 @@ def test_open_loop_commands_and_snapshots(oracle, torch_dev):
     sim = Simulator(sw.types, sw.glob, mode=0, steps_per_launch=32)
     pipe = Pipe(sim, n)
     st = torch.from_numpy(sw.state).to(dev)
+    ct = torch.zeros((10, n), dtype=torch.float32, device=dev)
     snaps = torch.empty((len(cmds) * 2, 3, n), dtype=torch.float32, pin_memory=True)
     for e, c in enumerate(cmds):
         pipe.push(c)
-        pipe.run(st, epoch_steps, sw.dt, snap_every=snap_every, snaps=snaps[2 * e:2 * e + 2])
+        pipe.run(st, epoch_steps, sw.dt, snap_every=snap_every, snaps=snaps[2 * e:2 * e + 2], carry=ct)
     pipe.sync()
     torch.cuda.synchronize()
     got = st.cpu().numpy()
     pipe.close()
     ref = torch.from_numpy(sw.state).to(dev)
+    rc = torch.zeros((10, n), dtype=torch.float32, device=dev)
     ref_snaps = []
     for c in cmds:
         mc = torch.from_numpy(c).to(dev)
         for _ in range(2):
-            sim.step(ref, snap_every, sw.dt, motor_cmd=mc)
+            sim.step(ref, snap_every, sw.dt, motor_cmd=mc, carry=rc)
             ref_snaps.append(ref[0:3].cpu().numpy())
     torch.cuda.synchronize()
-    assert np.array_equal(got, ref.cpu().numpy())
+    assert np.array_equal(got, ref.cpu().numpy()) and torch.equal(ct, rc)
     assert np.array_equal(snaps.numpy(), np.stack(ref_snaps))
+    # the reference over the same commands, one snapshot interval at a time
     exact = sw.state
+    ref_pos = []
     for c in cmds:
-        exact = oracle.rollout(exact, sw.types, sw.glob, 0, sw.dt, epoch_steps, motor_cmd=c)
+        for _ in range(epoch_steps // snap_every):
+            exact = oracle.rollout(exact, sw.types, sw.glob, 0, sw.dt, snap_every, motor_cmd=c)
+            ref_pos.append(exact[0:3].copy())
+    assert_snapshots_match(snaps.numpy(), np.stack(ref_pos))
     errs = rel_errors(got[:30], exact, sw.types, groups=OPEN_LOOP_GROUPS)
     assert max(v[0] for v in errs.values()) <= TOL
     sim.close()
 
 
-def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(torch_dev):
+def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(oracle, torch_dev):
     """Eight types with step budgets in the processing order, some agents
     dead: the pipe's global step index carries the budgets across runs, so
     the result equals one resident rollout bit for bit.  The snapshots hold
     every agent's position, also of the dead agents and of those past their
-    budget (which the kernel does not advance)."""
+    budget (which the kernel does not advance); the live agents' snapshots
+    match the reference rolled over the same epochs with the same budgets."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Pipe, Simulator
     sw = I.config3(scale=512)
@@ -185,26 +220,37 @@ def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(torch_dev):
     perm = sim.order_by_type(ti)
     pipe = Pipe(sim, n)
     st = torch.from_numpy(sw.state).to(dev)
+    ct = torch.zeros((10, n), dtype=torch.float32, device=dev)
     snaps = torch.full((n_epochs, per, 3, n), -1.0, dtype=torch.float32, pin_memory=True)
     for e in range(n_epochs):
         pipe.push(wps[e])
         pipe.run(st, epoch_steps, sw.dt, type_idx=ti, perm=perm, alive=alive, snap_every=snap_every,
-                 snaps=snaps[e])
+                 snaps=snaps[e], carry=ct)
     pipe.sync()
     assert pipe.stats() == (n_epochs * per, n_epochs * per)
     ref = torch.from_numpy(sw.state).to(dev)
+    rc = torch.zeros((10, n), dtype=torch.float32, device=dev)
     rwp = torch.from_numpy(wps).to(dev)
     ref_snaps = []
     for k in range(n_epochs * per):
         sim.step(ref, snap_every, sw.dt, type_idx=ti, perm=perm, alive=alive, wp=rwp,
-                 resample_every=epoch_steps, step0=k * snap_every)
+                 resample_every=epoch_steps, step0=k * snap_every, carry=rc)
         ref_snaps.append(ref[0:3].cpu().numpy())
     torch.cuda.synchronize()
-    assert torch.equal(st, ref)
+    assert torch.equal(st, ref) and torch.equal(ct, rc)
     assert np.array_equal(snaps.numpy().reshape(-1, 3, n), np.stack(ref_snaps))
     dead = alive.cpu().numpy() == 0
     assert np.array_equal(st.cpu().numpy()[:, dead], sw.state[:, dead])
     assert np.array_equal(snaps.numpy()[-1, -1][:, dead], sw.state[0:3, dead])
+    # live agents against the reference, one snapshot interval at a time
+    live = np.where(~dead)[0]
+    sub = I.subset(sw, live)
+    sub.wp = wps[:, :, live].copy()
+    ref_pos, exact = oracle_snapshots(oracle, sub, n_epochs * epoch_steps, snap_every, type_idx=sub.type_idx,
+                                      wp=sub.wp, resample_every=epoch_steps)
+    assert_snapshots_match(snaps.numpy().reshape(-1, 3, n)[:, :, live], ref_pos)
+    errs = rel_errors(st.cpu().numpy()[:, live], exact, sw.types, sub.type_idx)
+    assert max(v[0] for v in errs.values()) <= TOL, errs
     pipe.close()
     sim.close()
 
@@ -223,7 +269,7 @@ def test_pipe_rejects_invalid_use(torch_dev):
         pipe.push(np.zeros((4, 500), np.float32))
     pipe.push(sw.wp[0])
     lib = L.load()
-    sst = L.State(C.c_void_p(st.data_ptr()), st.stride(0))
+    sst = L.State(C.c_void_p(st.data_ptr()), st.stride(0), None, 0)
     pp = L.Params(None, None, None, 0, None)
     assert lib.potato_pipe_run(pipe._h, C.byref(sst), C.byref(pp), C.c_float(sw.dt), 20, 10, None,
                                None) == L.EINVAL                      # snapshot due, no buffer
@@ -248,7 +294,7 @@ def test_pipe_rejects_invalid_use(torch_dev):
         step_before = pipe.stats()
         assert lib.potato_pipe_run(pipe._h, C.byref(sst), C.byref(pp), C.c_float(sw.dt), 64, 1, small,
                                    C.c_void_p(torch.cuda.current_stream().cuda_stream)) == L.EINVAL
-        assert "fewer than" in lib.potato_last_error().decode()
+        assert "fewer than" in lib.potato_last_error(None).decode()
         torch.cuda.synchronize()
         assert torch.equal(st, before) and pipe.stats() == step_before
         assert hip.hipHostFree(small) == 0
