@@ -1,4 +1,5 @@
-"""ctypes binding of the FP64 CPU reference (``oracle.cpp``).
+"""ctypes binding of the FP64 CPU reference (``oracle.cpp`` for the
+quadrotors, ``vehicles.cpp`` for the cars and fixed-wing aircraft).
 
 TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
 benchmark's CPU-baseline leg, never by the simulator.  It imports nothing
@@ -16,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.cpp")
+SOURCES = (SRC_PATH, os.path.join(HERE, "vehicles.cpp"))
 
 TYPE_FIELDS = ("mass", "Ixx", "Iyy", "Izz", "arm", "alpha", "k_f", "k_m",
                "tau_m", "drag", "w_max", "w_ref")
@@ -27,16 +29,22 @@ class OracleType(C.Structure):
         ("gains", C.c_double * 9), ("step_budget", C.c_int64)]
 
 
+class OracleVehicle(C.Structure):
+    _fields_ = [("kind", C.c_int64), ("mass", C.c_double), ("drag", C.c_double),
+                ("veh", C.c_double * 12), ("step_budget", C.c_int64)]
+
+
 class OracleGlobals(C.Structure):
     _fields_ = [(f, C.c_double) for f in GLOBAL_FIELDS]
 
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with g++ (FP64, no contraction, OpenMP)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+    newest = max(os.path.getmtime(p) for p in SOURCES)
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < newest:
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
-                               "-ffp-contract=off", "-fno-fast-math", SRC_PATH, "-o", tmp])
+                               "-ffp-contract=off", "-fno-fast-math", *SOURCES, "-o", tmp])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -63,6 +71,12 @@ def lib():
         L.oracle_detect_collisions.restype = C.c_int64
         L.oracle_collides.argtypes = [P, I64, I64, P, P, I, P, P, I64, P, I]
         L.oracle_collides.restype = C.c_int
+        L.oracle_vehicle_rollout.argtypes = [P, I, D, I, P, I64, I64, P, P, P, I, I, I64, I64, D,
+                                             I64, I]
+        L.oracle_vehicle_derivative.argtypes = [P, D, P, P, P]
+        L.oracle_vehicle_guidance.argtypes = [P, D, P, P, P]
+        for fn in ("oracle_vehicle_rollout", "oracle_vehicle_derivative", "oracle_vehicle_guidance"):
+            getattr(L, fn).restype = C.c_int
         for fn in ("oracle_rollout", "oracle_jacobian", "oracle_derivative", "oracle_controller",
                    "oracle_allocation", "oracle_count_ops", "oracle_max_threads"):
             getattr(L, fn).restype = C.c_int
@@ -86,6 +100,17 @@ def make_types(types) -> C.Array:
     for i, t in enumerate(types):
         arr[i] = make_type(t)
     return arr
+
+
+def make_vehicle(t: dict) -> OracleVehicle:
+    """Widen one car or fixed-wing type dict to FP64."""
+    o = OracleVehicle()
+    o.kind = int(t["kind"])
+    o.mass, o.drag = float(t["mass"]), float(t["drag"])
+    for k, v in enumerate(t["veh"]):
+        o.veh[k] = float(v)
+    o.step_budget = int(t["budget"])
+    return o
 
 
 def make_globals(g: dict) -> OracleGlobals:
@@ -124,6 +149,81 @@ def rollout(state, types, glob, mode, dt, n_steps, *, type_idx=None, gains=None,
     if rc != 0:
         raise ValueError("oracle_rollout rejected its arguments")
     return s
+
+
+def kind_of(t: dict) -> int:
+    """Vehicle kind of a type dict: 0 quadrotor (the default), 1 car, 2 fixed wing."""
+    return int(t.get("kind", 0))
+
+
+def vehicle_rollout(state, types, g, mode, dt, n_steps, *, type_idx=None, motor_cmd=None, wp=None,
+                    resample_every=0, step0=0, threads=None):
+    """Advance a copy of ``state`` ([30, N]) of cars and fixed-wing aircraft
+    (every type in ``types`` of kind 1 or 2) and return it."""
+    s = np.array(state, dtype=np.float64, copy=True, order="C")
+    n = s.shape[1]
+    ti = None if type_idx is None else np.ascontiguousarray(type_idx, dtype=np.int32)
+    mc, w = _f64(motor_cmd), _f64(wp)
+    ne = 0 if w is None else w.shape[0]
+    arr = (OracleVehicle * len(types))()
+    for i, t in enumerate(types):
+        arr[i] = make_vehicle(t)
+    rc = lib().oracle_vehicle_rollout(C.addressof(arr), len(types), float(g), int(mode), _p(s), n, n, _p(ti),
+                                      _p(mc), _p(w), ne, int(resample_every), n, int(step0), float(dt),
+                                      int(n_steps), int(threads or threads_default()))
+    if rc != 0:
+        raise ValueError("oracle_vehicle_rollout rejected its arguments")
+    return s
+
+
+def rollout_kinds(state, types, glob, mode, dt, n_steps, *, type_idx=None, gains=None, motor_cmd=None,
+                  wp=None, resample_every=0, step0=0, threads=None):
+    """``rollout`` of a swarm that mixes vehicle kinds: each kind's agents go
+    through its own reference (quadrotors through ``oracle_rollout``, cars
+    and fixed-wing aircraft through ``oracle_vehicle_rollout``) with the
+    type table restricted to that kind; per-agent gains apply to the
+    quadrotors."""
+    s = np.array(state, dtype=np.float64, copy=True, order="C")
+    n = s.shape[1]
+    ti = np.zeros(n, dtype=np.int64) if type_idx is None else np.asarray(type_idx, dtype=np.int64)
+    kinds = np.array([kind_of(t) for t in types])
+    agent_kind = kinds[np.minimum(ti, len(types) - 1)]
+    cols = lambda a, idx, ax: None if a is None else np.ascontiguousarray(np.take(a, idx, axis=ax))
+    for group in ((0,), (1, 2)):
+        tsel = [k for k in range(len(types)) if kinds[k] in group]
+        idx = np.where(np.isin(agent_kind, group))[0]
+        if idx.size == 0:
+            continue
+        remap = np.full(len(types), -1, dtype=np.int64)
+        remap[tsel] = np.arange(len(tsel))
+        sub_ti = remap[ti[idx]]
+        sub_types = [types[k] for k in tsel]
+        kw = dict(type_idx=sub_ti, motor_cmd=cols(motor_cmd, idx, 1), wp=cols(wp, idx, 2),
+                  resample_every=resample_every, step0=step0, threads=threads)
+        if group == (0,):
+            out = rollout(s[:, idx], sub_types, glob, mode, dt, n_steps, gains=cols(gains, idx, 1), **kw)
+        else:
+            out = vehicle_rollout(s[:, idx], sub_types, glob["g"], mode, dt, n_steps, **kw)
+        s[:, idx] = out
+    return s
+
+
+def vehicle_derivative(t: dict, g: float, x, u):
+    """Right-hand side of one car or fixed-wing aircraft: x[7], u[3] -> dx[7]."""
+    x = _f64(x); u = _f64(u); dx = np.zeros(7)
+    o = make_vehicle(t)
+    if lib().oracle_vehicle_derivative(C.byref(o), float(g), _p(x), _p(u), _p(dx)) != 0:
+        raise ValueError("oracle_vehicle_derivative rejected its arguments")
+    return dx
+
+
+def vehicle_guidance(t: dict, g: float, x, wp):
+    """Closed-loop inputs u[3] of one car or fixed-wing aircraft."""
+    x = _f64(x); w = _f64(wp); u = np.zeros(3)
+    o = make_vehicle(t)
+    if lib().oracle_vehicle_guidance(C.byref(o), float(g), _p(x), _p(w), _p(u)) != 0:
+        raise ValueError("oracle_vehicle_guidance rejected its arguments")
+    return u
 
 
 def jacobian(state, types, glob, dt, n_steps, *, wp, type_idx=None, gains=None,

@@ -278,6 +278,125 @@ def limits_swarm(n_group: int = 64, n_steps: int = 1000) -> Swarm:
                  extra=dict(groups=("climb", "descend", "yaw", "tumble")))
 
 
+# ---------------------------------------------------------------------------
+# Cars and fixed-wing aircraft (vehicle kinds 1 and 2)
+# ---------------------------------------------------------------------------
+KIND_QUAD, KIND_CAR, KIND_WING = 0, 1, 2
+# Per-kind parameter vector ``veh`` (12 entries, the last unused):
+CAR_FIELDS = ("L", "l_r", "tau_delta", "delta_max", "a_max", "v_cruise", "rho", "lam",
+              "k_orb", "k_head", "k_speed")
+WING_FIELDS = ("tau_V", "tau_phi", "tau_gamma", "phi_max", "gamma_max", "V_cruise", "rho",
+               "lam", "k_orb", "k_head", "k_alt")
+# A passenger-car-sized vehicle circling at 8 m/s on a 25 m orbit, and a
+# small fixed-wing aircraft at 18 m/s on an 80 m orbit.
+CAR_DEFAULTS = dict(L=2.6, l_r=1.3, tau_delta=0.1, delta_max=0.5, a_max=3.0, v_cruise=8.0,
+                    rho=25.0, lam=1.0, k_orb=2.0, k_head=1.5, k_speed=0.5)
+WING_DEFAULTS = dict(tau_V=1.0, tau_phi=0.3, tau_gamma=0.5, phi_max=0.6, gamma_max=0.25,
+                     V_cruise=18.0, rho=80.0, lam=1.0, k_orb=1.5, k_head=1.2, k_alt=0.05)
+WING_ALTITUDE = (40.0, 60.0)
+
+
+def vehicle_type(kind: int, mass: float, drag: float, radius: float, budget: int = NO_BUDGET,
+                 **params) -> dict:
+    """A car (kind 1) or fixed-wing (kind 2) type dict: float32 mass, linear
+    drag coefficient (cars: longitudinal, N s/m), collision radius and the
+    12-entry parameter vector ``veh`` in the order of CAR_FIELDS or
+    WING_FIELDS.  Quadrotor fields are absent (the binding sends zeros)."""
+    fields, defaults = (CAR_FIELDS, CAR_DEFAULTS) if kind == KIND_CAR else (WING_FIELDS, WING_DEFAULTS)
+    unknown = set(params) - set(fields)
+    if unknown:
+        raise ValueError(f"unknown parameters {sorted(unknown)}")
+    vals = dict(defaults)
+    vals.update(params)
+    veh = np.zeros(12, dtype=np.float32)
+    veh[:len(fields)] = f32([vals[f] for f in fields])
+    return dict(kind=int(kind), mass=np.float32(mass), drag=np.float32(drag), radius=np.float32(radius),
+                veh=veh, gains=np.zeros(N_GAINS, dtype=np.float32), budget=int(budget))
+
+
+def car_type(mass: float = 1200.0, drag: float = 60.0, radius: float = 1.5, budget: int = NO_BUDGET,
+             **params) -> dict:
+    return vehicle_type(KIND_CAR, mass, drag, radius, budget, **params)
+
+
+def wing_type(mass: float = 2.0, radius: float = 0.8, budget: int = NO_BUDGET, **params) -> dict:
+    return vehicle_type(KIND_WING, mass, 0.0, radius, budget, **params)
+
+
+def veh_param(t: dict, name: str) -> float:
+    fields = CAR_FIELDS if t["kind"] == KIND_CAR else WING_FIELDS
+    return float(t["veh"][fields.index(name)])
+
+
+def orbit_starts(r: np.random.Generator, t: dict, centre: np.ndarray) -> np.ndarray:
+    """Initial rows 0-6 of vehicles of type ``t`` around orbit centres
+    ``centre`` [3, n]: at a distance U[0.5, 1.5] x rho in a uniform
+    direction theta, heading along the orbit's direction of travel
+    (theta + lambda pi/2) give or take U[-pi/3, pi/3], so every start has a
+    course error well inside (-pi, pi); cars on the ground at rest to
+    cruise speed with the wheels straight, aircraft within 5 m of the orbit
+    altitude at 0.9-1.1 x cruise speed, wings level."""
+    n = centre.shape[1]
+    rho, lam = veh_param(t, "rho"), veh_param(t, "lam")
+    d = r.uniform(0.5, 1.5, n) * rho
+    th = r.uniform(0.0, 2.0 * math.pi, n)
+    x = np.zeros((7, n))
+    x[0] = centre[0] + d * np.cos(th)
+    x[1] = centre[1] + d * np.sin(th)
+    x[4] = th + lam * 0.5 * math.pi + r.uniform(-math.pi / 3.0, math.pi / 3.0, n)
+    if t["kind"] == KIND_CAR:
+        x[2] = 0.0
+        x[3] = veh_param(t, "v_cruise") * r.uniform(0.0, 1.0, n)
+    else:
+        x[2] = centre[2] + r.uniform(-5.0, 5.0, n)
+        x[3] = veh_param(t, "V_cruise") * r.uniform(0.9, 1.1, n)
+    return x
+
+
+KINDS_FRACTIONS = (0.5, 0.25, 0.25)
+
+
+def config_kinds(n: int = 1 << 20, n_steps: int = 10000, resample_every: int = 2000,
+                 fractions=KINDS_FRACTIONS) -> Swarm:
+    """Quadrotors, cars and fixed-wing aircraft in one batch (the three
+    robot kinds of Sec. II-B; the aircraft circle as in the first demo of
+    Sec. IV).  Types: 0 the base quadrotor, 1-2 cars circling
+    counter-clockwise / clockwise, 3-4 aircraft likewise.  ``fractions``
+    splits the agents between quadrotors, cars and aircraft (each vehicle
+    kind evenly between its two directions); labels are shuffled.
+    Quadrotors hover in the box and get new waypoints every
+    ``resample_every`` steps as in the scale workload; a car's or
+    aircraft's waypoint is its orbit centre (uniform in the box's
+    footprint, on the ground for cars, at 40-60 m for aircraft), the same
+    in every epoch."""
+    r = rng(6, 0)
+    types = [base_type(), car_type(lam=1.0), car_type(lam=-1.0), wing_type(lam=1.0), wing_type(lam=-1.0)]
+    n_q = int(round(fractions[0] * n))
+    n_c = int(round(fractions[1] * n))
+    n_w = n - n_q - n_c
+    counts = [n_q, n_c - n_c // 2, n_c // 2, n_w - n_w // 2, n_w // 2]
+    labels = np.concatenate([np.full(c, t, dtype=np.uint8) for t, c in enumerate(counts)])
+    r.shuffle(labels)
+    n_ep = max(1, -(-n_steps // resample_every))
+    pos = _box_positions(r, n)
+    s = np.zeros((N_ROWS, n), dtype=np.float64)
+    s[0:3] = pos
+    s[6] = 1.0
+    wp = np.stack([_box_positions(r, n) for _ in range(n_ep)])
+    for t in range(1, len(types)):
+        idx = np.where(labels == t)[0]
+        if idx.size == 0:
+            continue
+        centre = np.stack([r.uniform(0.0, BOX[0], idx.size), r.uniform(0.0, BOX[1], idx.size),
+                           np.zeros(idx.size) if types[t]["kind"] == KIND_CAR
+                           else r.uniform(*WING_ALTITUDE, idx.size)])
+        s[:, idx] = 0.0
+        s[0:7, idx] = orbit_starts(r, types[t], centre)
+        wp[:, :, idx] = centre[None]
+    return Swarm("kinds", 1, 1e-3, n_steps, f32(s), types, globals_f32(), type_idx=labels,
+                 wp=f32(wp), resample_every=resample_every, extra=dict(counts=counts))
+
+
 def subset(sw: Swarm, idx: np.ndarray) -> Swarm:
     """The same workload restricted to the agents ``idx`` (column gather)."""
     idx = np.asarray(idx)

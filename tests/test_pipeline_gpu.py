@@ -40,14 +40,22 @@ def padded(state, ld):
     return buf
 
 
-def oracle_snapshots(oracle, sw, n_steps, snap_every, **kw):
-    """The reference rolled in chunks of snap_every steps from global step 0:
-    (positions after each chunk [k, 3, n], final state [30, n])."""
+def oracle_snapshots(oracle, sw, n_runs, run_steps, snap_every, **kw):
+    """The reference over n_runs runs of run_steps steps from global step 0,
+    stopped where the pipe takes its snapshots: after every snap_every steps
+    of each run (a remainder of a run shorter than snap_every has none).
+    Returns (positions at each snapshot [k, 3, n], final state [30, n])."""
     x = sw.state
     out = []
-    for k in range(n_steps // snap_every):
-        x = oracle.rollout(x, sw.types, sw.glob, sw.mode, sw.dt, snap_every, step0=k * snap_every, **kw)
-        out.append(x[0:3].copy())
+    t = 0
+    for e in range(n_runs):
+        for j in range(run_steps // snap_every):
+            at = e * run_steps + (j + 1) * snap_every
+            x = oracle.rollout(x, sw.types, sw.glob, sw.mode, sw.dt, at - t, step0=t, **kw)
+            t = at
+            out.append(x[0:3].copy())
+    if t < n_runs * run_steps:
+        x = oracle.rollout(x, sw.types, sw.glob, sw.mode, sw.dt, n_runs * run_steps - t, step0=t, **kw)
     return np.stack(out), x
 
 
@@ -148,7 +156,7 @@ def test_decision_loop_matches_resident_rollout_and_oracle(oracle, torch_dev, n,
         assert np.array_equal(a, b), f"snapshot {k}"
     # the decision really used streamed positions: epoch 2 waypoints follow snapshot data
     assert not np.array_equal(wps[2], wps[1])
-    ref_pos, exact = oracle_snapshots(oracle, sw, n_epochs * epoch_steps, snap_every, wp=wps,
+    ref_pos, exact = oracle_snapshots(oracle, sw, n_epochs, epoch_steps, snap_every, wp=wps,
                                       resample_every=epoch_steps)
     assert_snapshots_match(np.stack(flat)[:, :, :n], ref_pos)
     errs = rel_errors(got[:30, :n], exact, sw.types)
@@ -246,7 +254,7 @@ def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(oracle, torch_de
     live = np.where(~dead)[0]
     sub = I.subset(sw, live)
     sub.wp = wps[:, :, live].copy()
-    ref_pos, exact = oracle_snapshots(oracle, sub, n_epochs * epoch_steps, snap_every, type_idx=sub.type_idx,
+    ref_pos, exact = oracle_snapshots(oracle, sub, n_epochs, epoch_steps, snap_every, type_idx=sub.type_idx,
                                       wp=sub.wp, resample_every=epoch_steps)
     assert_snapshots_match(snaps.numpy().reshape(-1, 3, n)[:, :, live], ref_pos)
     errs = rel_errors(st.cpu().numpy()[:, live], exact, sw.types, sub.type_idx)
