@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--agents", type=int, default=1 << 20)
     ap.add_argument("--sim-steps", type=int, default=10000)
     ap.add_argument("--no-extra", action="store_true", help="skip the other forms")
-    ap.add_argument("--forms", default="plain,fused_eager,hetero,collisions,pipeline,fwd_bwd",
+    ap.add_argument("--forms", default="plain,fused_eager,hetero,kinds,collisions,pipeline,fwd_bwd",
                     help="comma-separated subset of the other forms to run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--sweep", action="store_true",
@@ -250,6 +250,8 @@ def extra_forms(torch, dev, stream, sim, state, carry, wp, sw, T, which):
         log(f"fused eager: {res['fused_eager']['agent_steps_per_s']:.4e} agent-steps/s")
     if "hetero" in which:
         res.update(hetero_form(torch, dev, timed))
+    if "kinds" in which:
+        res.update(kinds_form(torch, dev, timed, N))
     if "collisions" in which:
         res["collisions"] = collisions_form(torch, dev, timed, N)
     if "pipeline" in which:
@@ -329,6 +331,38 @@ def hetero_form(torch, dev, timed):
                       "roofline": alu_roofline(work / (ms * 1e-3))}
         log(f"{label}: {res[label]['agent_steps_per_s']:.4e} agent-steps/s")
     hsim.close()
+    return res
+
+
+def kinds_form(torch, dev, timed, N, steps=2000):
+    """Quadrotors, cars and fixed-wing aircraft in one launch (half, a
+    quarter, a quarter; labels shuffled), closed loop, in index order and in
+    the type order; and the same launch with only the quadrotors alive, so
+    that the cars' and aircraft's share of the time shows."""
+    from paper_2308_12698_amd import inputs as I
+    from paper_2308_12698_amd.sim import Simulator
+    kw = I.config_kinds(n=N, n_steps=steps)
+    ksim = Simulator(kw.types, kw.glob, mode=1, form="fused", steps_per_launch=1000, use_graph=True)
+    ks = torch.from_numpy(kw.state).to(dev)
+    ti = torch.from_numpy(kw.type_idx).to(dev)
+    kwp = torch.from_numpy(kw.wp).to(dev)
+    perm = ksim.order_by_type(ti)
+    quads_only = torch.from_numpy((kw.type_idx == 0).astype(np.uint8)).to(dev)
+    res = {}
+    for label, order, alive in (("kinds_unordered", None, None), ("kinds", perm, None),
+                                ("kinds_quads_only", perm, quads_only)):
+        s0 = ks.clone()
+        c0 = torch.zeros((10, kw.n), dtype=torch.float32, device=dev)
+        ms = timed(lambda: ksim.step(s0, steps, kw.dt, type_idx=ti, perm=order, wp=kwp,
+                                     resample_every=kw.resample_every, carry=c0, alive=alive), reps=2)
+        n_adv = kw.n if alive is None else int(kw.extra["counts"][0])
+        res[label] = {"agent_steps_per_s": n_adv * steps / (ms * 1e-3), "n_agents": kw.n,
+                      "agents_advanced": n_adv, "sim_steps": steps, "rollout_ms": ms,
+                      "counts_quad_car_wing": [int(kw.extra["counts"][0]),
+                                               int(sum(kw.extra["counts"][1:3])),
+                                               int(sum(kw.extra["counts"][3:5]))]}
+        log(f"{label}: {res[label]['agent_steps_per_s']:.4e} agent-steps/s ({ms:.2f} ms)")
+    ksim.close()
     return res
 
 

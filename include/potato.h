@@ -44,7 +44,8 @@
  *
  * Rounding carries (optional): float32 carry[10][carry_ld], one column per
  * agent (carry_ld >= n_agents): 0-2 position, 3-5 velocity, 6 J, 7-9
- * position-loop integral.  Each holds the low-order part that an FP32
+ * position-loop integral (cars and fixed-wing aircraft: row k holds the
+ * carry of state row k, k = 0-6).  Each holds the low-order part that an FP32
  * update of its row dropped (compensated summation, Dekker's Fast2Sum), so
  * the represented value is row + carry; a fresh state has carries 0 and
  * they stay below one ulp of their row.  With a carry buffer the
@@ -81,20 +82,44 @@ enum { POTATO_FORM_AUTO = 0, POTATO_FORM_PLAIN = 1, POTATO_FORM_FUSED = 2 };
 enum { POTATO_ROWS = 30, POTATO_CARRY_ROWS = 10, POTATO_CKPT_ROWS = 40 };
 enum { POTATO_GAINS = 9, POTATO_MAX_TYPES = 256 };
 
-/* One airframe type (all FP32, SI units).  alpha is the rotor-arm angle of
- * the allocation matrix of eq. (3) (pi/4 for an X frame); k_f, k_m are the
- * thrust and torque coefficients of eq. (2) in N/(rad/s)^2 and N m/(rad/s)^2;
- * tau_m the rotor time constant (s); drag the linear drag coefficient (N s/m);
- * w_max the rotor speed limit (rad/s); w_ref the reference speed the stored
- * rotor rows are relative to (any value; the hover speed keeps them small);
- * radius the collision radius (m) used by potato_detect_collisions.
- * gains = [kpp kip kdp kpa kia kda kpr kir kdr] (position, attitude, rate
- * loops; P, I, D).  step_budget: an agent of this type is advanced only
- * while its global step index is below it (INT32_MAX = unlimited). */
+/* One agent type (all FP32, SI units, angles in radians).
+ *
+ * kind POTATO_KIND_QUAD (0), the quadrotor of Sec. II-B: alpha is the
+ * rotor-arm angle of the allocation matrix of eq. (3) (pi/4 for an X frame);
+ * k_f, k_m are the thrust and torque coefficients of eq. (2) in
+ * N/(rad/s)^2 and N m/(rad/s)^2; tau_m the rotor time constant (s); drag
+ * the linear drag coefficient (N s/m); w_max the rotor speed limit (rad/s);
+ * w_ref the reference speed the stored rotor rows are relative to (any
+ * value; the hover speed keeps them small).  gains = [kpp kip kdp kpa kia
+ * kda kpr kir kdr] (position, attitude, rate loops; P, I, D).  veh unused.
+ *
+ * kinds POTATO_KIND_CAR (1) and POTATO_KIND_WING (2), the two other robot
+ * kinds of Sec. II-B: a car on the kinematic bicycle model and a
+ * fixed-wing aircraft on the coordinated-turn guidance model, both guided
+ * in closed loop around an orbit of radius rho about their waypoint
+ * (circle trajectories as in the first demonstration of Sec. IV).  Only
+ * mass, drag (car: longitudinal, N s/m), radius, step_budget, kind and
+ * veh are read:
+ *   car:  veh = [L wheelbase (m), l_r centre of mass to rear axle (m),
+ *                tau_delta steering lag (s), delta_max (rad),
+ *                a_max (m/s^2), v_cruise (m/s), rho (m), lambda (+1
+ *                counter-clockwise, -1 clockwise), k_orb, k_head, k_speed];
+ *         needs L, tau_delta, rho > 0 and rho > l_r.
+ *   wing: veh = [tau_V, tau_phi, tau_gamma (s), phi_max, gamma_max (rad),
+ *                V_cruise (m/s), rho (m), lambda, k_orb, k_head, k_alt];
+ *         needs the time constants, V_cruise and rho > 0.
+ * Their state rows and inputs are listed at potato_step.
+ *
+ * Every kind: radius is the collision radius (m) used by
+ * potato_detect_collisions; step_budget: an agent of this type is advanced
+ * only while its global step index is below it (INT32_MAX = unlimited). */
+enum { POTATO_KIND_QUAD = 0, POTATO_KIND_CAR = 1, POTATO_KIND_WING = 2 };
 typedef struct {
     float mass, Ixx, Iyy, Izz, arm, alpha, k_f, k_m, tau_m, drag, w_max, w_ref, radius;
     float gains[9];
     int32_t step_budget;
+    int32_t kind;
+    float veh[12];
 } potato_type_params;
 
 /* Controller limits shared by all types: gravity g, position-error
@@ -186,12 +211,22 @@ potato_status potato_set_options(potato_ctx* ctx, const potato_options* opts);
 /*
  * Advance agents 0..n_agents-1 by n_steps time steps of length dt in place.
  * An agent of type t takes min(n_steps, max(0, step_budget_t - step0))
- * steps.  Errors (POTATO_EINVAL): ctx/state/params/cmds NULL, rows NULL,
+ * steps.  Cars and fixed-wing aircraft (types of kind 1 and 2) use rows 0-6
+ * of the state: 0-2 position, 3 speed (m/s), 4 heading (car yaw, aircraft
+ * course; from +x towards +y), 5 steering angle (car) or bank angle
+ * (aircraft, positive turns left), 6 flight-path angle (aircraft); they do
+ * not touch rows 7-29, nor a car rows 2 and 6 (nor those carry rows); for
+ * them carry row k (k = 0-6) holds the rounding carry of state row k.  Their open-loop inputs are motor_cmd rows 0-2
+ * (car: acceleration, steering command; aircraft: airspeed, bank and
+ * flight-path commands), held for the call; in closed loop their waypoint
+ * is the centre of the orbit they fly.  Errors (POTATO_EINVAL): ctx/state/params/cmds NULL, rows NULL,
  * n_agents outside [1, 2^30], ld < n_agents, carry given with carry_ld <
  * n_agents, n_steps < 0, dt not finite and > 0, missing motor_cmd (open
  * loop) or wp / n_epochs < 1 (closed loop), cmds->ld < n_agents, gains_ld <
  * n_agents when gains are given, ckpt set with ckpt_every < 1 or without a
- * carry buffer.  n_steps == 0 is a no-op.
+ * carry buffer.  POTATO_EUNSUPPORTED: ckpt with a type table that holds
+ * cars or fixed-wing aircraft (the adjoint covers quadrotors).  n_steps == 0
+ * is a no-op.
  * ckpt (optional, device float[ceil(n_steps/ckpt_every)][40][ld]): slot c
  * receives the state (rows 0-29) and its carries (rows 30-39) at
  * call-relative step c*ckpt_every, before that step; it is what
@@ -252,7 +287,8 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
  * recomputes the next segment while another reverses the current one, with
  * the same result bit for bit.  Errors: POTATO_EINVAL as in potato_step, plus null ckpt,
  * grad_final or grad_x0, ckpt_every < 1 or a workspace that is too small;
- * POTATO_EUNSUPPORTED in open-loop mode.  grad_x0 may alias grad_final.
+ * POTATO_EUNSUPPORTED in open-loop mode and for a context whose type table
+ * holds cars or fixed-wing aircraft.  grad_x0 may alias grad_final.
  */
 int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* params, int64_t n_agents,
                                         int32_t ckpt_every);

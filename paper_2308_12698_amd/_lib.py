@@ -25,7 +25,8 @@ LIMIT_FIELDS = ("g", "r_sat", "ipos_max", "iatt_max", "irate_max", "az_min_frac"
 
 class TypeParams(C.Structure):
     _fields_ = [(f, C.c_float) for f in TYPE_FIELDS] + [
-        ("gains", C.c_float * 9), ("step_budget", C.c_int32)]
+        ("gains", C.c_float * 9), ("step_budget", C.c_int32), ("kind", C.c_int32),
+        ("veh", C.c_float * 12)]
 
 
 class Limits(C.Structure):
@@ -106,8 +107,8 @@ def load():
     L.potato_version.restype = C.c_char_p
     for fn in ("potato_create", "potato_destroy", "potato_set_options", "potato_step",
                "potato_autotune", "potato_order_by_type", "potato_step_backward",
-               "potato_detect_collisions", "potato_pipe_create", "potato_pipe_push",
-               "potato_pipe_run", "potato_pipe_wait_snapshots", "potato_pipe_sync",
+               "potato_detect_collisions", "potato_pipe_create",
+               "potato_pipe_push", "potato_pipe_run", "potato_pipe_wait_snapshots", "potato_pipe_sync",
                "potato_pipe_stats", "potato_pipe_destroy", "potato_count_nonfinite"):
         getattr(L, fn).restype = C.c_int
     _lib = L
@@ -120,12 +121,24 @@ def check(status: int):
 
 
 def make_type_params(types) -> C.Array:
+    """potato_type_params of type dicts: a quadrotor (kind 0, the default)
+    gives every field of TYPE_FIELDS; a car or fixed-wing aircraft (kind 1,
+    2) gives mass, drag, radius and ``veh`` (other fields are sent as 0)."""
     arr = (TypeParams * len(types))()
     for i, t in enumerate(types):
+        kind = int(t.get("kind", 0))
+        arr[i].kind = kind
         for f in TYPE_FIELDS:
-            setattr(arr[i], f, float(t.get(f, t["arm"]) if f == "radius" else t[f]))
+            if kind == 0:
+                v = t.get(f, t["arm"]) if f == "radius" else t[f]
+            else:
+                v = t.get(f, 0.0)
+            setattr(arr[i], f, float(v))
         for k in range(9):
             arr[i].gains[k] = float(t["gains"][k])
+        if kind != 0:
+            for k, v in enumerate(t.get("veh", ())):
+                arr[i].veh[k] = float(v)
         arr[i].step_budget = int(min(int(t.get("budget", 2**31 - 1)), 2**31 - 1))
     return arr
 

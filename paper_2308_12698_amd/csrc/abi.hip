@@ -57,6 +57,7 @@ struct Tuned { int block, steps, grid; };
 struct potato_ctx {
     int device = 0;
     int n_types = 0;
+    bool kinds = false;                /* some type is a car or fixed-wing aircraft */
     std::vector<potato_type_params> params;
     std::vector<TypeConst> consts;
     TypeConst* d_table = nullptr;
@@ -112,6 +113,46 @@ TypeConst derive(const potato_type_params& p, const potato_limits& L) {
     c.inv_kf = (float)(1.0 / kf);
     for (int k = 0; k < 9; ++k) c.gains[k] = p.gains[k];
     c.budget = p.step_budget;
+    c.kind = KIND_QUAD;
+    return c;
+}
+
+/* Constants of a car or fixed-wing type (kinds 1, 2), in double rounded to
+ * FP32 like the quadrotor's. */
+TypeConst derive_vehicle(const potato_type_params& p, const potato_limits& L) {
+    TypeConst c{};
+    VehConst& v = c.veh;
+    double x[12];
+    for (int k = 0; k < 12; ++k) x[k] = p.veh[k];
+    const double pi = 3.14159265358979323846;
+    v.rho = p.veh[6];
+    v.lam = p.veh[7];
+    v.lam_half_pi = (float)(x[7] * 0.5 * pi);
+    v.k_orb_rho = (float)(x[8] / x[6]);
+    v.k_head = p.veh[9];
+    v.k_hold = p.veh[10];
+    if (p.kind == POTATO_KIND_CAR) {
+        const double Lw = x[0], lr = x[1];
+        v.inv_tau[0] = (float)(1.0 / x[2]);
+        v.lim[0] = p.veh[4];
+        v.lim[1] = p.veh[3];
+        v.cruise = p.veh[5];
+        v.cd_m = (float)((double)p.drag / (double)p.mass);
+        v.inv_L = (float)(1.0 / Lw);
+        v.lr_L = (float)(lr / Lw);
+        v.ff = (float)(x[7] * std::atan(Lw / std::sqrt(x[6] * x[6] - lr * lr)));
+    } else {
+        v.inv_tau[0] = (float)(1.0 / x[0]);
+        v.inv_tau[1] = (float)(1.0 / x[1]);
+        v.inv_tau[2] = (float)(1.0 / x[2]);
+        v.lim[1] = p.veh[3];
+        v.lim[2] = p.veh[4];
+        v.cruise = p.veh[5];
+        v.inv_g_rho = (float)(1.0 / ((double)L.g * x[6]));
+        v.g = L.g;
+    }
+    c.budget = p.step_budget;
+    c.kind = p.kind;
     return c;
 }
 
@@ -134,7 +175,30 @@ Limits make_limits(const potato_limits& L, float dt) {
     return r;
 }
 
+potato_status check_vehicle(const potato_type_params& p, int t) {
+    if (!finite_pos(p.mass)) return fail(POTATO_EINVAL, "type %d: mass must be finite and > 0", t);
+    if (!std::isfinite(p.drag) || p.drag < 0.0f || !std::isfinite(p.radius) || p.radius < 0.0f)
+        return fail(POTATO_EINVAL, "type %d: drag and radius must be finite and >= 0", t);
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(p.veh[k])) return fail(POTATO_EINVAL, "type %d: veh[%d] must be finite", t, k);
+    const float* v = p.veh;
+    if (p.kind == POTATO_KIND_CAR) {
+        if (!finite_pos(v[0]) || !finite_pos(v[2]) || !finite_pos(v[6]) || !(v[6] > v[1]) || v[1] < 0.0f)
+            return fail(POTATO_EINVAL, "type %d (car): need L > 0, tau_delta > 0, 0 <= l_r < rho", t);
+        if (v[3] < 0.0f || v[4] < 0.0f)
+            return fail(POTATO_EINVAL, "type %d (car): delta_max and a_max must be >= 0", t);
+    } else {
+        if (!finite_pos(v[0]) || !finite_pos(v[1]) || !finite_pos(v[2]) || !finite_pos(v[5]) || !finite_pos(v[6]))
+            return fail(POTATO_EINVAL, "type %d (fixed wing): need time constants, V_cruise and rho > 0", t);
+        if (v[3] < 0.0f || v[4] < 0.0f)
+            return fail(POTATO_EINVAL, "type %d (fixed wing): phi_max and gamma_max must be >= 0", t);
+    }
+    return POTATO_OK;
+}
+
 potato_status check_type(const potato_type_params& p, int t) {
+    if (p.kind == POTATO_KIND_CAR || p.kind == POTATO_KIND_WING) return check_vehicle(p, t);
+    if (p.kind != POTATO_KIND_QUAD) return fail(POTATO_EINVAL, "type %d: kind must be 0, 1 or 2", t);
     const float vals[] = {p.mass, p.Ixx, p.Iyy, p.Izz, p.arm, p.k_f, p.k_m, p.tau_m};
     for (float v : vals)
         if (!finite_pos(v)) return fail(POTATO_EINVAL, "type %d: mass, inertia, arm, k_f, k_m, tau_m must be finite and > 0", t);
@@ -206,6 +270,9 @@ potato_status validate_step(const potato_ctx* ctx, const potato_state* st, const
                                    "compensated integrator");
     if (ckpt && ctx->opts.form == POTATO_FORM_PLAIN)
         return fail(POTATO_EUNSUPPORTED, "checkpoints need the fused form");
+    if (ckpt && ctx->kinds)
+        return fail(POTATO_EUNSUPPORTED, "checkpoints (the adjoint) cover quadrotors only; the type table "
+                                         "holds cars or fixed-wing aircraft");
     if (pp->type == nullptr && pp->perm != nullptr)
         return fail(POTATO_EUNSUPPORTED, "params.perm needs params.type");
     return POTATO_OK;
@@ -220,6 +287,8 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     P.v.ckpt = ckpt != nullptr;
     P.v.perm = P.v.het && pp->perm != nullptr;
     P.v.carry = st->carry != nullptr;
+    /* a homogeneous launch stages type 0 only */
+    P.v.kinds = P.v.het ? ctx->kinds : ctx->consts[0].kind != KIND_QUAD;
     StepArgs& a = P.a;
     a.rows = st->rows; a.ld = st->ld; a.n = n;
     a.carry = st->carry; a.carry_ld = st->carry ? st->carry_ld : 0;
@@ -335,7 +404,11 @@ potato_status potato_create(potato_ctx** out, const potato_type_params* types, i
     ctx->params.assign(types, types + n_types);
     ctx->limits = *limits;
     ctx->opts = *opts;
-    for (int t = 0; t < n_types; ++t) ctx->consts.push_back(derive(types[t], *limits));
+    for (int t = 0; t < n_types; ++t) {
+        const bool quad = types[t].kind == POTATO_KIND_QUAD;
+        ctx->consts.push_back(quad ? derive(types[t], *limits) : derive_vehicle(types[t], *limits));
+        ctx->kinds = ctx->kinds || !quad;
+    }
     /* rank of each type: longest budget first, ties by index */
     std::vector<int32_t> order(n_types), rank(n_types);
     for (int t = 0; t < n_types; ++t) order[t] = t;
@@ -591,6 +664,9 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
     if (!ctx || !params || !cmds) return fail(POTATO_EINVAL, "ctx, params and cmds must be non-null");
     if (ctx->opts.mode != POTATO_CLOSED_LOOP)
         return fail(POTATO_EUNSUPPORTED, "the adjoint is implemented for closed-loop rollouts");
+    if (ctx->kinds)
+        return fail(POTATO_EUNSUPPORTED, "the adjoint covers quadrotors only; the type table holds cars or "
+                                         "fixed-wing aircraft");
     if (!ckpt || !grad_final || !grad_x0 || !workspace)
         return fail(POTATO_EINVAL, "ckpt, grad_final, grad_x0 and workspace must be non-null");
     if (n_agents < 1 || n_agents > kMaxAgents) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30]");

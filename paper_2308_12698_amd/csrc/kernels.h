@@ -56,6 +56,7 @@ struct Variant {
     bool ckpt;       /* write checkpoints */
     bool perm;       /* processing order */
     bool carry;      /* rounding carries kept in a carry buffer */
+    bool kinds;      /* the type table holds cars or fixed-wing aircraft */
 };
 
 /* Arguments of the adjoint (reverse sweep) launch. */

@@ -17,7 +17,10 @@
  *         CARRY: the adjoint replays the compensated integrator);
  *   PERM  processing order (agents grouped by type);
  *   CARRY rounding carries of p, v, J and the position-loop integral kept
- *         in the caller's carry rows (without: uncompensated updates).
+ *         in the caller's carry rows (without: uncompensated updates);
+ *   KINDS the type table also holds cars and fixed-wing aircraft: a lane
+ *         whose type is one of those runs its own step (vehicle_step.h)
+ *         over rows 0-6 instead of the quadrotor's.
  * k_adjoint: reverse sweep of a checkpointed rollout, one agent per lane,
  * each segment recomputed into a per-wave tape and then reversed;
  * k_adjoint_pipe: the same sweep for small swarms, a recomputing and a
@@ -28,6 +31,7 @@
 #include "kernels.h"
 #include "quad_adjoint.h"
 #include "scan.h"
+#include "vehicle_step.h"
 
 namespace potato {
 
@@ -73,8 +77,64 @@ __device__ __forceinline__ void stage_constants(const TypeConst* table, int n_ty
     __syncthreads();
 }
 
-template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY>
+/* Advance one car or fixed-wing agent (byte offset bo into the rows)
+ * `steps` time steps from rows 0-6 and their carries (carry row k holds the
+ * carry of state row k), store them, and return its final position in p. */
+template <int KIND, int MODE, bool CARRY>
+__device__ __forceinline__ void advance_vehicle(const StepArgs& A, const VehConst& c, const Limits& lim,
+                                                uint32_t bo, int steps, float p[3]) {
+    float* const R = A.rows;
+    const int64_t ld = A.ld;
+    auto row = [&](int k) -> float& { return elem(uniform(R + k * ld), bo); };
+    auto crow = [&](int k) -> float& { return elem(uniform(A.carry + k * A.carry_ld), bo); };
+    float x[7], lo[7], u[3] = {0.0f, 0.0f, 0.0f}, wp[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        x[k] = veh_row<KIND>(k) ? row(k) : 0.0f;
+        lo[k] = CARRY && veh_row<KIND>(k) ? crow(k) : 0.0f;
+    }
+    int64_t next_epoch_step = INT64_MAX;
+    int epoch = 0;
+    if (MODE == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) u[k] = elem(uniform(A.motor_cmd + k * A.cmd_ld), bo);
+    } else {
+        if (A.resample > 0) {
+            const int64_t e0 = A.step0 / A.resample;
+            epoch = e0 < A.n_epochs - 1 ? (int)e0 : A.n_epochs - 1;
+            next_epoch_step = e0 < A.n_epochs - 1 ? (e0 + 1) * A.resample : INT64_MAX;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wp[k] = elem(uniform(A.wp + ((int64_t)epoch * 3 + k) * A.cmd_ld), bo);
+    }
+    for (int s = 0; s < steps; ++s) {
+        if (MODE == 1) {
+            if (A.step0 + s == next_epoch_step) {
+                ++epoch;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    wp[k] = elem(uniform(A.wp + ((int64_t)epoch * 3 + k) * A.cmd_ld), bo);
+                next_epoch_step = epoch < A.n_epochs - 1 ? next_epoch_step + A.resample : INT64_MAX;
+            }
+            veh_guidance<KIND>(c, x, wp, u);
+        }
+        veh_rk4<KIND, CARRY>(c, lim, x, lo, u);
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        if (veh_row<KIND>(k)) row(k) = x[k];
+    if (CARRY) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if (veh_row<KIND>(k)) crow(k) = lo[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = x[k];
+}
+
+template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY, bool KINDS>
 __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
+    static_assert(!(KINDS && CKPT), "checkpoints (the adjoint) cover quadrotors only");
     static_assert(CARRY || !CKPT, "checkpoints hold the carries");
     extern __shared__ float4 lds_raw[];
     Limits* lim_lds = reinterpret_cast<Limits*>(lds_raw);
@@ -122,6 +182,18 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         const int steps = left < A.n_steps ? (int)left : A.n_steps;
         if (steps == 0) {
             snap_stored();
+            continue;
+        }
+        if (KINDS && c.kind != KIND_QUAD) {
+            float pf[3];
+            if (c.kind == KIND_CAR)
+                advance_vehicle<KIND_CAR, MODE, CARRY>(A, c.veh, lim, bo, steps, pf);
+            else
+                advance_vehicle<KIND_WING, MODE, CARRY>(A, c.veh, lim, bo, steps, pf);
+            if (snapshot) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) snap(k) = pf[k];
+            }
             continue;
         }
 
@@ -443,18 +515,22 @@ __global__ void __launch_bounds__(256) k_count_nonfinite(const float* rows, int6
         atomicAdd(count, (unsigned long long)__popcll(mask));
 }
 
-template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY>
+template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY, bool KINDS>
 const void* kfn() {
-    return reinterpret_cast<const void*>(&k_rollout<MODE, HET, GAINS, CKPT, PERM, CARRY>);
+    return reinterpret_cast<const void*>(&k_rollout<MODE, HET, GAINS, CKPT, PERM, CARRY, KINDS>);
 }
 
-/* Checkpoints are only written with carries (the host refuses the other
- * combination), so a variant with ckpt maps to the checkpointing kernel,
- * which reads and writes the carries. */
+/* Checkpoints are only written with carries and only for quadrotor tables
+ * (the host refuses the other combinations), so a variant with ckpt maps to
+ * the checkpointing kernel, which reads and writes the carries. */
 template <int MODE, bool HET, bool GAINS, bool PERM>
 const void* kfn_carry(const Variant& v) {
-    if (MODE == 1 && v.ckpt) return kfn<MODE, HET, GAINS, MODE == 1, PERM, true>();
-    return v.carry ? kfn<MODE, HET, GAINS, false, PERM, true>() : kfn<MODE, HET, GAINS, false, PERM, false>();
+    if (MODE == 1 && v.ckpt) return kfn<MODE, HET, GAINS, MODE == 1, PERM, true, false>();
+    if (v.kinds)
+        return v.carry ? kfn<MODE, HET, GAINS, false, PERM, true, true>()
+                       : kfn<MODE, HET, GAINS, false, PERM, false, true>();
+    return v.carry ? kfn<MODE, HET, GAINS, false, PERM, true, false>()
+                   : kfn<MODE, HET, GAINS, false, PERM, false, false>();
 }
 
 }  // namespace

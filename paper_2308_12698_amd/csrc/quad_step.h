@@ -42,24 +42,51 @@
 
 namespace potato {
 
-/* Per-type constants, derived once on the host from potato_type_params and
- * rounded to FP32. */
-struct TypeConst {
-    float mass, inv_m, cd_m, ncd_m;       /* m, 1/m, c_d/m, -c_d/m */
-    float Ix, Iy, Iz, iIx, iIy, iIz;      /* inertia and its inverse */
-    float F0, F0_g, kf_m;                 /* 4 k_f w_ref^2/m, F0 - g, k_f/m */
-    float F0_2, kf_m2;                    /* 2 F0, 2 k_f/m (exact doublings) */
-    float kf_ls, kf_lc, km;               /* k_f L sin(a), k_f L cos(a), k_m */
-    float ax, ay, az;                     /* k_f L sin(a)/Ixx, k_f L cos(a)/Iyy, k_m/Izz */
-    float gx, gy, gz;                     /* (Izz-Iyy)/Ixx, (Ixx-Izz)/Iyy, (Iyy-Ixx)/Izz */
-    float w_ref, two_w, four_w2;          /* w_ref, 2 w_ref, 4 w_ref^2 */
-    float inv_tau;                        /* 1 / tau_m */
-    float mix_x, mix_y, mix_z;            /* 1/(4 L sin a), 1/(4 L cos a), k_f/(4 k_m) */
-    float f_max, inv_kf;                  /* k_f w_max^2, 1/k_f */
-    float gains[9];
-    int32_t budget;
-    int32_t pad_;
+/* Constants of a car or fixed-wing type (vehicle kinds 1 and 2, see
+ * vehicle_step.h), held in a type-table entry in place of a quadrotor's. */
+struct VehConst {
+    float inv_tau[3];     /* car: 1/tau_delta, 0, 0; wing: 1/tau_V, 1/tau_phi, 1/tau_gamma */
+    float lim[3];         /* car: a_max, delta_max, 0; wing: 0, phi_max, gamma_max */
+    float cruise;         /* cruise speed (m/s) */
+    float rho, lam;       /* orbit radius (m) and direction (+1 counter-clockwise, -1 clockwise) */
+    float lam_half_pi;    /* lam pi/2 */
+    float k_orb_rho;      /* k_orb / rho: gain of the radial error in the course command */
+    float k_head;         /* course error -> steering or bank */
+    float k_hold;         /* car: speed-hold gain k_speed; wing: altitude-hold gain k_alt */
+    float cd_m;           /* car: drag / m (1/s) */
+    float inv_L, lr_L;    /* car: 1/wheelbase, l_r / wheelbase */
+    float ff;             /* car: steering that holds the orbit, lam atan(L / sqrt(rho^2 - l_r^2)) */
+    float inv_g_rho;      /* wing: 1 / (g rho) */
+    float g;              /* wing: gravity */
 };
+
+/* Per-type constants, derived once on the host from potato_type_params and
+ * rounded to FP32.  An entry holds a quadrotor's constants (kind 0) or a
+ * car's or fixed-wing aircraft's (kinds 1, 2) in the same bytes. */
+struct TypeConst {
+    union {
+        struct {
+            float mass, inv_m, cd_m, ncd_m;       /* m, 1/m, c_d/m, -c_d/m */
+            float Ix, Iy, Iz, iIx, iIy, iIz;      /* inertia and its inverse */
+            float F0, F0_g, kf_m;                 /* 4 k_f w_ref^2/m, F0 - g, k_f/m */
+            float F0_2, kf_m2;                    /* 2 F0, 2 k_f/m (exact doublings) */
+            float kf_ls, kf_lc, km;               /* k_f L sin(a), k_f L cos(a), k_m */
+            float ax, ay, az;                     /* k_f L sin(a)/Ixx, k_f L cos(a)/Iyy, k_m/Izz */
+            float gx, gy, gz;                     /* (Izz-Iyy)/Ixx, (Ixx-Izz)/Iyy, (Iyy-Ixx)/Izz */
+            float w_ref, two_w, four_w2;          /* w_ref, 2 w_ref, 4 w_ref^2 */
+            float inv_tau;                        /* 1 / tau_m */
+            float mix_x, mix_y, mix_z;            /* 1/(4 L sin a), 1/(4 L cos a), k_f/(4 k_m) */
+            float f_max, inv_kf;                  /* k_f w_max^2, 1/k_f */
+            float gains[9];
+        };
+        VehConst veh;
+    };
+    int32_t budget;
+    int32_t kind;                                 /* 0 quadrotor, 1 car, 2 fixed wing */
+};
+static_assert(sizeof(TypeConst) == 44 * 4, "type table entry: 42 constants, budget, kind");
+
+enum { KIND_QUAD = 0, KIND_CAR = 1, KIND_WING = 2 };
 
 /* Controller limits and the time step, shared by all agents of a launch. */
 struct Limits {

@@ -24,6 +24,15 @@ GROUPS = {
     "J": (slice(29, 30), 1.0),
 }
 OPEN_LOOP_GROUPS = ("p", "v", "q", "w", "rotor")
+# Cars and fixed-wing aircraft (rows 0-6): position, speed, heading, actuator
+# angle (steering or bank), flight-path angle; floors 1 m, 1 m/s, 1 rad.
+VEHICLE_GROUPS = {
+    "p": (slice(0, 3), 1.0),
+    "speed": (slice(3, 4), 1.0),
+    "heading": (slice(4, 5), 1.0),
+    "actuator": (slice(5, 6), 1.0),
+    "path_angle": (slice(6, 7), 1.0),
+}
 
 
 def w_ref_per_agent(types, type_idx, n):
@@ -47,6 +56,22 @@ def rel_errors(got, ref, types, type_idx=None, groups=None):
         else:
             den = np.maximum(np.linalg.norm(ref[sl], axis=0), floor)
         e = d / den
+        e = np.where(np.isfinite(e), e, np.inf)
+        out[name] = (float(e.max()) if n else 0.0, float(np.percentile(e, 99)) if n else 0.0,
+                     int(e.argmax()) if n else -1)
+    return out
+
+
+def vehicle_rel_errors(got, ref):
+    """Per-group max relative error over car and aircraft agents (columns of
+    got and ref): dict group -> (max, p99, argmax)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    n = ref.shape[1]
+    out = {}
+    for name, (sl, floor) in VEHICLE_GROUPS.items():
+        d = np.linalg.norm(got[sl] - ref[sl], axis=0)
+        e = d / np.maximum(np.linalg.norm(ref[sl], axis=0), floor)
         e = np.where(np.isfinite(e), e, np.inf)
         out[name] = (float(e.max()) if n else 0.0, float(np.percentile(e, 99)) if n else 0.0,
                      int(e.argmax()) if n else -1)

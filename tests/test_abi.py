@@ -65,6 +65,29 @@ def test_create_rejects_invalid_types(lib, bad):
     assert len(lib.potato_last_error(None)) > 0
 
 
+@pytest.mark.parametrize("bad", [
+    I.car_type(rho=1.0, l_r=1.3), I.car_type(L=0.0), I.car_type(tau_delta=0.0), I.car_type(delta_max=-0.1),
+    I.car_type(mass=0.0), I.car_type(drag=-1.0), I.wing_type(V_cruise=0.0), I.wing_type(tau_phi=-1.0),
+    I.wing_type(rho=0.0), I.wing_type(gamma_max=-0.2), I.wing_type(k_head=float("nan")),
+    dict(I.car_type(), kind=3), dict(I.base_type(), kind=-1)])
+def test_create_rejects_invalid_vehicle_types(lib, bad):
+    """Cars and fixed-wing aircraft are validated before any device call
+    (the first type is a valid quadrotor)."""
+    st, h = _create(lib, [I.base_type(), bad])
+    assert st == L.EINVAL and not h.value
+    assert b"type 1" in lib.potato_last_error(None)
+
+
+def test_type_params_layout(lib):
+    """The ctypes view of potato_type_params matches the header: 13 floats,
+    9 gains, the budget, the kind and 12 vehicle parameters."""
+    assert C.sizeof(L.TypeParams) == (13 + 9 + 1 + 1 + 12) * 4
+    assert L.TypeParams.kind.offset == (13 + 9 + 1) * 4
+    arr = L.make_type_params([I.wing_type(rho=55.0), I.base_type()])
+    assert arr[0].kind == 2 and arr[0].veh[6] == 55.0 and arr[0].Ixx == 0.0
+    assert arr[1].kind == 0 and arr[1].mass == 1.0 and list(arr[1].veh) == [0.0] * 12
+
+
 def test_create_rejects_invalid_counts_limits_options(lib):
     t = I.base_type()
     arr = L.make_type_params([t])

@@ -1,0 +1,279 @@
+"""Cars and fixed-wing aircraft in the quadrotors' type-indexed launch (the
+three robot kinds of Sec. II-B; aircraft circling as in the first
+demonstration of Sec. IV), through the C ABI, against the FP64 references
+(quadrotors through the quadrotor reference, cars and aircraft through the
+vehicle reference, each on its own agents).
+
+Tolerance: relative state error <= 1e-4 per agent and state group (the
+quadrotor groups of tests/_util.py for quadrotors; position, speed,
+heading, actuator angle and flight-path angle for the others).  Plain and
+fused launches, ordered and unordered launches, and a kind's agents run
+alone are compared bitwise: a lane's arithmetic does not depend on the
+launch or on its neighbours' kinds.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_12698_amd import inputs as I
+from tests._util import OPEN_LOOP_GROUPS, rel_errors, vehicle_rel_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def _dev(torch, dev, a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def agent_kinds(sw):
+    kinds = np.array([int(t.get("kind", 0)) for t in sw.types])
+    ti = np.zeros(sw.n, dtype=np.int64) if sw.type_idx is None else sw.type_idx.astype(np.int64)
+    return kinds[ti]
+
+
+def gpu_run(torch_dev, sw, n_steps, *, form="fused", steps_per_launch=0, ordered=False, carry=True,
+            alive=None, state=None):
+    """The workload on the GPU: float64 [30, N] after n_steps."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sim = Simulator(sw.types, sw.glob, mode=sw.mode, form=form, steps_per_launch=steps_per_launch,
+                    debug=True)
+    st = _dev(torch, dev, sw.state if state is None else state)
+    ti = _dev(torch, dev, sw.type_idx)
+    perm = sim.order_by_type(ti) if ordered else None
+    ct = torch.zeros((10, sw.n), dtype=torch.float32, device=dev) if carry else None
+    sim.step(st, n_steps, sw.dt, type_idx=ti, perm=perm, motor_cmd=_dev(torch, dev, sw.motor_cmd),
+             wp=_dev(torch, dev, sw.wp), resample_every=sw.resample_every, carry=ct,
+             alive=_dev(torch, dev, alive))
+    torch.cuda.synchronize()
+    got = st.cpu().numpy().astype(np.float64)
+    sim.close()
+    return got
+
+
+def oracle_run(oracle, sw, n_steps, agents=None):
+    sub = sw if agents is None else I.subset(sw, agents)
+    return oracle.rollout_kinds(sub.state, sub.types, sub.glob, sub.mode, sub.dt, n_steps,
+                                type_idx=sub.type_idx, gains=sub.gains, motor_cmd=sub.motor_cmd, wp=sub.wp,
+                                resample_every=sub.resample_every)
+
+
+def assert_kinds_parity(got, ref, sw, agents=None, tol=TOL):
+    """got, ref: [30, len(agents)] of the agents `agents` (default all)."""
+    kinds = agent_kinds(sw)
+    if agents is not None:
+        kinds = kinds[agents]
+    ti = (np.zeros(sw.n, dtype=np.int64) if sw.type_idx is None else sw.type_idx.astype(np.int64))
+    if agents is not None:
+        ti = ti[agents]
+    quad = kinds == 0
+    worst = {}
+    if quad.any():
+        qtypes = [k for k, t in enumerate(sw.types) if int(t.get("kind", 0)) == 0]
+        remap = np.full(len(sw.types), -1)
+        remap[qtypes] = np.arange(len(qtypes))
+        groups = OPEN_LOOP_GROUPS if sw.mode == 0 else None
+        errs = rel_errors(got[:30, quad], ref[:30, quad], [sw.types[k] for k in qtypes], remap[ti[quad]], groups)
+        worst.update({f"quad {g}": v for g, v in errs.items()})
+    for kind, name in ((1, "car"), (2, "wing")):
+        sel = kinds == kind
+        if sel.any():
+            errs = vehicle_rel_errors(got[:7, sel], ref[:7, sel])
+            worst.update({f"{name} {g}": v for g, v in errs.items()})
+    print("worst relative errors:", {k: f"{v[0]:.2e}" for k, v in worst.items()}, flush=True)
+    bad = {k: v for k, v in worst.items() if not v[0] <= tol}
+    assert not bad, bad
+
+
+def open_loop_kinds(n=6000, seed=11):
+    """Open-loop quadrotors (rotor commands within 10 % of hover), cars
+    (constant acceleration and steering commands) and aircraft (constant
+    airspeed, bank and flight-path commands), labels shuffled."""
+    r = np.random.default_rng(seed)
+    types = [I.base_type(), I.car_type(), I.wing_type()]
+    labels = r.integers(0, 3, n).astype(np.uint8)
+    s = np.zeros((30, n))
+    s[0:3] = np.stack([r.uniform(0, 100, n), r.uniform(0, 100, n), r.uniform(0, 20, n)])
+    s[6] = 1.0
+    cmd = np.zeros((4, n))
+    w_ref = float(types[0]["w_ref"])
+    cmd[:, labels == 0] = r.uniform(-0.1, 0.1, (4, int((labels == 0).sum()))) * w_ref
+    for kind in (1, 2):
+        idx = np.where(labels == kind)[0]
+        centre = np.stack([r.uniform(0, 100, idx.size), r.uniform(0, 100, idx.size),
+                           np.zeros(idx.size) if kind == 1 else r.uniform(40, 60, idx.size)])
+        s[:, idx] = 0.0
+        s[0:7, idx] = I.orbit_starts(r, types[kind], centre)
+        if kind == 1:
+            cmd[0, idx] = r.uniform(-1.0, 1.0, idx.size)
+            cmd[1, idx] = r.uniform(-0.4, 0.4, idx.size)
+        else:
+            cmd[0, idx] = r.uniform(15.0, 21.0, idx.size)
+            cmd[1, idx] = r.uniform(-0.5, 0.5, idx.size)
+            cmd[2, idx] = r.uniform(-0.1, 0.1, idx.size)
+    return I.Swarm("kinds_open", 0, 1e-3, 2000, I.f32(s), types, I.globals_f32(), type_idx=labels,
+                   motor_cmd=I.f32(cmd))
+
+
+def test_mixed_kinds_closed_loop_matches_oracle(oracle, torch_dev):
+    """Quadrotors, cars and aircraft shuffled in one launch, 1,000 steps, in
+    index order and in the type order; vehicles leave rows 7-29 (and a car
+    rows 2 and 6) exactly as they were."""
+    sw = I.config_kinds(n=6000, n_steps=1000)
+    ref = oracle_run(oracle, sw, 1000)
+    kinds = agent_kinds(sw)
+    outs = []
+    for ordered in (False, True):
+        got = gpu_run(torch_dev, sw, 1000, steps_per_launch=250, ordered=ordered)
+        assert_kinds_parity(got, ref, sw)
+        veh = kinds != 0
+        assert np.array_equal(got[7:, veh], sw.state[7:, veh].astype(np.float64))
+        car = kinds == 1
+        assert np.array_equal(got[[2, 6]][:, car], sw.state[[2, 6]][:, car].astype(np.float64))
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_mixed_kinds_open_loop_matches_oracle(oracle, torch_dev):
+    sw = open_loop_kinds()
+    ref = oracle_run(oracle, sw, sw.n_steps)
+    got = gpu_run(torch_dev, sw, sw.n_steps, steps_per_launch=500)
+    assert_kinds_parity(got, ref, sw)
+
+
+def test_vehicles_settle_on_their_orbits(torch_dev):
+    """Closed loop, 20,000 steps (20 s) from starts up to half a radius off
+    the orbit and 60 degrees off its direction: every car ends within 1 cm
+    of its orbit's radius around its waypoint, every aircraft within 0.5 m
+    of its orbit and 1 cm of its altitude (the circles of the paper's
+    demonstration; the FP64 reference ends within 0.06 mm and 0.18 m)."""
+    sw = I.config_kinds(n=4000, n_steps=20000)
+    got = gpu_run(torch_dev, sw, 20000, steps_per_launch=1000)
+    kinds = agent_kinds(sw)
+    for kind, tol in ((1, 0.01), (2, 0.5)):
+        sel = kinds == kind
+        t = sw.types[1] if kind == 1 else sw.types[3]
+        rho = I.veh_param(t, "rho")
+        c = sw.wp[-1][:, sel].astype(np.float64)
+        d = np.hypot(got[0, sel] - c[0], got[1, sel] - c[1])
+        assert np.abs(d - rho).max() < tol, (kind, np.abs(d - rho).max())
+        if kind == 2:
+            assert np.abs(got[2, sel] - c[2]).max() < 0.01
+
+
+def test_plain_equals_fused_bitwise(torch_dev):
+    sw = I.config_kinds(n=3000, n_steps=200)
+    a = gpu_run(torch_dev, sw, 200, form="plain")
+    b = gpu_run(torch_dev, sw, 200, steps_per_launch=37)
+    assert np.array_equal(a, b)
+    ol = open_loop_kinds(n=2000, seed=3)
+    a = gpu_run(torch_dev, ol, 150, form="plain", carry=False)
+    b = gpu_run(torch_dev, ol, 150, steps_per_launch=150, carry=False)
+    assert np.array_equal(a, b)
+
+
+def test_each_kind_equals_its_own_launch(torch_dev):
+    """A kind's agents advanced in a mixed launch equal the same agents
+    advanced alone (a type table and launch of their kind only), bitwise."""
+    sw = I.config_kinds(n=4000, n_steps=300)
+    mixed = gpu_run(torch_dev, sw, 300, steps_per_launch=100)
+    kinds = agent_kinds(sw)
+    for group in ((0,), (1,), (2,)):
+        idx = np.where(np.isin(kinds, group))[0]
+        sub = I.subset(sw, idx)
+        keep = sorted({int(t) for t in sub.type_idx})
+        remap = np.zeros(len(sw.types), dtype=np.uint8)
+        remap[keep] = np.arange(len(keep))
+        alone = I.Swarm(sub.name, sub.mode, sub.dt, sub.n_steps, sub.state, [sw.types[k] for k in keep], sub.glob,
+                        type_idx=remap[sub.type_idx], wp=sub.wp, resample_every=sub.resample_every)
+        got = gpu_run(torch_dev, alone, 300, steps_per_launch=100)
+        assert np.array_equal(got, mixed[:, idx]), group
+
+
+def test_kinds_full_size(oracle, torch_dev):
+    """1,048,576 agents (half quadrotors, a quarter cars, a quarter
+    aircraft) in the type order: every agent against the references after
+    1,000 steps, then 2,048 sampled agents after 10,000 steps (waypoints
+    redrawn every 2,000 steps for the quadrotors)."""
+    torch, dev = torch_dev
+    sw = I.config_kinds()
+    print("kinds full size: 1,048,576 agents, 1,000 steps then 10,000", flush=True)
+    got = gpu_run(torch_dev, sw, 1000, steps_per_launch=1000, ordered=True)
+    assert np.isfinite(got).all()
+    ref = oracle_run(oracle, sw, 1000)
+    assert_kinds_parity(got, ref, sw)
+    del ref
+    got = gpu_run(torch_dev, sw, 10000, steps_per_launch=1000, ordered=True)
+    sample = np.sort(np.random.default_rng(21).choice(sw.n, 2048, replace=False))
+    ref = oracle_run(oracle, sw, 10000, agents=sample)
+    assert_kinds_parity(got[:, sample], ref, sw, agents=sample)
+
+
+def test_vehicle_budgets_and_dead_agents(oracle, torch_dev):
+    """Per-type step budgets (cars 300, counter-clockwise aircraft 700) and
+    dead agents: each live agent takes min(steps, budget) steps, dead ones
+    none."""
+    sw = I.config_kinds(n=3000, n_steps=1000)
+    types = [dict(t) for t in sw.types]
+    types[1]["budget"] = 300
+    types[2]["budget"] = 300
+    types[3]["budget"] = 700
+    sw = I.Swarm(sw.name, sw.mode, sw.dt, sw.n_steps, sw.state, types, sw.glob, type_idx=sw.type_idx, wp=sw.wp,
+                 resample_every=sw.resample_every)
+    alive = (np.arange(sw.n) % 5 != 0).astype(np.uint8)
+    got = gpu_run(torch_dev, sw, 1000, steps_per_launch=400, alive=alive)
+    live = np.where(alive == 1)[0]
+    ref = oracle_run(oracle, sw, 1000, agents=live)
+    assert_kinds_parity(got[:, live], ref, sw, agents=live)
+    dead = alive == 0
+    assert np.array_equal(got[:, dead], sw.state[:, dead].astype(np.float64))
+
+
+def test_kinds_reject_checkpoints_and_the_adjoint(torch_dev):
+    torch, dev = torch_dev
+    from paper_2308_12698_amd import _lib as L
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config_kinds(n=256, n_steps=100)
+    sim = Simulator(sw.types, sw.glob, mode=1)
+    st = _dev(torch, dev, sw.state)
+    ti = _dev(torch, dev, sw.type_idx)
+    wp = _dev(torch, dev, sw.wp)
+    ck = torch.empty((2, 40, sw.n), device=dev)
+    with pytest.raises(L.PotatoError) as e:
+        sim.step(st, 100, sw.dt, type_idx=ti, wp=wp, ckpt=ck, ckpt_every=50,
+                 carry=torch.zeros((10, sw.n), device=dev))
+    assert e.value.status == L.EUNSUPPORTED
+    with pytest.raises(L.PotatoError) as e:
+        sim.step_backward(ck, 50, 100, sw.dt, torch.zeros((30, sw.n), device=dev), type_idx=ti, wp=wp)
+    assert e.value.status == L.EUNSUPPORTED
+    sim.close()
+
+
+def test_collision_radius_of_vehicle_types(oracle, torch_dev):
+    """Vehicle types carry their own collision radius through the type index."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config_kinds(n=20000, n_steps=10)
+    r = np.random.default_rng(4)
+    state = sw.state.copy()
+    state[0:3] = I.f32(np.stack([r.uniform(0, 40, sw.n), r.uniform(0, 40, sw.n), r.uniform(0, 4, sw.n)]))
+    sim = Simulator(sw.types, sw.glob, mode=1)
+    st = _dev(torch, dev, state)
+    alive = torch.ones(sw.n, dtype=torch.uint8, device=dev)
+    died = torch.zeros(1, dtype=torch.int64, device=dev)
+    sim.detect_collisions(st, alive, type_idx=_dev(torch, dev, sw.type_idx), died=died)
+    torch.cuda.synchronize()
+    got = alive.cpu().numpy()
+    sim.close()
+    ref, ref_died = oracle.detect_collisions(state, [t["radius"] for t in sw.types], np.ones(sw.n, np.uint8),
+                                             type_idx=sw.type_idx)
+    assert np.array_equal(got, ref) and int(died.item()) == ref_died > 0
