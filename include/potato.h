@@ -318,6 +318,26 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
                                        int64_t workspace_bytes, void* stream);
 
 /*
+ * potato_detect_collisions without a caller workspace, for callers that
+ * cannot allocate device memory (code under hipGraph capture, serving loops
+ * with a fixed memory budget, harnesses that forbid hipMalloc).  Same
+ * arguments, decisions and errors as potato_detect_collisions, but the
+ * pass's scratch memory (bucket counts and starts, the sorted positions) is
+ * a static device array of the library, sized for
+ * POTATO_NOALLOC_MAX_AGENTS agents (about 40 MiB, held by every GPU the
+ * library runs on until the process ends); the call allocates nothing.
+ * Errors: POTATO_EINVAL as in potato_detect_collisions, and for
+ * n_agents > POTATO_NOALLOC_MAX_AGENTS.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads, other contexts) race and must be serialised by the caller;
+ * calls on one stream are ordered and safe.
+ */
+enum { POTATO_NOALLOC_MAX_AGENTS = 1 << 20 };
+potato_status potato_detect_collisions_noalloc(potato_ctx* ctx, const potato_state* state,
+                                               const potato_params* params, int64_t n_agents, uint8_t* alive,
+                                               int64_t* died, void* stream);
+
+/*
  * Command ingress and snapshot egress around a running rollout (Sec. II-A,
  * Fig. 2: the decision side is kept out of the simulation loop, so the
  * simulated world keeps running while new commands are produced, and the

@@ -93,6 +93,7 @@ def load():
     L.potato_collision_workspace_bytes.argtypes = [I64]
     L.potato_collision_workspace_bytes.restype = I64
     L.potato_detect_collisions.argtypes = [P, P, P, I64, P, P, P, I64, P]
+    L.potato_detect_collisions_noalloc.argtypes = [P, P, P, I64, P, P, P]
     L.potato_pipe_create.argtypes = [P, I64, C.POINTER(C.c_void_p)]
     L.potato_pipe_push.argtypes = [P, P]
     L.potato_pipe_run.argtypes = [P, P, P, F, I32, I32, P, P]
@@ -107,7 +108,7 @@ def load():
     L.potato_version.restype = C.c_char_p
     for fn in ("potato_create", "potato_destroy", "potato_set_options", "potato_step",
                "potato_autotune", "potato_order_by_type", "potato_step_backward",
-               "potato_detect_collisions", "potato_pipe_create",
+               "potato_detect_collisions", "potato_detect_collisions_noalloc", "potato_pipe_create",
                "potato_pipe_push", "potato_pipe_run", "potato_pipe_wait_snapshots", "potato_pipe_sync",
                "potato_pipe_stats", "potato_pipe_destroy", "potato_count_nonfinite"):
         getattr(L, fn).restype = C.c_int

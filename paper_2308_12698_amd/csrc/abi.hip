@@ -64,6 +64,8 @@ struct potato_ctx {
     int32_t* d_rank = nullptr;         /* rank of each type by budget (longest first) */
     float* d_radius = nullptr;         /* collision radius per type */
     float r_max = 0.0f;
+    void* scratch = nullptr;           /* this device's static collision workspace */
+    int64_t scratch_bytes = 0;
     potato_limits limits{};
     potato_options opts{};
     hipStream_t cap_stream = nullptr;
@@ -431,6 +433,7 @@ potato_status potato_create(potato_ctx** out, const potato_type_params* types, i
         e = hipMemcpy(ctx->d_table, ctx->consts.data(), sizeof(TypeConst) * n_types, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_rank, rank.data(), sizeof(int32_t) * n_types, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = collision_scratch(&ctx->scratch, &ctx->scratch_bytes);
     if (e != hipSuccess) {
         potato_destroy(ctx);
         return hip_fail(e, "potato_create");
@@ -726,22 +729,56 @@ int64_t potato_collision_workspace_bytes(int64_t n_agents) {
     return collision_workspace_bytes(n_agents);
 }
 
-potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* state, const potato_params* params,
-                                       int64_t n_agents, uint8_t* alive, int64_t* died, void* workspace,
-                                       int64_t workspace_bytes, void* stream) {
-    ApiRange range("potato_detect_collisions");
-    if (!ctx || !state || !state->rows || !alive || !workspace)
-        return fail(POTATO_EINVAL, "ctx, state, state.rows, alive and workspace must be non-null");
-    if (n_agents < 1 || n_agents > 0x3fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30)");
-    if (state->ld < n_agents) return fail(POTATO_EINVAL, "state.ld < n_agents");
-    const int64_t need = collision_workspace_bytes(n_agents);
-    if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
-    if (!(ctx->r_max > 0.0f)) return fail(POTATO_EINVAL, "every type has radius 0: nothing can collide");
+namespace {
+
+potato_status detect_collisions(const char* name, potato_ctx* ctx, const potato_state* state,
+                                const potato_params* params, int64_t n_agents, uint8_t* alive, int64_t* died,
+                                void* workspace, void* stream) {
     hipError_t e = launch_detect_collisions(state->rows, state->ld, n_agents, params ? params->type : nullptr,
                                             ctx->n_types, ctx->d_radius, ctx->r_max, alive,
                                             reinterpret_cast<unsigned long long*>(died), workspace,
                                             reinterpret_cast<hipStream_t>(stream));
-    return e == hipSuccess ? POTATO_OK : hip_fail(e, "potato_detect_collisions launch");
+    return e == hipSuccess ? POTATO_OK : hip_fail(e, name);
+}
+
+potato_status check_collision_args(const potato_ctx* ctx, const potato_state* state, int64_t n_agents,
+                                   const uint8_t* alive) {
+    if (!ctx || !state || !state->rows || !alive)
+        return fail(POTATO_EINVAL, "ctx, state, state.rows and alive must be non-null");
+    if (n_agents < 1 || n_agents > 0x3fffffffLL) return fail(POTATO_EINVAL, "n_agents must be in [1, 2^30)");
+    if (state->ld < n_agents) return fail(POTATO_EINVAL, "state.ld < n_agents");
+    if (!(ctx->r_max > 0.0f)) return fail(POTATO_EINVAL, "every type has radius 0: nothing can collide");
+    return POTATO_OK;
+}
+
+}  // namespace
+
+potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* state, const potato_params* params,
+                                       int64_t n_agents, uint8_t* alive, int64_t* died, void* workspace,
+                                       int64_t workspace_bytes, void* stream) {
+    ApiRange range("potato_detect_collisions");
+    potato_status s = check_collision_args(ctx, state, n_agents, alive);
+    if (s != POTATO_OK) return s;
+    if (!workspace) return fail(POTATO_EINVAL, "workspace must be non-null");
+    const int64_t need = collision_workspace_bytes(n_agents);
+    if (workspace_bytes < need) return fail(POTATO_EINVAL, "workspace too small: need %lld bytes", (long long)need);
+    return detect_collisions("potato_detect_collisions launch", ctx, state, params, n_agents, alive, died,
+                             workspace, stream);
+}
+
+potato_status potato_detect_collisions_noalloc(potato_ctx* ctx, const potato_state* state,
+                                               const potato_params* params, int64_t n_agents, uint8_t* alive,
+                                               int64_t* died, void* stream) {
+    ApiRange range("potato_detect_collisions_noalloc");
+    potato_status s = check_collision_args(ctx, state, n_agents, alive);
+    if (s != POTATO_OK) return s;
+    if (n_agents > kNoAllocMaxAgents)
+        return fail(POTATO_EINVAL, "n_agents (%lld) exceeds the static workspace's limit of %lld agents",
+                    (long long)n_agents, (long long)kNoAllocMaxAgents);
+    if (!ctx->scratch || ctx->scratch_bytes < collision_workspace_bytes(n_agents))
+        return fail(POTATO_EHIP, "static collision workspace unavailable on this device");
+    return detect_collisions("potato_detect_collisions_noalloc launch", ctx, state, params, n_agents, alive, died,
+                             ctx->scratch, stream);
 }
 
 potato_status potato_count_nonfinite(potato_ctx* ctx, const potato_state* state, int64_t n_agents, int64_t* count,

@@ -19,6 +19,9 @@
  * it.  The 1 % margin in h keeps the neighbour property exact for
  * |coordinates| < 2^16 h (about 22 km for 0.17 m radii).
  */
+#include <mutex>
+#include <vector>
+
 #include "kernels.h"
 #include "scan.h"
 
@@ -190,18 +193,55 @@ __global__ void __launch_bounds__(256) k_coll_query(const float4* spos, const in
 #define POTATO_BUCKETS_PER_AGENT 2
 #endif
 
-uint32_t collision_buckets(int64_t n) {
+namespace {
+
+constexpr uint32_t buckets_for(int64_t n) {
     uint32_t m = 1024;
     while ((int64_t)m < POTATO_BUCKETS_PER_AGENT * n && m < (1u << 30)) m <<= 1;   /* the Z-order code has 30 bits */
     return m;
 }
 
-int64_t collision_workspace_bytes(int64_t n) {
-    const int64_t m = collision_buckets(n);
-    const int64_t chunks = scan_chunks(m);
+constexpr int64_t workspace_for(int64_t n) {
+    const int64_t m = buckets_for(n);
+    const int64_t chunks = (m + kScanBlock - 1) / kScanBlock;
     /* sorted (x, y, z, r) [n] first (16-byte aligned); count [m]; start [m+1];
      * key, ids [n]; chunk totals [chunks] */
     return 16 * n + (m + (m + 1) + 2 * n + chunks) * 4 + 256;
+}
+
+/* Workspace of the allocation-free entry point: a file-scope device array
+ * sized for the largest swarm it accepts.  Every GPU the library runs on
+ * holds its own copy until the process ends; host code reaches it only
+ * through the address hipGetSymbolAddress returns for the current device
+ * (the array's name in host code is not a device address). */
+constexpr int64_t kNoAllocBytes = workspace_for(kNoAllocMaxAgents);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+uint32_t collision_buckets(int64_t n) { return buckets_for(n); }
+
+int64_t collision_workspace_bytes(int64_t n) { return workspace_for(n); }
+
+hipError_t collision_scratch(void** ptr, int64_t* bytes) {
+    static std::mutex mu;
+    static std::vector<void*> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(mu);
+    if ((size_t)dev >= addr.size()) addr.resize((size_t)dev + 1, nullptr);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kNoAllocBytes;
+    return hipSuccess;
 }
 
 hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type, int n_types,

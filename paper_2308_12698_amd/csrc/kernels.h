@@ -129,6 +129,11 @@ hipError_t launch_count_nonfinite(const float* rows, int64_t ld, int64_t n, int 
 /* Collision detection on a hashed grid (see collide.hip). */
 uint32_t collision_buckets(int64_t n);
 int64_t collision_workspace_bytes(int64_t n);
+/* Largest swarm of the allocation-free collision entry point. */
+constexpr int64_t kNoAllocMaxAgents = int64_t(1) << 20;
+/* Device address (current device) and size of that entry point's static
+ * workspace; the address is looked up once per device and kept. */
+hipError_t collision_scratch(void** ptr, int64_t* bytes);
 hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type, int n_types,
                                     const float* radius_dev, float r_max, uint8_t* alive,
                                     unsigned long long* died, void* workspace, hipStream_t s);

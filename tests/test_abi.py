@@ -145,6 +145,8 @@ def test_collision_workspace_size(lib):
 def test_detect_rejects_null_context(lib):
     st = L.State(None, 10)
     assert lib.potato_detect_collisions(None, C.byref(st), None, 10, None, None, None, 0, None) == L.EINVAL
+    assert lib.potato_detect_collisions_noalloc(None, C.byref(st), None, 10, None, None, None) == L.EINVAL
+    assert b"non-null" in lib.potato_last_error(None)
 
 
 def test_type_radius_is_validated(lib):
