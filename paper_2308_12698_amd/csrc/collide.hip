@@ -1,5 +1,5 @@
 /*
- * collide.hip -- collision detection between agents on a hashed uniform
+ * collide.hip -- collision detection between agents on a wrapped uniform
  * grid (the detection module of Sec. II-A: colliding agents are marked dead
  * and excluded from the simulation).
  *
@@ -10,14 +10,22 @@
  * on entry (simultaneous events).
  *
  * Grid: cell edge h = 2.02 r_max (r_max the largest radius), so any colliding
- * pair sits in the same or an adjacent cell; cells map to M = 2^k >= 2N
- * buckets by the low bits of their Z-order (Morton) code.  Passes: clear, count agents per
- * bucket, exclusive scan, counting-sort scatter of (id, x, y, z, radius)
- * into bucket order, then one thread per sorted slot tests the slots of the
- * buckets of its 27 neighbour cells.  Slots within a bucket come out in
- * atomic order, but the result (an OR over neighbours) does not depend on
- * it.  The 1 % margin in h keeps the neighbour property exact for
- * |coordinates| < 2^16 h (about 22 km for 0.17 m radii).
+ * pair sits in the same or an adjacent cell.  Cells map to buckets by their
+ * indices wrapped to 2^bx x 2^by x 2^bz, where the bits split the budget
+ * 2^k >= 2N by the extent of the alive agents' bounding box (so a flat
+ * swarm does not leave the buckets of an unused depth empty); buckets are
+ * linear with x fastest, and each x row holds two extra ghost columns (a
+ * copy of the last column before the first and of the first after the
+ * last), so the three x neighbours of any cell are three consecutive
+ * buckets and a cell's 27 neighbours are 9 contiguous bucket ranges.
+ * Passes: clear; bounding box (block partials, then one block); count (an agent's rank in its bucket, and in
+ * its ghost bucket when it has one); exclusive scan; scatter of
+ * (x, y, z, radius) and the agent id into bucket order; query, one thread
+ * per sorted slot, over the candidates of its 9 ranges in batches of loads
+ * in flight.  Cells that share a bucket are far apart and fail the distance
+ * test; the decision is always the distance test.  The 1 % margin in h keeps
+ * the neighbour property exact for |coordinates| < 2^16 h (about 22 km for
+ * 0.17 m radii).
  */
 #include <mutex>
 #include <vector>
@@ -27,36 +35,16 @@
 
 namespace potato {
 
-/* Cells whose first two candidates are loaded together in the query (a
- * divisor of 27).  At 1M agents a pass took 0.36 ms with 3, 0.37 with 1
- * and with 9 (150 VGPRs), 0.48 with 27 (more registers than two waves per
- * SIMD allow). */
-#ifndef POTATO_QUERY_CELLS_PER_GROUP
-#define POTATO_QUERY_CELLS_PER_GROUP 3
+/* Candidates whose loads are issued together in the query. */
+#ifndef POTATO_QUERY_BATCH
+#define POTATO_QUERY_BATCH 8
 #endif
 
 namespace {
 
-
-/* Low 10 bits of v moved to every third bit position (bit interleaving for
- * a Morton / Z-order code). */
-__device__ __forceinline__ uint32_t spread3(int32_t v) {
-    uint32_t x = (uint32_t)v & 0x3ffu;
-    x = (x | (x << 16)) & 0x030000ffu;
-    x = (x | (x << 8)) & 0x0300f00fu;
-    x = (x | (x << 4)) & 0x030c30c3u;
-    x = (x | (x << 2)) & 0x09249249u;
-    return x;
-}
-
-/* Bucket of a cell: the low bits of its Z-order code, i.e. a grid that wraps
- * around every 2^(bits/3) cells per axis.  Cells that share a bucket are far
- * apart and fail the distance test; cells that are close get nearby bucket
- * numbers, so agents sorted by bucket are sorted along a space-filling
- * curve and neighbouring threads of the query read the same buckets. */
-__device__ __forceinline__ uint32_t cell_bucket(uint32_t sx, uint32_t sy, uint32_t sz, uint32_t mask) {
-    return (sx | (sy << 1) | (sz << 2)) & mask;
-}
+/* Fewest bits of the ghost-padded x axis: 2^5 columns + 2 ghosts keeps the
+ * padding within 1/16 of the bucket budget. */
+constexpr int kMinXBits = 5;
 
 /* Cell index along one axis.  The coordinate in cells is clamped to
  * [-2^24, 2^24] before the conversion, so infinite, NaN (max/min return the
@@ -69,144 +57,313 @@ __device__ __forceinline__ int32_t cell_index(float x, float inv_h) {
     return (int32_t)floorf(c);
 }
 
-__device__ __forceinline__ void cell_of(float x, float y, float z, float inv_h, int32_t& ix, int32_t& iy,
-                                        int32_t& iz) {
-    ix = cell_index(x, inv_h);
-    iy = cell_index(y, inv_h);
-    iz = cell_index(z, inv_h);
+/* Wrap of the grid: 2^bx x 2^by x 2^bz cells, x rows of 2^bx + 2 buckets. */
+struct Wrap {
+    int bx, by, bz;
+    uint32_t mx, my, mz;     /* 2^b - 1 */
+    uint32_t row;            /* 2^bx + 2 */
+};
+
+__device__ __forceinline__ int ceil_log2(int64_t e) {
+    int b = 0;
+    while (b < 40 && (int64_t(1) << b) < e) ++b;
+    return b;
+}
+
+/* Bits per axis for bucket budget 2^k from the bounding box (min x, y, z,
+ * max x, y, z, in cells): start from the bits that cover each extent, then
+ * take bits away, each time from the axis whose extent is the smallest
+ * multiple of its halved wrap (it gains the fewest wraps), x not below
+ * kMinXBits.  Wave-uniform: every kernel of a pass computes the same wrap. */
+__device__ __forceinline__ Wrap plan_wrap(const int32_t* box, int k) {
+    int64_t e[3];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t lo = box[a], hi = box[3 + a];
+        e[a] = hi >= lo ? hi - lo + 1 : 1;       /* no alive agent: any wrap */
+    }
+    int b[3] = {ceil_log2(e[0]), ceil_log2(e[1]), ceil_log2(e[2])};
+    if (b[0] < kMinXBits) b[0] = kMinXBits;
+    while (b[0] + b[1] + b[2] > k) {
+        int best = -1;
+        for (int a = 2; a >= 0; --a) {
+            if (b[a] == 0 || (a == 0 && b[a] == kMinXBits)) continue;
+            /* e[a] / 2^(b[a]-1) < e[best] / 2^(b[best]-1), cross-multiplied */
+            if (best < 0 || e[a] * (int64_t(1) << b[best]) < e[best] * (int64_t(1) << b[a])) best = a;
+        }
+        --b[best];
+    }
+    Wrap w;
+    w.bx = b[0]; w.by = b[1]; w.bz = b[2];
+    w.mx = (1u << b[0]) - 1u; w.my = (1u << b[1]) - 1u; w.mz = (1u << b[2]) - 1u;
+    w.row = (1u << b[0]) + 2u;
+    return w;
+}
+
+/* Bucket of wrapped cell (column col = wrapped x + 1, wrapped y, wrapped z). */
+__device__ __forceinline__ uint32_t bucket_of(const Wrap& w, uint32_t col, uint32_t wy, uint32_t wz) {
+    return col + w.row * (wy | (wz << w.by));
 }
 
 __global__ void __launch_bounds__(256) k_coll_clear(int32_t* count, uint32_t m) {
     for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < m; b += gridDim.x * blockDim.x) count[b] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_coll_count(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
-                                                    float inv_h, uint32_t mask, int32_t* count, uint32_t* key) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !alive[i]) return;
-    int32_t ix, iy, iz;
-    cell_of(rows[i], rows[ld + i], rows[2 * ld + i], inv_h, ix, iy, iz);
-    const uint32_t b = cell_bucket(spread3(ix), spread3(iy), spread3(iz), mask);
-    key[i] = b;
-    atomicAdd(&count[b], 1);
+/* Bounding box of the alive agents' cells, in two launches: each block of a
+ * grid of at most kBoxBlocks reduces its grid-stride share to six partial
+ * bounds, then one block reduces the partials (one atomic per block on six
+ * shared words serialised the first form of this pass: 96 us at 1M agents). */
+constexpr int kBoxBlocks = 1024;
+
+__device__ __forceinline__ int32_t bound_op(int a, int32_t x, int32_t y) { return a < 3 ? min(x, y) : max(x, y); }
+
+/* Block reduction of v[6] (min of 0-2, max of 3-5); the result is valid in
+ * thread 0..5 as red[a][0]. */
+__device__ __forceinline__ void block_bounds(int32_t v[6], int32_t (*red)[256 / 64]) {
+    for (int a = 0; a < 6; ++a) {
+        int32_t x = v[a];
+        for (int off = 32; off > 0; off >>= 1) x = bound_op(a, x, __shfl_xor(x, off));
+        v[a] = x;
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 6; ++a) red[a][threadIdx.x / 64] = v[a];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        int32_t x = red[a][0];
+        for (int w = 1; w < (int)(blockDim.x / 64); ++w) x = bound_op(a, x, red[a][w]);
+        red[a][0] = x;
+    }
 }
 
-/* Counting sort of the alive agents by bucket: agent i gets a slot in its
- * bucket's range (taking the bucket's count down to zero), and the slot
- * receives the agent id and (x, y, z, radius), so that the query reads each
- * bucket's candidates from consecutive addresses. */
+__global__ void __launch_bounds__(256) k_coll_bounds(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
+                                                     float inv_h, int32_t* partial) {
+    __shared__ int32_t red[6][256 / 64];
+    int32_t v[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!alive[i]) continue;
+        for (int a = 0; a < 3; ++a) {
+            const int32_t c = cell_index(rows[a * ld + i], inv_h);
+            v[a] = min(v[a], c);
+            v[3 + a] = max(v[3 + a], c);
+        }
+    }
+    block_bounds(v, red);
+    if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_coll_box(const int32_t* partial, int n_partial, int32_t* box) {
+    __shared__ int32_t red[6][256 / 64];
+    int32_t v[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int b = threadIdx.x; b < n_partial; b += blockDim.x)
+        for (int a = 0; a < 6; ++a) v[a] = bound_op(a, v[a], partial[b * 6 + a]);
+    block_bounds(v, red);
+    if (threadIdx.x < 6) box[threadIdx.x] = red[threadIdx.x][0];
+}
+
+/* Blocks are dispatched to the 8 XCDs in turn (block b to XCD b mod 8), and
+ * each XCD has its own L2.  Mapping block b to tile xcd * (blocks per XCD) +
+ * b / 8 gives each XCD one contiguous eighth of the tiles, so neighbouring
+ * tiles, which read the same data, share an L2. */
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n_blocks) {
+    const uint32_t q = n_blocks / kXcds, r = n_blocks % kXcds;
+    const uint32_t x = b % kXcds, pos = b / kXcds;
+    return x * q + (x < r ? x : r) + pos;
+}
+
+/* Wrapped cell of a position. */
+__device__ __forceinline__ void wrapped_cell(const Wrap& w, float x, float y, float z, float inv_h, uint32_t& wx,
+                                             uint32_t& wy, uint32_t& wz) {
+    wx = (uint32_t)cell_index(x, inv_h) & w.mx;
+    wy = (uint32_t)cell_index(y, inv_h) & w.my;
+    wz = (uint32_t)cell_index(z, inv_h) & w.mz;
+}
+
+/* An agent in the first wrapped column also sits in the ghost column after
+ * the last, one in the last column in the ghost column before the first:
+ * the bucket offset of its ghost, or 0. */
+__device__ __forceinline__ int32_t ghost_offset(const Wrap& w, uint32_t wx) {
+    return wx == 0 ? (int32_t)(w.mx + 1) : (wx == w.mx ? -(int32_t)(w.mx + 1) : 0);
+}
+
+/* Count the alive agents per bucket; each agent (and its ghost) keeps its
+ * rank in the bucket, which places it in the scatter without atomics. */
+__global__ void __launch_bounds__(256) k_coll_count(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
+                                                    float inv_h, const int32_t* box, int k, int32_t* count,
+                                                    int32_t* rank, int32_t* grank) {
+    const Wrap w = plan_wrap(box, k);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !alive[i]) return;
+    uint32_t wx, wy, wz;
+    wrapped_cell(w, rows[i], rows[ld + i], rows[2 * ld + i], inv_h, wx, wy, wz);
+    const uint32_t b = bucket_of(w, wx + 1, wy, wz);
+    rank[i] = atomicAdd(&count[b], 1);
+    const int32_t g = ghost_offset(w, wx);
+    if (g != 0) grank[i] = atomicAdd(&count[(int32_t)b + g], 1);
+}
+
+/* Counting-sort scatter: the agent (and its ghost, id tagged with the top
+ * bit) goes to slot start[bucket] + rank with its (x, y, z, radius), so the
+ * query reads each bucket's candidates from consecutive addresses. */
 __global__ void __launch_bounds__(256) k_coll_scatter(const float* rows, int64_t ld, int64_t n, const uint8_t* alive,
                                                       const uint8_t* type, int n_types, const float* radius,
-                                                      const uint32_t* key,
-                                                      const int32_t* start, int32_t* count, int32_t* ids,
+                                                      float inv_h, const int32_t* box, int k, const int32_t* start,
+                                                      const int32_t* rank, const int32_t* grank, int32_t* ids,
                                                       float4* spos) {
+    const Wrap w = plan_wrap(box, k);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !alive[i]) return;
-    const uint32_t b = key[i];
-    const int32_t slot = start[b] + atomicSub(&count[b], 1) - 1;
+    const float4 p = make_float4(rows[i], rows[ld + i], rows[2 * ld + i],
+                                 radius[type ? type_entry(type, (uint32_t)i, n_types) : 0]);
+    uint32_t wx, wy, wz;
+    wrapped_cell(w, p.x, p.y, p.z, inv_h, wx, wy, wz);
+    const uint32_t b = bucket_of(w, wx + 1, wy, wz);
+    const int32_t slot = start[b] + rank[i];
     ids[slot] = (int32_t)i;
-    spos[slot] = make_float4(rows[i], rows[ld + i], rows[2 * ld + i],
-                             radius[type ? type_entry(type, (uint32_t)i, n_types) : 0]);
+    spos[slot] = p;
+    const int32_t g = ghost_offset(w, wx);
+    if (g != 0) {
+        const int32_t gslot = start[(int32_t)b + g] + grank[i];
+        ids[gslot] = (int32_t)((uint32_t)i | 0x80000000u);
+        spos[gslot] = p;
+    }
 }
 
-/* One thread per sorted slot: consecutive lanes hold agents of the same or
- * nearby cells, so the bucket ranges and candidate positions they read are
- * shared through the caches. */
+/* One thread per sorted real slot (grid-stride; ghost slots are skipped):
+ * consecutive lanes hold agents of the same or nearby cells, so the bucket
+ * ranges and candidates they read are shared through the caches, and each
+ * XCD takes a contiguous range of slots (xcd_tile).  The 9
+ * candidate ranges are walked as one sequence, POTATO_QUERY_BATCH loads at
+ * a time (indices past a lane's end read its own slot and are masked), and
+ * a lane stops once it has found a collision. */
 __global__ void __launch_bounds__(256) k_coll_query(const float4* spos, const int32_t* ids, const int32_t* start,
-                                                    const int32_t* total, float inv_h, uint32_t mask,
-                                                    uint8_t* alive, unsigned long long* died) {
+                                                    const int32_t* total, float inv_h, const int32_t* box, int k_bits,
+                                                    uint8_t* alive, int32_t* died_part) {
 #pragma clang fp contract(off)
-    const int32_t k = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (k >= *total) return;
-    const float4 pk = spos[k];
-    int32_t cx, cy, cz;
-    cell_of(pk.x, pk.y, pk.z, inv_h, cx, cy, cz);
-    const uint32_t sx[3] = {spread3(cx - 1), spread3(cx), spread3(cx + 1)};
-    const uint32_t sy[3] = {spread3(cy - 1), spread3(cy), spread3(cy + 1)};
-    const uint32_t sz[3] = {spread3(cz - 1), spread3(cz), spread3(cz + 1)};
-    /* all 27 bucket ranges are requested before any is used, so their
-     * loads are in flight together instead of one round trip per cell */
-    int32_t lo[27], hi[27];
+    __shared__ int32_t wave_died[256 / 64];
+    int32_t my_died = 0;
+    const Wrap w = plan_wrap(box, k_bits);
+    const int64_t slots = *total;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    for (int64_t k0 = tile * blockDim.x; k0 < slots; k0 += stride) {
+        /* whole blocks stay in the loop together, so the ballot below sees
+         * every lane of the wave that holds a real slot; slot indices stay
+         * below 2^31 (at most two slots per agent, fewer than 2^30 agents) */
+        const int32_t k = (int32_t)(k0 + threadIdx.x);
+        const int32_t id = k < slots ? ids[k] : -1;
+        bool hit = false;
+        if (id >= 0) {
+            const float4 pk = spos[k];
+            uint32_t wx, wy, wz;
+            wrapped_cell(w, pk.x, pk.y, pk.z, inv_h, wx, wy, wz);
+            /* the 9 (y, z) rows: bucket range of columns wx .. wx + 2 (ghost-padded) */
+            int32_t lo[9], hi[9];
 #pragma unroll
-    for (int c = 0; c < 27; ++c) {
-        const uint32_t b = cell_bucket(sx[c % 3], sy[(c / 3) % 3], sz[c / 9], mask);
-        lo[c] = start[b];
-        hi[c] = start[b + 1];
-    }
-    /* The decision for one candidate j: the same FP32 operations, in the
-     * same order, as the reference's pair test. */
-    auto collides = [&](const float4& pj) {
-        const float ex = pk.x - pj.x, ey = pk.y - pj.y, ez = pk.z - pj.z;
-        const float d2 = (ex * ex + ey * ey) + ez * ez;
-        const float rs = pk.w + pj.w;
-        return d2 < rs * rs;
-    };
-    /* Candidates are read in groups of three cells, the first two slots of
-     * each cell unconditionally (at a clamped, always valid index, the
-     * result masked), so that six independent loads are in flight per
-     * round trip instead of one load per dependent loop iteration; a cell
-     * holds ~0.5 candidates on average, and the rare further ones are read
-     * by a loop. */
-    const int32_t last = *total - 1;
-    bool hit = false;
-    constexpr int G = POTATO_QUERY_CELLS_PER_GROUP;
+            for (int r = 0; r < 9; ++r) {
+                const uint32_t ry = (wy + (uint32_t)(r % 3) - 1u) & w.my;
+                const uint32_t rz = (wz + (uint32_t)(r / 3) - 1u) & w.mz;
+                const uint32_t b0 = bucket_of(w, wx, ry, rz);
+                lo[r] = start[b0];
+                hi[r] = start[b0 + 3];
+            }
+            /* candidate t of the sequence is slot t + d[r] for the last range r
+             * whose first candidate number cum[r] is <= t */
+            int32_t cum[9], d[9];
+            int32_t T = 0;
 #pragma unroll
-    for (int g = 0; g < 27 / G; ++g) {
-        float4 pc[2 * G];
-        bool use[2 * G];
+            for (int r = 0; r < 9; ++r) {
+                cum[r] = T;
+                d[r] = lo[r] - T;
+                T += hi[r] - lo[r];
+            }
+            auto collides = [&](const float4& pj) {
+                const float ex = pk.x - pj.x, ey = pk.y - pj.y, ez = pk.z - pj.z;
+                const float d2 = (ex * ex + ey * ey) + ez * ez;
+                const float rs = pk.w + pj.w;
+                return d2 < rs * rs;
+            };
+            constexpr int B = POTATO_QUERY_BATCH;
+            for (int32_t t0 = 0; t0 < T && !hit; t0 += B) {
+                float4 pc[B];
+                bool use[B];
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-            const int c = G * g + u;
-            const int32_t j0 = lo[c], j1 = lo[c] + 1;
-            pc[2 * u] = spos[j0 < last ? j0 : last];
-            pc[2 * u + 1] = spos[j1 < last ? j1 : last];
-            use[2 * u] = j0 < hi[c] && j0 != k;
-            use[2 * u + 1] = j1 < hi[c] && j1 != k;
+                for (int u = 0; u < B; ++u) {
+                    const int32_t t = t0 + u;
+                    int32_t j = t + d[0];
+#pragma unroll
+                    for (int r = 1; r < 9; ++r) j = t >= cum[r] ? t + d[r] : j;
+                    use[u] = t < T && j != k;
+                    pc[u] = spos[t < T ? j : k];
+                }
+#pragma unroll
+                for (int u = 0; u < B; ++u) hit |= use[u] && collides(pc[u]);
+            }
+            /* the query reads positions from the sorted copy only, so the
+             * mask is updated in place */
+            if (hit) alive[id] = 0;
         }
-#pragma unroll
-        for (int t = 0; t < 2 * G; ++t) hit |= use[t] && collides(pc[t]);
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-            const int c = G * g + u;
-            for (int32_t j = lo[c] + 2; j < hi[c]; ++j)
-                if (j != k) hit |= collides(spos[j]);
+        my_died += hit ? 1 : 0;
+    }
+    /* agents marked dead by this block: a partial sum per block, added up by
+     * k_coll_died (atomics on one counter serialise across the chip: one per
+     * wave took most of the query's 0.21 ms at 1M agents) */
+    if (died_part) {
+        int32_t x = my_died;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if ((threadIdx.x & 63) == 0) wave_died[threadIdx.x / 64] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t sum = 0;
+            for (int w = 0; w < (int)(blockDim.x / 64); ++w) sum += wave_died[w];
+            died_part[blockIdx.x] = sum;
         }
     }
-    /* the query reads positions from the sorted copy only, so the mask is
-     * updated in place */
-    if (hit) alive[ids[k]] = 0;
-    if (died) {
-        /* one atomic per wave: most agents of a dense swarm collide, and one
-         * atomic each on a single counter serialises the whole pass */
-        const unsigned long long m = __ballot(hit);
-        if (m && (threadIdx.x & (warpSize - 1)) == (unsigned)(__ffsll((long long)m) - 1))
-            atomicAdd(died, (unsigned long long)__popcll(m));
+}
+
+/* *died += the sum of the per-block counts of the query. */
+__global__ void __launch_bounds__(256) k_coll_died(const int32_t* died_part, int n_part, unsigned long long* died) {
+    __shared__ unsigned long long red[256 / 64];
+    unsigned long long x = 0;
+    for (int b = threadIdx.x; b < n_part; b += blockDim.x) x += (unsigned long long)died_part[b];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) sum += red[w];
+        *died += sum;
     }
 }
 
 }  // namespace
 
-/* Buckets per agent (rounded up to a power of two).  More buckets mean
- * fewer far cells sharing a bucket, but longer clear and scan passes: at
- * 1M agents 2 measured 0.36 ms per pass, 4, 8 and 16 0.37, 0.40, 0.47. */
-#ifndef POTATO_BUCKETS_PER_AGENT
-#define POTATO_BUCKETS_PER_AGENT 2
-#endif
-
 namespace {
 
-constexpr uint32_t buckets_for(int64_t n) {
-    uint32_t m = 1024;
-    while ((int64_t)m < POTATO_BUCKETS_PER_AGENT * n && m < (1u << 30)) m <<= 1;   /* the Z-order code has 30 bits */
-    return m;
+/* Bucket budget 2^k >= 2N, at least 2^10 (the wrap splits its k bits). */
+constexpr int budget_bits(int64_t n) {
+    int k = 10;
+    while ((int64_t(1) << k) < 2 * n && k < 30) ++k;
+    return k;
+}
+
+/* Buckets allocated: the budget plus the ghost columns (at most 2 per
+ * 2^kMinXBits columns). */
+constexpr int64_t buckets_alloc(int64_t n) {
+    const int k = budget_bits(n);
+    return (int64_t(1) << k) + (int64_t(1) << (k + 1 - kMinXBits));
 }
 
 constexpr int64_t workspace_for(int64_t n) {
-    const int64_t m = buckets_for(n);
+    const int64_t m = buckets_alloc(n);
     const int64_t chunks = (m + kScanBlock - 1) / kScanBlock;
-    /* sorted (x, y, z, r) [n] first (16-byte aligned); count [m]; start [m+1];
-     * key, ids [n]; chunk totals [chunks] */
-    return 16 * n + (m + (m + 1) + 2 * n + chunks) * 4 + 256;
+    /* sorted (x, y, z, r) [2n] first (16-byte aligned: agents and ghosts);
+     * ids [2n]; rank, ghost rank [n]; count [m]; start [m+1]; chunk totals
+     * [chunks]; bounding box [6]; its per-block partials [kBoxBlocks][6];
+     * the query's per-block counts of dead agents [blocks] */
+    const int64_t blocks = (n + 255) / 256;
+    return 16 * 2 * n + 4 * (2 * n + 2 * n + m + (m + 1) + chunks + 6 + 6 * kBoxBlocks + blocks) + 256;
 }
 
 /* Workspace of the allocation-free entry point: a file-scope device array
@@ -220,7 +377,7 @@ constexpr int64_t kNoAllocBytes = workspace_for(kNoAllocMaxAgents);
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
-uint32_t collision_buckets(int64_t n) { return buckets_for(n); }
+uint32_t collision_buckets(int64_t n) { return (uint32_t)buckets_alloc(n); }
 
 int64_t collision_workspace_bytes(int64_t n) { return workspace_for(n); }
 
@@ -247,23 +404,32 @@ hipError_t collision_scratch(void** ptr, int64_t* bytes) {
 hipError_t launch_detect_collisions(const float* rows, int64_t ld, int64_t n, const uint8_t* type, int n_types,
                                     const float* radius_dev, float r_max, uint8_t* alive,
                                     unsigned long long* died, void* workspace, hipStream_t s) {
-    const uint32_t m = collision_buckets(n);
+    const int k = budget_bits(n);
+    const uint32_t m = (uint32_t)buckets_alloc(n);
     float4* spos = reinterpret_cast<float4*>(workspace);
-    int32_t* count = reinterpret_cast<int32_t*>(spos + n);
+    int32_t* ids = reinterpret_cast<int32_t*>(spos + 2 * n);
+    int32_t* rank = ids + 2 * n;
+    int32_t* grank = rank + n;
+    int32_t* count = grank + n;
     int32_t* start = count + m;
-    uint32_t* key = reinterpret_cast<uint32_t*>(start + m + 1);
-    int32_t* ids = reinterpret_cast<int32_t*>(key + n);
-    int32_t* totals = ids + n;
+    int32_t* totals = start + m + 1;
+    int32_t* box = totals + scan_chunks(m);
+    int32_t* partial = box + 6;
+    int32_t* died_part = partial + 6 * kBoxBlocks;
     const float inv_h = 1.0f / (2.02f * r_max);
-    const uint32_t mask = m - 1;
     const unsigned nb = (unsigned)((n + 255) / 256);
+    const unsigned nbox = nb < (unsigned)kBoxBlocks ? nb : (unsigned)kBoxBlocks;
     hipLaunchKernelGGL(k_coll_clear, dim3((m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096), dim3(256), 0, s, count, m);
-    hipLaunchKernelGGL(k_coll_count, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, inv_h, mask, count, key);
-    launch_exclusive_scan(count, start, totals, start + m, m, s);   /* grand total in start[m] */
-    hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, type, n_types, radius_dev, key,
-                       start, count, ids, spos);
-    hipLaunchKernelGGL(k_coll_query, dim3(nb), dim3(256), 0, s, spos, ids, start, start + m, inv_h, mask, alive,
-                       died);
+    hipLaunchKernelGGL(k_coll_bounds, dim3(nbox), dim3(256), 0, s, rows, ld, n, alive, inv_h, partial);
+    hipLaunchKernelGGL(k_coll_box, dim3(1), dim3(256), 0, s, partial, (int)nbox, box);
+    hipLaunchKernelGGL(k_coll_count, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, inv_h, box, k, count, rank,
+                       grank);
+    launch_exclusive_scan(count, start, totals, start + m, m, s);   /* grand total (slots) in start[m] */
+    hipLaunchKernelGGL(k_coll_scatter, dim3(nb), dim3(256), 0, s, rows, ld, n, alive, type, n_types, radius_dev, inv_h,
+                       box, k, start, rank, grank, ids, spos);
+    hipLaunchKernelGGL(k_coll_query, dim3(nb), dim3(256), 0, s, spos, ids, start, start + m, inv_h, box, k, alive,
+                       died ? died_part : nullptr);
+    if (died) hipLaunchKernelGGL(k_coll_died, dim3(1), dim3(256), 0, s, died_part, (int)nb, died);
     return hipGetLastError();
 }
 

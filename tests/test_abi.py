@@ -135,11 +135,15 @@ def test_collision_workspace_size(lib):
     lib.potato_collision_workspace_bytes.restype = C.c_int64
     lib.potato_collision_workspace_bytes.argtypes = [C.c_int64]
     assert lib.potato_collision_workspace_bytes(0) == -1
-    n = 1000
-    m = 2048                                   # smallest power of two >= 2n (and >= 1024)
-    # sorted (x, y, z, r) [n]; count [m]; start [m + 1]; key, ids [n]; chunk totals
-    expect = 16 * n + (m + (m + 1) + 2 * n + m // 1024) * 4 + 256
-    assert lib.potato_collision_workspace_bytes(n) == expect
+    for n, k in ((1000, 11), (1 << 20, 21), (3, 10)):
+        # bucket budget 2^k >= 2n (at least 2^10) plus 2 ghost columns per 32
+        m = 2 ** k + 2 ** (k + 1 - 5)
+        # sorted (x, y, z, r) and ids of agents and ghosts [2n]; ranks [n] x 2;
+        # count [m]; start [m + 1]; chunk totals; bounding box [6] and its
+        # partials over at most 1,024 blocks; per-block counts of the dead
+        expect = 16 * 2 * n + 4 * (2 * n + 2 * n + m + (m + 1) + math.ceil(m / 1024) + 6 + 6 * 1024
+                                   + math.ceil(n / 256)) + 256
+        assert lib.potato_collision_workspace_bytes(n) == expect
 
 
 def test_detect_rejects_null_context(lib):
