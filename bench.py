@@ -55,7 +55,7 @@ REV_FLOPS_PER_AGENT_STEP = 539 + 4 * 282 + 468 + 45        # 2180
 BWD_FLOPS_PER_AGENT_STEP = FLOPS_PER_AGENT_STEP + REV_FLOPS_PER_AGENT_STEP   # 3059
 # Rows per agent-step of the adjoint's recomputation tape (written once and
 # read once per agent-step).
-TAPE_ROWS = 30
+TAPE_ROWS = 31            # step-start state without J and w_prev (26), held command (4), branch bits (1)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_12698_amd", "csrc", f)
                   for f in ("quad_step.h", "kernels.hip", "kernels.h")]

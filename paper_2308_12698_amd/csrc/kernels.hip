@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(kAdjPipeBlock)
             } else {
                 const int seg = n_seg_all - t;
                 if (t > 0 && seg < n_seg)
-                    reverse_segment(c, lim, g, A.K, seg, steps, A.step0, A.resample, wc,
+                    reverse_segment(c, lim, g, A.ckpt, ld, bo, A.K, seg, steps, A.step0, A.resample, wc,
                                     tape + (seg & 1) * buf_stride, tape_step, lb, lam, gk);
             }
             __syncthreads();

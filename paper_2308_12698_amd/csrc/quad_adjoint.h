@@ -11,8 +11,12 @@
  * Non-smooth points take the derivative of the branch the forward pass
  * took: a clamp passes the cotangent inside its interval and stops it
  * outside; the error-quaternion sign is a constant; sqrt'(0) is taken as 0.
- * The rounding carries of the forward integrator are not differentiated
- * (the represented value is row + carry, so both have the same cotangent).
+ * The branches are the forward's own decisions, recorded on the tape by the
+ * recomputation (which replays the forward bit for bit), as is the rotor
+ * command it held through the step; the reverse sweep does not decide any
+ * branch itself.  The rounding carries of the forward integrator are not
+ * differentiated (the represented value is row + carry, so both have the
+ * same cotangent).
  */
 #pragma once
 
@@ -111,23 +115,15 @@ __device__ __forceinline__ void dyn_axpy(const Dyn& x, float h, const Dyn& k, Dy
 
 /*
  * Reverse of one step.  `a` is the step-start state (as the forward pass
- * saw it), wp the waypoint of this step, k the gains.  lam holds the
- * cotangent of the step-end state on entry and of the step-start state on
- * return; gk accumulates the gain cotangents.
+ * saw it; its J and carries are not read), wp the waypoint of this step, k
+ * the gains, dc the rotor command the forward controller held through the
+ * step and bits its branch decisions (kBit*).  lam holds the cotangent of
+ * the step-end state on entry and of the step-start state on return; gk
+ * accumulates the gain cotangents.
  */
 __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, const Gains& k,
-                                         const Agent& a, const float wp[3], AgentAdj& lam,
-                                         float gk[9]) {
-    /* ---------------- held command: the forward controller on a copy ----------------
-     * (its intermediates are recomputed below, after the RK4 reverse, so they
-     * are not live while the stage states are; storing the command on the
-     * tape instead measured no faster) */
-    float dc[4];
-    {
-        Agent tmp = a;
-        controller(c, L, k, tmp, wp, dc);
-    }
-
+                                         const Agent& a, const float wp[3], const float dc[4],
+                                         uint32_t bits, AgentAdj& lam, float gk[9]) {
     /* ---------------- RK4 forward, keeping the stage states ---------------- */
     Dyn y1, y2, y3, y4, kk;
 #pragma unroll
@@ -215,10 +211,11 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
         }
     }
 
-    /* ---------------- controller, forward with intermediates ---------------- */
+    /* ---------------- controller, forward with intermediates ----------------
+     * (the values the reverse needs; the branches are the recorded ones) */
     float er[3] = {wp[0] - a.p[0], wp[1] - a.p[1], wp[2] - a.p[2]};
     const float n2 = er[0] * er[0] + er[1] * er[1] + er[2] * er[2];
-    const bool sat = n2 > L.r_sat2;
+    const bool sat = (bits & kBitSat) != 0;
     float rs = 0.0f, sc = 1.0f;
     if (sat) { rs = rsq(n2); sc = L.r_sat * rs; }
     const float e[3] = {er[0] * sc, er[1] * sc, er[2] * sc};
@@ -227,18 +224,17 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float pre = a.ip[i] + e[i] * L.dt;
-        in_ip[i] = !(pre < -L.ipos_max) && !(pre > L.ipos_max);
+        in_ip[i] = (bits & (kBitIp << i)) != 0;
         ipn[i] = clampf_(pre, -L.ipos_max, L.ipos_max);
     }
     float acc[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc[i] = k.kpp * e[i] + k.kip * ipn[i] - k.kdp * a.v[i];
     acc[2] += L.g;
-    const bool az_cl = acc[2] < L.az_min;
+    const bool az_cl = (bits & kBitAz) != 0;
     if (az_cl) acc[2] = L.az_min;
     float bz[3];
     body_z(a.q, bz);
-    const float fc = c.mass * (acc[0] * bz[0] + acc[1] * bz[1] + acc[2] * bz[2]);
     const float ra = rsq(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
     const float nv[3] = {acc[0] * ra, acc[1] * ra, acc[2] * ra};
     const float qr0 = 1.0f + nv[2], qr1 = -nv[1], qr2 = nv[0];
@@ -249,37 +245,28 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
     const float qex = q[0] * qd[1] - q[1] * qd[0] + q[3] * qd[2];
     const float qey = q[0] * qd[2] - q[2] * qd[0] - q[3] * qd[1];
     const float qez = q[2] * qd[1] - q[1] * qd[2] - q[3] * qd[0];
-    const float sg = qew < 0.0f ? -2.0f : 2.0f;
+    const float sg = (bits & kBitSgn) != 0 ? -2.0f : 2.0f;
     const float eatt[3] = {sg * qex, sg * qey, sg * qez};
-    float ian[3], irn[3], wdes[3], erate[3], alpha[3];
+    float ian[3], irn[3], wdes[3], erate[3];
     bool in_ia[3], in_ir[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float pa = a.ia[i] + eatt[i] * L.dt;
-        in_ia[i] = !(pa < -L.iatt_max) && !(pa > L.iatt_max);
+        in_ia[i] = (bits & (kBitIa << i)) != 0;
         ian[i] = clampf_(pa, -L.iatt_max, L.iatt_max);
         wdes[i] = k.kpa * eatt[i] + k.kia * ian[i] - k.kda * a.w[i];
         erate[i] = wdes[i] - a.w[i];
         const float pr = a.ir[i] + erate[i] * L.dt;
-        in_ir[i] = !(pr < -L.irate_max) && !(pr > L.irate_max);
+        in_ir[i] = (bits & (kBitIr << i)) != 0;
         irn[i] = clampf_(pr, -L.irate_max, L.irate_max);
-        alpha[i] = k.kpr * erate[i] + k.kir * irn[i] - k.kdr * ((a.w[i] - a.wprev[i]) * L.inv_dt);
     }
-    const float Iwx = c.Ix * a.w[0], Iwy = c.Iy * a.w[1], Iwz = c.Iz * a.w[2];
-    const float tx = c.Ix * alpha[0] + (a.w[1] * Iwz - a.w[2] * Iwy);
-    const float ty = c.Iy * alpha[1] + (a.w[2] * Iwx - a.w[0] * Iwz);
-    const float tz = c.Iz * alpha[2] + (a.w[0] * Iwy - a.w[1] * Iwx);
-    const float f4 = 0.25f * fc;
-    const float X = tx * c.mix_x, Y = ty * c.mix_y, Z = tz * c.mix_z;
-    const float f[4] = {f4 + X - Y + Z, f4 - X - Y - Z, f4 - X + Y + Z, f4 + X + Y - Z};
+    /* rotor speed W = sqrt(f / k_f) of the held command: dW/df = 1 / (2 k_f W),
+     * zero where the thrust was clamped or W == 0 */
     float lf_scale[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const bool in_f = !(f[i] < 0.0f) && !(f[i] > c.f_max);
-        const float w2 = clampf_(f[i], 0.0f, c.f_max) * c.inv_kf;
-        /* W = sqrt(w2): d W / d f = inv_kf / (2 W) = inv_kf rsq(w2) / 2, zero
-         * when clamped or W == 0 */
-        lf_scale[i] = (in_f && w2 > 0.0f) ? 0.5f * c.inv_kf * rsq(w2) : 0.0f;
+        const float W = dc[i] + c.w_ref;
+        lf_scale[i] = (bits & (kBitRotor << i)) != 0 ? 0.5f * c.inv_kf * __builtin_amdgcn_rcpf(W) : 0.0f;
     }
 
     /* ---------------- reverse: controller ---------------- */
@@ -409,20 +396,6 @@ __device__ __forceinline__ void load_rows(const float* base, int64_t ld, uint32_
     a.J_lo = carries ? row(36) : 0.0f;
 }
 
-/* The 30 physical rows (the tape does not need the carries). */
-__device__ __forceinline__ void store_phys_rows(float* base, int64_t ld, uint32_t bo, const Agent& a) {
-    auto row = [&](int k) -> float& { return elem(row_ptr(base, ld, k), bo); };
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k];
-        row(17 + k) = a.ip[k]; row(20 + k) = a.ia[k];
-        row(23 + k) = a.ir[k]; row(26 + k) = a.wprev[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { row(6 + k) = a.q[k]; row(13 + k) = a.d[k]; }
-    row(29) = a.J;
-}
-
 __device__ __forceinline__ void load_adj(const float* base, int64_t ld, uint32_t bo, AgentAdj& l) {
     auto row = [&](int k) { return elem(row_ptr(base, ld, k), bo); };
 #pragma unroll
@@ -451,7 +424,7 @@ __device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, 
 
 /* Tape slots: one block of kTapeRows x 64 floats per wave and step, a row
  * being 64 consecutive floats (one per lane).  `slot` is the block's base,
- * the same for the whole wave; rows 0-15 and 16-29 are addressed from two
+ * the same for the whole wave; rows 0-15 and 16-30 are addressed from two
  * scalar bases at immediate offsets (k x 256 bytes, within the 4 KiB range
  * of the instruction's offset field), and `lb` is the lane's byte offset. */
 template <typename T>
@@ -462,34 +435,78 @@ struct TapeRows {
     __device__ __forceinline__ T* row(int k) const { return k < 16 ? lo + k * 64 : hi + (k - 16) * 64; }
 };
 
+/* Step-start state of a tape slot: rows 0-25 (p, v, q, w, rotors, the three
+ * integrals). */
 __device__ __forceinline__ void store_tape(float* slot, uint32_t lb, const Agent& a) {
     const TapeRows<float> t(slot);
     auto row = [&](int k) -> float& { return elem(t.row(k), lb); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         row(k) = a.p[k]; row(3 + k) = a.v[k]; row(10 + k) = a.w[k];
-        row(17 + k) = a.ip[k]; row(20 + k) = a.ia[k];
-        row(23 + k) = a.ir[k]; row(26 + k) = a.wprev[k];
+        row(17 + k) = a.ip[k]; row(20 + k) = a.ia[k]; row(23 + k) = a.ir[k];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) { row(6 + k) = a.q[k]; row(13 + k) = a.d[k]; }
-    row(29) = a.J;
 }
 
-__device__ __forceinline__ void load_tape(const float* slot, uint32_t lb, Agent& a) {
+/* The controller's held command and branch decisions of a tape slot. */
+__device__ __forceinline__ void store_tape_cmd(float* slot, uint32_t lb, const float dc[4], uint32_t bits) {
+    const TapeRows<float> t(slot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) elem(t.row(kTapeCmd + k), lb) = dc[k];
+    elem(t.row(kTapeBits), lb) = __uint_as_float(bits);
+}
+
+/* A tape slot: the step-start state (w_prev given by the caller; J and the
+ * carries are not needed), the held command and the branch decisions. */
+__device__ __forceinline__ void load_tape(const float* slot, uint32_t lb, const float wprev[3], Agent& a,
+                                          float dc[4], uint32_t& bits) {
     const TapeRows<const float> t(slot);
     auto row = [&](int k) { return elem(t.row(k), lb); };
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         a.p[k] = row(k); a.v[k] = row(3 + k); a.w[k] = row(10 + k);
-        a.ip[k] = row(17 + k); a.ia[k] = row(20 + k);
-        a.ir[k] = row(23 + k); a.wprev[k] = row(26 + k);
+        a.ip[k] = row(17 + k); a.ia[k] = row(20 + k); a.ir[k] = row(23 + k);
+        a.wprev[k] = wprev[k];
         a.p_lo[k] = a.v_lo[k] = a.ip_lo[k] = 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { a.q[k] = row(6 + k); a.d[k] = row(13 + k); }
-    a.J = row(29);
-    a.J_lo = 0.0f;
+    for (int k = 0; k < 4; ++k) { a.q[k] = row(6 + k); a.d[k] = row(13 + k); dc[k] = row(kTapeCmd + k); }
+    bits = __float_as_uint(row(kTapeBits));
+    a.J = a.J_lo = 0.0f;
+}
+
+/* Body rates at the start of a step (the w_prev of the next): rows 10-12
+ * of a tape slot. */
+__device__ __forceinline__ void load_tape_w(const float* slot, uint32_t lb, float w[3]) {
+    const TapeRows<const float> t(slot);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = elem(t.row(10 + k), lb);
+}
+
+/* w_prev of step s of a segment: the body rates of step s - 1 on the tape,
+ * or, for the segment's first step, the checkpoint's rows 26-28. */
+__device__ __forceinline__ void step_wprev(const float* tape, int64_t tape_step, uint32_t lb, int s,
+                                           const float* ckpt_seg, int64_t ld, uint32_t bo, float wprev[3]) {
+    if (s > 0) {
+        load_tape_w(tape + (int64_t)(s - 1) * tape_step, lb, wprev);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wprev[k] = elem(row_ptr(ckpt_seg, ld, 26 + k), bo);
+    }
+}
+
+/* One recomputed forward step: its start state, held command and branch
+ * decisions go to the tape slot, then the state advances (the forward
+ * pass's own arithmetic, carries included, so the same bits). */
+__device__ __forceinline__ void recompute_step(const TypeConst& c, const Limits& L, const Gains& g, Agent& a,
+                                               const float wp[3], float* slot, uint32_t lb) {
+    store_tape(slot, lb, a);
+    float dc[4];
+    uint32_t bits;
+    controller<true, true>(c, L, g, a, wp, dc, &bits);
+    store_tape_cmd(slot, lb, dc, bits);
+    rk4_step(c, L, a, dc);
 }
 
 /*
@@ -544,23 +561,24 @@ __device__ __forceinline__ void agent_backward(const TypeConst& c, const Limits&
         int64_t e = resample > 0 ? k0 / resample : 0;
         int64_t next = resample > 0 ? (e + 1) * period : INT64_MAX;   /* first step of epoch e + 1 */
         for (int s = 0; s < len; ++s) {
-            store_tape(tape + (int64_t)s * tape_step, lb, a);
             if (k0 + s == next) { ++e; next += period; }
             use_epoch(e);
-            float dc[4];
-            controller(c, L, g, a, wpv, dc);
-            rk4_step(c, L, a, dc);
+            recompute_step(c, L, g, a, wpv, tape + (int64_t)s * tape_step, lb);
         }
         /* reverse: start from the epoch of the segment's last step */
         e = resample > 0 ? (k0 + len - 1) / resample : 0;
         int64_t first = resample > 0 ? e * period : INT64_MIN;         /* first step of epoch e */
+        const float* ck = ckpt + (int64_t)seg * kCkptRows * ld;
         for (int s = K - 1; s >= 0; --s) {
             if (s >= len) continue;
             if (k0 + s < first) { --e; first -= period; }
             Agent x;
-            load_tape(tape + (int64_t)s * tape_step, lb, x);
+            float dc[4], wprev[3];
+            uint32_t bits;
+            step_wprev(tape, tape_step, lb, s, ck, ld, bo, wprev);
+            load_tape(tape + (int64_t)s * tape_step, lb, wprev, x, dc, bits);
             use_epoch(e);
-            step_vjp(c, L, g, x, wpv, lam, gk);
+            step_vjp(c, L, g, x, wpv, dc, bits, lam, gk);
         }
     }
 }
@@ -601,16 +619,14 @@ __device__ __forceinline__ void recompute_segment(const TypeConst& c, const Limi
     int64_t e = resample > 0 ? k0 / resample : 0;
     int64_t next = resample > 0 ? (e + 1) * period : INT64_MAX;
     for (int s = 0; s < len; ++s) {
-        store_tape(tape + (int64_t)s * tape_step, lb, a);
         if (k0 + s == next) { ++e; next += period; }
         wc.use(e);
-        float dc[4];
-        controller(c, L, g, a, wc.v, dc);
-        rk4_step(c, L, a, dc);
+        recompute_step(c, L, g, a, wc.v, tape + (int64_t)s * tape_step, lb);
     }
 }
 
-__device__ __forceinline__ void reverse_segment(const TypeConst& c, const Limits& L, const Gains& g, int K,
+__device__ __forceinline__ void reverse_segment(const TypeConst& c, const Limits& L, const Gains& g,
+                                                const float* ckpt, int64_t ld, uint32_t bo, int K,
                                                 int seg, int steps, int64_t step0, int resample,
                                                 WaypointCache& wc, const float* tape, int64_t tape_step,
                                                 uint32_t lb, AgentAdj& lam, float gk[9]) {
@@ -620,13 +636,17 @@ __device__ __forceinline__ void reverse_segment(const TypeConst& c, const Limits
     const int64_t k0 = step0 + k_begin;
     int64_t e = resample > 0 ? (k0 + len - 1) / resample : 0;
     int64_t first = resample > 0 ? e * period : INT64_MIN;
+    const float* ck = ckpt + (int64_t)seg * kCkptRows * ld;
     for (int s = K - 1; s >= 0; --s) {
         if (s >= len) continue;
         if (k0 + s < first) { --e; first -= period; }
         Agent x;
-        load_tape(tape + (int64_t)s * tape_step, lb, x);
+        float dc[4], wprev[3];
+        uint32_t bits;
+        step_wprev(tape, tape_step, lb, s, ck, ld, bo, wprev);
+        load_tape(tape + (int64_t)s * tape_step, lb, wprev, x, dc, bits);
         wc.use(e);
-        step_vjp(c, L, g, x, wc.v, lam, gk);
+        step_vjp(c, L, g, x, wc.v, dc, bits, lam, gk);
     }
 }
 

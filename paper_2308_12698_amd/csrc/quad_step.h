@@ -154,9 +154,26 @@ __device__ __forceinline__ uint32_t order_entry(const int32_t* perm, uint32_t j,
     return a < last ? a : last;
 }
 
-/* Rows per step of the adjoint's recomputation tape: the 30 physical rows
- * of the step-start state. */
-constexpr int kTapeRows = 30;
+/* Rows per step of the adjoint's recomputation tape: the step-start state
+ * without its cost and previous body rates (26 rows: p, v, q, w, rotors,
+ * the three integrals), the rotor command the controller held through the
+ * step (4) and the controller's branch decisions (1, bits as a float). */
+constexpr int kTapeRows = 31;
+constexpr int kTapeCmd = 26;      /* first row of the held command */
+constexpr int kTapeBits = 30;     /* row of the branch decisions */
+
+/* Branch decisions of one controller evaluation, recorded by the forward
+ * pass so that the reverse sweep differentiates exactly the branches it
+ * took (bit set = condition true). */
+enum : uint32_t {
+    kBitSat = 1u << 0,            /* position error saturated to r_sat */
+    kBitIp = 1u << 1,             /* bits 1-3: position integral inside its clamp, per axis */
+    kBitAz = 1u << 4,             /* vertical acceleration raised to its floor */
+    kBitSgn = 1u << 5,            /* error quaternion flipped to the short arc */
+    kBitIa = 1u << 6,             /* bits 6-8: attitude integral inside its clamp */
+    kBitIr = 1u << 9,             /* bits 9-11: rate integral inside its clamp */
+    kBitRotor = 1u << 12          /* bits 12-15: rotor thrust in (0, f_max] (speed differentiable) */
+};
 
 #define POTATO_FMA(a, b, c) __builtin_fmaf((a), (b), (c))
 
@@ -246,15 +263,19 @@ __device__ __forceinline__ void derivative(const TypeConst& c, const float v[3],
 /* Position -> attitude -> body-rate PID cascade and mixer, evaluated once
  * per step on the step-start state; returns rotor commands relative to
  * w_ref and updates the controller memory.  CARRY: the position-loop
- * integral keeps its rounding carry in a.ip_lo. */
-template <bool CARRY = true>
+ * integral keeps its rounding carry in a.ip_lo.  BITS: the branch
+ * decisions go to *bits (kBit*; comparisons only, the arithmetic is the
+ * same). */
+template <bool CARRY = true, bool BITS = false>
 __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, const Gains& k,
-                                           Agent& a, const float wp[3], float dc[4]) {
+                                           Agent& a, const float wp[3], float dc[4],
+                                           uint32_t* bits = nullptr) {
 #pragma clang fp contract(off)
     /* position loop: error saturated to radius r_sat */
     float e[3] = {wp[0] - a.p[0], wp[1] - a.p[1], wp[2] - a.p[2]};
     const float n2 = POTATO_FMA(e[2], e[2], POTATO_FMA(e[1], e[1], e[0] * e[0]));
     const float sc = n2 > L.r_sat2 ? L.r_sat * rsq(n2) : 1.0f;
+    uint32_t b = n2 > L.r_sat2 ? kBitSat : 0u;
     float acc[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -267,9 +288,11 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
             const float lo = y - (s - a.ip[i]);
             a.ip_lo[i] = cl == s ? lo : 0.0f;
         }
+        if (BITS && cl == s) b |= kBitIp << i;
         a.ip[i] = cl;
         acc[i] = POTATO_FMA(-k.kdp, a.v[i], POTATO_FMA(k.kip, cl, k.kpp * e[i]));
     }
+    if (BITS && acc[2] + L.g < L.az_min) b |= kBitAz;
     acc[2] = fmaxf(acc[2] + L.g, L.az_min);
 
     /* collective thrust: commanded acceleration along the current body z */
@@ -292,15 +315,20 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
     const float ey = POTATO_FMA(-q[3], qd1, POTATO_FMA(-q[2], qd0, q[0] * qd2));
     const float ez = POTATO_FMA(-q[3], qd0, POTATO_FMA(-q[1], qd2, q[2] * qd1));
     const float sg = ew < 0.0f ? -2.0f : 2.0f;
+    if (BITS && ew < 0.0f) b |= kBitSgn;
     const float eatt[3] = {sg * ex, sg * ey, sg * ez};
     float alpha[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        a.ia[i] = clampf_(POTATO_FMA(eatt[i], L.dt, a.ia[i]), -L.iatt_max, L.iatt_max);
+        const float pa = POTATO_FMA(eatt[i], L.dt, a.ia[i]);
+        a.ia[i] = clampf_(pa, -L.iatt_max, L.iatt_max);
+        if (BITS && a.ia[i] == pa) b |= kBitIa << i;
         const float wdes = POTATO_FMA(-k.kda, a.w[i], POTATO_FMA(k.kia, a.ia[i], k.kpa * eatt[i]));
         /* body-rate loop, derivative on the measured rate */
         const float erate = wdes - a.w[i];
-        a.ir[i] = clampf_(POTATO_FMA(erate, L.dt, a.ir[i]), -L.irate_max, L.irate_max);
+        const float pr = POTATO_FMA(erate, L.dt, a.ir[i]);
+        a.ir[i] = clampf_(pr, -L.irate_max, L.irate_max);
+        if (BITS && a.ir[i] == pr) b |= kBitIr << i;
         alpha[i] = POTATO_FMA(-k.kdr_dt, a.w[i] - a.wprev[i], POTATO_FMA(k.kir, a.ir[i], k.kpr * erate));
         a.wprev[i] = a.w[i];
     }
@@ -318,8 +346,10 @@ __device__ __forceinline__ void controller(const TypeConst& c, const Limits& L, 
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float fi = clampf_(f[i], 0.0f, c.f_max);
+        if (BITS && f[i] > 0.0f && f[i] <= c.f_max) b |= kBitRotor << i;
         dc[i] = sqrt_fast(fi * c.inv_kf) - c.w_ref;
     }
+    if (BITS) *bits = b;
 }
 
 /* Classical RK4 with the command held, then quaternion renormalisation.

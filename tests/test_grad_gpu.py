@@ -319,7 +319,7 @@ def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
         torch.cuda.synchronize()
         runs.append((ws, gx0[:, :small.n].cpu().numpy(), gg[:, :small.n].cpu().numpy()))
         sim.close()
-    tape_per_thread = K * 30 * 4
+    tape_per_thread = K * 31 * 4          # 31 tape rows per step (state, held command, branch bits)
     assert runs[0][0] == tape_per_thread * 128 * (small.n // 64)      # pipelined: 64 blocks of 2 waves
     assert runs[1][0] % (tape_per_thread * 256) == 0                   # one agent per thread, 256-thread blocks
     assert np.isfinite(runs[0][1]).all() and np.abs(runs[0][2]).max() > 0
