@@ -32,9 +32,11 @@ struct AgentAdj {
 };
 
 /* Cotangent of the integrated rates of (v, q, w, d, J); the position rate
- * is v itself and is folded in by the caller. */
+ * is v itself and is folded in by the caller.  qh holds half the cotangent
+ * of the quaternion rate q o (0, w) / 2, i.e. the cotangent of q o (0, w),
+ * so the kinematics need no factor. */
 struct RateAdj {
-    float v[3], q[4], w[3], d[4], J;
+    float v[3], qh[4], w[3], d[4], J;
 };
 
 /* Dynamic part of the state seen by the right-hand side. */
@@ -42,11 +44,14 @@ struct Dyn {
     float v[3], q[4], w[3], d[4];
 };
 
-/* Transpose of the Jacobian of derivative() at y, applied to mu.  Adds the
- * state cotangent to (lv, lq, lw, ld) and the command cotangent to ldc. */
+/* Transpose of the Jacobian of the right-hand side (eqs. qd2-qd4, 2, 3 and
+ * the rotor lag) at y, applied to mu.  Adds the state cotangent to
+ * (lv, lq, lw, ld); the rotor-command cotangent, inv_tau times the
+ * rotor-rate cotangent, is formed by the caller from the summed mu.d.
+ * Products with inverse inertia use the per-type constants of the forward
+ * step: (I_z - I_y)/I_x = gx etc., k_f L sin(a)/I_x = ax etc. */
 __device__ __forceinline__ void derivative_vjp(const TypeConst& c, const Dyn& y, const RateAdj& mu,
-                                               float lv[3], float lq[4], float lw[3], float ld[4],
-                                               float ldc[4]) {
+                                               float lv[3], float lq[4], float lw[3], float ld[4]) {
     const float* q = y.q;
     const float* w = y.w;
     float s[4];
@@ -55,62 +60,43 @@ __device__ __forceinline__ void derivative_vjp(const TypeConst& c, const Dyn& y,
     const float ssum = (s[0] + s[1]) + (s[2] + s[3]);
     const float ftm = c.F0 + c.kf_m * ssum;
     const float x2y2 = q[1] * q[1] + q[2] * q[2];
-    const float bx = 2.0f * (q[1] * q[3] + q[0] * q[2]);
-    const float by = 2.0f * (q[2] * q[3] - q[0] * q[1]);
+    const float hbx = q[1] * q[3] + q[0] * q[2];      /* half of R(q) z, x and y */
+    const float hby = q[2] * q[3] - q[0] * q[1];
 
-    /* translational part */
-    const float l_ftm = mu.v[0] * bx + mu.v[1] * by - 2.0f * mu.v[2] * x2y2;
-    float l_ssum = c.kf_m * (l_ftm + mu.v[2]) + mu.J;
-    const float l_bx = mu.v[0] * ftm, l_by = mu.v[1] * ftm, l_x2y2 = -2.0f * ftm * mu.v[2];
+    /* translational part: v' = 2 ftm (hbx, hby, 1/2 - x2y2) - (c_d/m) v - g z */
+    const float l_ftm = 2.0f * (mu.v[0] * hbx + mu.v[1] * hby - mu.v[2] * x2y2);
+    const float l_ssum = c.kf_m * (l_ftm + mu.v[2]) + mu.J;
+    const float m0 = 2.0f * ftm * mu.v[0], m1 = 2.0f * ftm * mu.v[1], m2 = 4.0f * ftm * mu.v[2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) lv[i] -= c.cd_m * mu.v[i];
-    lq[0] += 2.0f * (q[2] * l_bx - q[1] * l_by);
-    lq[1] += 2.0f * (q[3] * l_bx - q[0] * l_by + q[1] * l_x2y2);
-    lq[2] += 2.0f * (q[0] * l_bx + q[3] * l_by + q[2] * l_x2y2);
-    lq[3] += 2.0f * (q[1] * l_bx + q[2] * l_by);
+    lq[0] += m0 * q[2] - m1 * q[1];
+    lq[1] += m0 * q[3] - m1 * q[0] - m2 * q[1];
+    lq[2] += m0 * q[0] + m1 * q[3] - m2 * q[2];
+    lq[3] += m0 * q[1] + m1 * q[2];
 
-    /* quaternion kinematics q' = 1/2 q o (0, w) */
-    const float* m = mu.q;
-    lq[0] += 0.5f * (w[0] * m[1] + w[1] * m[2] + w[2] * m[3]);
-    lq[1] += 0.5f * (-w[0] * m[0] - w[2] * m[2] + w[1] * m[3]);
-    lq[2] += 0.5f * (-w[1] * m[0] + w[2] * m[1] - w[0] * m[3]);
-    lq[3] += 0.5f * (-w[2] * m[0] - w[1] * m[1] + w[0] * m[2]);
-    lw[0] += 0.5f * (-q[1] * m[0] + q[0] * m[1] + q[3] * m[2] - q[2] * m[3]);
-    lw[1] += 0.5f * (-q[2] * m[0] - q[3] * m[1] + q[0] * m[2] + q[1] * m[3]);
-    lw[2] += 0.5f * (-q[3] * m[0] + q[2] * m[1] - q[1] * m[2] + q[0] * m[3]);
+    /* quaternion kinematics q o (0, w), cotangent mu.qh */
+    const float* m = mu.qh;
+    lq[0] += w[0] * m[1] + w[1] * m[2] + w[2] * m[3];
+    lq[1] += -w[0] * m[0] - w[2] * m[2] + w[1] * m[3];
+    lq[2] += -w[1] * m[0] + w[2] * m[1] - w[0] * m[3];
+    lq[3] += -w[2] * m[0] - w[1] * m[1] + w[0] * m[2];
+    lw[0] += -q[1] * m[0] + q[0] * m[1] + q[3] * m[2] - q[2] * m[3];
+    lw[1] += -q[2] * m[0] - q[3] * m[1] + q[0] * m[2] + q[1] * m[3];
+    lw[2] += -q[3] * m[0] + q[2] * m[1] - q[1] * m[2] + q[0] * m[3];
 
-    /* Euler's equations: w' = I^-1 (tau - w x I w) */
-    const float a0 = c.iIx * mu.w[0], a1 = c.iIy * mu.w[1], a2 = c.iIz * mu.w[2];
-    const float gzy = c.Iz - c.Iy, gxz = c.Ix - c.Iz, gyx = c.Iy - c.Ix;
-    lw[0] -= a1 * gxz * w[2] + a2 * gyx * w[1];
-    lw[1] -= a0 * gzy * w[2] + a2 * gyx * w[0];
-    lw[2] -= a0 * gzy * w[1] + a1 * gxz * w[0];
+    /* Euler's equations: w' = (ax (A + B), ay (P23 - P01), az (A - B)) - (gx w1 w2, gy w2 w0, gz w0 w1) */
+    const float b0 = c.gx * mu.w[0], b1 = c.gy * mu.w[1], b2 = c.gz * mu.w[2];
+    lw[0] -= b1 * w[2] + b2 * w[1];
+    lw[1] -= b0 * w[2] + b2 * w[0];
+    lw[2] -= b0 * w[1] + b1 * w[0];
 
     /* rotor model and allocation (eqs. 2, 3) through s_i = W_i^2 - w_ref^2 */
-    const float tX = c.kf_ls * a0, tY = c.kf_lc * a1, tZ = c.km * a2;
-    const float ls0 = tX - tY + tZ + l_ssum;
-    const float ls1 = -tX - tY - tZ + l_ssum;
-    const float ls2 = -tX + tY + tZ + l_ssum;
-    const float ls3 = tX + tY - tZ + l_ssum;
-    const float lsv[4] = {ls0, ls1, ls2, ls3};
+    const float tX = c.ax * mu.w[0], tY = c.ay * mu.w[1], tZ = c.az * mu.w[2];
+    const float pz = l_ssum + tZ, mz = l_ssum - tZ, u = tX - tY, v = tX + tY;
+    const float lsv[4] = {pz + u, mz - v, pz - u, mz + v};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        ld[i] += lsv[i] * 2.0f * (c.w_ref + y.d[i]) - c.inv_tau * mu.d[i];
-        ldc[i] += c.inv_tau * mu.d[i];
-    }
-}
-
-/* Rates of the dynamic part (same arithmetic as the forward step). */
-__device__ __forceinline__ void dyn_rate(const TypeConst& c, const Dyn& y, const float dc[4], Dyn& k,
-                                         float& kJ) {
-    derivative(c, y.v, y.q, y.w, y.d, dc, k.v, k.q, k.w, k.d, kJ);
-}
-
-__device__ __forceinline__ void dyn_axpy(const Dyn& x, float h, const Dyn& k, Dyn& out) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { out.v[i] = x.v[i] + h * k.v[i]; out.w[i] = x.w[i] + h * k.w[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { out.q[i] = x.q[i] + h * k.q[i]; out.d[i] = x.d[i] + h * k.d[i]; }
+    for (int i = 0; i < 4; ++i)
+        ld[i] += lsv[i] * (c.two_w + 2.0f * y.d[i]) - c.inv_tau * mu.d[i];
 }
 
 /*
@@ -124,30 +110,50 @@ __device__ __forceinline__ void dyn_axpy(const Dyn& x, float h, const Dyn& k, Dy
 __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, const Gains& k,
                                          const Agent& a, const float wp[3], const float dc[4],
                                          uint32_t bits, AgentAdj& lam, float gk[9]) {
-    /* ---------------- RK4 forward, keeping the stage states ---------------- */
-    Dyn y1, y2, y3, y4, kk;
+    /* ---------------- RK4 forward, keeping the stage states ----------------
+     * (the forward step's own arithmetic: rates() with the quaternion rate's
+     * factor 1/2 on the step sizes, and the rotor lag's closed-form stage
+     * values, so the stage states are the forward's bits) */
+    const float z = -(L.dt * c.inv_tau);
+    const float hz = 0.5f * z;
+    const float c2 = 1.0f + hz;
+    const float c3 = __builtin_fmaf(hz, c2, 1.0f);
+    const float c4 = __builtin_fmaf(z, c3, 1.0f);
+    float e_d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e_d[i] = a.d[i] - dc[i];
+    Dyn y1, y2, y3, y4;
+    float kv[3], kq[4], kw[3], aq[4];
 #pragma unroll
     for (int i = 0; i < 3; ++i) { y1.v[i] = a.v[i]; y1.w[i] = a.w[i]; }
 #pragma unroll
     for (int i = 0; i < 4; ++i) { y1.q[i] = a.q[i]; y1.d[i] = a.d[i]; }
-    float kJ;
-    dyn_rate(c, y1, dc, kk, kJ);
-    dyn_axpy(y1, L.half_dt, kk, y2);
-    Dyn acc_q;   /* sum of weighted rates, only q is needed (renormalisation) */
+    auto stage = [&](const Dyn& from, float hvw, float hq, float cp, Dyn& to) {
+        rates(c, from.v, from.q, from.w, from.d, kv, kq, kw);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc_q.q[i] = kk.q[i];
-    dyn_rate(c, y2, dc, kk, kJ);
-    dyn_axpy(y1, L.half_dt, kk, y3);
+        for (int i = 0; i < 3; ++i) {
+            to.v[i] = __builtin_fmaf(hvw, kv[i], y1.v[i]);
+            to.w[i] = __builtin_fmaf(hvw, kw[i], y1.w[i]);
+        }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc_q.q[i] += 2.0f * kk.q[i];
-    dyn_rate(c, y3, dc, kk, kJ);
-    dyn_axpy(y1, L.dt, kk, y4);
+        for (int i = 0; i < 4; ++i) {
+            to.q[i] = __builtin_fmaf(hq, kq[i], y1.q[i]);
+            to.d[i] = __builtin_fmaf(e_d[i], cp, dc[i]);
+        }
+    };
+    stage(y1, L.half_dt, L.quarter_dt, c2, y2);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc_q.q[i] += 2.0f * kk.q[i];
-    dyn_rate(c, y4, dc, kk, kJ);
+    for (int i = 0; i < 4; ++i) aq[i] = kq[i];
+    stage(y2, L.half_dt, L.quarter_dt, c3, y3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) aq[i] = __builtin_fmaf(2.0f, kq[i], aq[i]);
+    stage(y3, L.dt, L.half_dt, c4, y4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) aq[i] = __builtin_fmaf(2.0f, kq[i], aq[i]);
+    rates(c, y4.v, y4.q, y4.w, y4.d, kv, kq, kw);
     float qn[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) qn[i] = a.q[i] + L.dt6 * (acc_q.q[i] + kk.q[i]);
+    for (int i = 0; i < 4; ++i) qn[i] = __builtin_fmaf(L.dt12, aq[i] + kq[i], a.q[i]);
 
     /* ---------------- reverse: renormalisation ---------------- */
     {
@@ -165,10 +171,13 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
      * integrate, so their cotangents pass through unchanged and enter each
      * stage as b_i * dt * lam.p (on the stage velocity) and b_i * dt * lam.J. */
     const AgentAdj lo = lam;                 /* cotangent of the step end */
-    float ldc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float mdsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};   /* rotor-rate cotangents summed over the stages */
     float sv[3], sq[4], sw[3], sd[4];        /* running stage-state cotangent */
     const float bw[4] = {L.dt6, 2.0f * L.dt6, 2.0f * L.dt6, L.dt6};
     const float hs[4] = {0.0f, L.half_dt, L.half_dt, L.dt};   /* stage offsets */
+    /* the same halved, for the quaternion-rate cotangent mu.qh */
+    const float bwh[4] = {L.dt12, L.dt6, L.dt6, L.dt12};
+    const float hsh[4] = {0.0f, L.quarter_dt, L.quarter_dt, L.half_dt};
 #pragma unroll
     for (int i = 0; i < 3; ++i) { sv[i] = 0.0f; sw[i] = 0.0f; }
 #pragma unroll
@@ -177,6 +186,7 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
     for (int st = 3; st >= 0; --st) {
         /* cotangent of this stage's rate: b dt lam_end + h_{next} lam_{next stage} */
         const float hn = st < 3 ? hs[st + 1] : 0.0f;
+        const float hnh = st < 3 ? hsh[st + 1] : 0.0f;
         RateAdj mu;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -185,8 +195,9 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            mu.q[i] = bw[st] * lo.q[i] + hn * sq[i];
+            mu.qh[i] = bwh[st] * lo.q[i] + hnh * sq[i];
             mu.d[i] = bw[st] * lo.d[i] + hn * sd[i];
+            mdsum[i] += mu.d[i];
         }
         mu.J = bw[st] * lo.J;
         const Dyn& ys = st == 3 ? y4 : (st == 2 ? y3 : (st == 1 ? y2 : y1));
@@ -196,7 +207,7 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
         for (int i = 0; i < 3; ++i) { nv_[i] = bw[st] * lo.p[i]; nw_[i] = 0.0f; }
 #pragma unroll
         for (int i = 0; i < 4; ++i) { nq_[i] = 0.0f; nd_[i] = 0.0f; }
-        derivative_vjp(c, ys, mu, nv_, nq_, nw_, nd_, ldc);
+        derivative_vjp(c, ys, mu, nv_, nq_, nw_, nd_);
         /* stage state = y1 + h_st * previous rate: cotangent flows to y1 and
          * (scaled by h_st) to the previous stage's rate */
 #pragma unroll
@@ -210,6 +221,9 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
             lam.q[i] += nq_[i]; lam.d[i] += nd_[i];
         }
     }
+    float ldc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ldc[i] = c.inv_tau * mdsum[i];
 
     /* ---------------- controller, forward with intermediates ----------------
      * (the values the reverse needs; the branches are the recorded ones) */
