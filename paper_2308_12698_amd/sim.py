@@ -10,6 +10,7 @@ import ctypes as C
 import hashlib
 import json
 import os
+import re
 import weakref
 
 import torch
@@ -49,16 +50,29 @@ def _check_rows(name, t, rows, n, dtype=torch.float32):
                          f"{tuple(t.shape)} strides {t.stride()}")
 
 
-_LIB_DIGEST = None
+_BUILD_DIGEST = None
 
 
-def _library_digest() -> str:
-    """Hash of the loaded library file: tuned shapes are kept per build."""
-    global _LIB_DIGEST
-    if _LIB_DIGEST is None:
-        with open(L.LIB_PATH, "rb") as f:
-            _LIB_DIGEST = hashlib.sha256(f.read()).hexdigest()[:16]
-    return _LIB_DIGEST
+def build_digest() -> str:
+    """Hash of what the library is built from: the HIP sources and headers
+    (comments and blank space removed) and the compiler flags.  Tuned launch
+    shapes are kept per build: a change of the kernels invalidates them, a
+    rebuild of the same sources does not."""
+    global _BUILD_DIGEST
+    if _BUILD_DIGEST is None:
+        from . import build as B
+        h = hashlib.sha256()
+        paths = sorted(os.path.join(B.CSRC, f) for f in os.listdir(B.CSRC) if f.endswith((".hip", ".h")))
+        for path in paths + [os.path.join(B.INCLUDE, "potato.h")]:
+            with open(path) as f:
+                text = f.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            h.update(os.path.basename(path).encode())
+            h.update("".join(text.split()).encode())
+        h.update(" ".join(B.HIP_FLAGS).encode())
+        _BUILD_DIGEST = h.hexdigest()[:16]
+    return _BUILD_DIGEST
 
 
 def autotune_cached(path: str, key: str, run) -> dict:
@@ -213,13 +227,16 @@ class Simulator:
         """Time the fused form's launch shapes on a scratch copy; keep the best.
 
         ``cache`` (default: the POTATO_AUTOTUNE_CACHE environment variable) is
-        a JSON file of earlier results, keyed by device, library build,
+        a JSON file of earlier results, keyed by device, build (build_digest),
         variant, agent count and probe length; a hit skips the timing."""
         n = int(n_agents if n_agents is not None else state.shape[1])
         st, pp, cm = self._structs(state, n, type_idx, perm, gains, motor_cmd, wp,
                                    resample_every, step0, carry=carry)
 
+        self.tuned_from_cache = True
+
         def run():
+            self.tuned_from_cache = False
             best = L.Options()
             L.check(self._lib.potato_autotune(self._h, C.byref(st), C.byref(pp), C.byref(cm),
                                               float(dt), n, int(probe_steps), C.byref(best),
@@ -232,7 +249,7 @@ class Simulator:
             return run()
         props = torch.cuda.get_device_properties(state.device)
         key = "|".join(str(x) for x in (
-            getattr(props, "gcnArchName", props.name), _library_digest(), self.mode, self.n_types,
+            getattr(props, "gcnArchName", props.name), build_digest(), self.mode, self.n_types,
             type_idx is not None, gains is not None, perm is not None, carry is not None, n,
             int(probe_steps)))
         return autotune_cached(path, key, run)
