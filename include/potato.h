@@ -266,17 +266,17 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
 
 /*
  * Reverse mode of a closed-loop potato_step call that wrote checkpoints:
- * given grad_final = dL/dx_N (device float[30][ld], the 30 physical rows of
- * the final state), compute grad_x0 = dL/dx_0 (device float[30][ld]) and,
- * if grad_gains is not NULL, dL/dgains per agent (device float[9][ld]; with
- * type gains the caller sums over the agents of a type).  This is the
- * vector-Jacobian product of the rollout map (x_0, gains) -> x_N through
- * every step of the forward pass: controller, mixer, RK4 stages and
- * renormalisation (the time discretisation of Sec. II-B differentiated
- * exactly, not the continuous adjoint).  grad_x0 covers all 30 rows: rows
- * 0-16 are the cotangent of the initial rigid-body and rotor state, rows
- * 17-28 that of the initial controller memory, row 29 that of the initial
- * cost (a carry has the cotangent of its row).
+ * given grad_final = dL/dx_N (device float[30][ld], the 30 rows of the
+ * final state), compute grad_x0 = dL/dx_0 for the initial rigid-body and
+ * rotor state (device float[17][ld]: rows 0-16 of the state layout), if
+ * grad_mem is not NULL the cotangent of the initial controller memory and
+ * cost (device float[13][ld]: state rows 17-29), and, if grad_gains is not
+ * NULL, dL/dgains per agent (device float[9][ld]; with type gains the
+ * caller sums over the agents of a type).  This is the vector-Jacobian
+ * product of the rollout map (x_0, gains) -> x_N through every step of the
+ * forward pass: controller, mixer, RK4 stages and renormalisation (the time
+ * discretisation of Sec. II-B differentiated exactly, not the continuous
+ * adjoint).  A carry has the cotangent of its row.
  *   params, cmds, dt, n_agents, n_steps: exactly as in the forward call;
  *   ckpt, ckpt_every: the checkpoints that call wrote (40 rows per slot:
  *   the state and its carries);
@@ -288,14 +288,16 @@ potato_status potato_order_by_type(potato_ctx* ctx, const uint8_t* type, int64_t
  * the same result bit for bit.  Errors: POTATO_EINVAL as in potato_step, plus null ckpt,
  * grad_final or grad_x0, ckpt_every < 1 or a workspace that is too small;
  * POTATO_EUNSUPPORTED in open-loop mode and for a context whose type table
- * holds cars or fixed-wing aircraft.  grad_x0 may alias grad_final.
+ * holds cars or fixed-wing aircraft.  grad_x0 may alias rows 0-16 of
+ * grad_final and grad_mem rows 17-29 (each agent's column is read before
+ * it is written).
  */
 int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* params, int64_t n_agents,
                                         int32_t ckpt_every);
 potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params, const potato_cmds* cmds,
                                    float dt, int64_t n_agents, int32_t n_steps, const float* ckpt,
                                    int32_t ckpt_every, int64_t ld, const float* grad_final,
-                                   float* grad_x0, float* grad_gains, void* workspace,
+                                   float* grad_x0, float* grad_mem, float* grad_gains, void* workspace,
                                    int64_t workspace_bytes, void* stream);
 
 /*

@@ -89,7 +89,7 @@ def load():
     L.potato_order_by_type.argtypes = [P, P, I64, P, P, I64, P]
     L.potato_backward_workspace_bytes.argtypes = [P, P, I64, I32]
     L.potato_backward_workspace_bytes.restype = I64
-    L.potato_step_backward.argtypes = [P, P, P, F, I64, I32, P, I32, I64, P, P, P, P, I64, P]
+    L.potato_step_backward.argtypes = [P, P, P, F, I64, I32, P, I32, I64, P, P, P, P, P, I64, P]
     L.potato_collision_workspace_bytes.argtypes = [I64]
     L.potato_collision_workspace_bytes.restype = I64
     L.potato_detect_collisions.argtypes = [P, P, P, I64, P, P, P, I64, P]

@@ -662,7 +662,8 @@ int64_t potato_backward_workspace_bytes(potato_ctx* ctx, const potato_params* pa
 potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params, const potato_cmds* cmds,
                                    float dt, int64_t n_agents, int32_t n_steps, const float* ckpt,
                                    int32_t ckpt_every, int64_t ld, const float* grad_final, float* grad_x0,
-                                   float* grad_gains, void* workspace, int64_t workspace_bytes, void* stream) {
+                                   float* grad_mem, float* grad_gains, void* workspace, int64_t workspace_bytes,
+                                   void* stream) {
     ApiRange range("potato_step_backward");
     if (!ctx || !params || !cmds) return fail(POTATO_EINVAL, "ctx, params and cmds must be non-null");
     if (ctx->opts.mode != POTATO_CLOSED_LOOP)
@@ -696,7 +697,7 @@ potato_status potato_step_backward(potato_ctx* ctx, const potato_params* params,
     a.gains = params->gains; a.gains_ld = params->gains_ld;
     a.wp = cmds->wp; a.cmd_ld = cmds->ld; a.n_epochs = cmds->n_epochs; a.resample = cmds->resample_every;
     a.step0 = cmds->step0; a.n_steps = n_steps; a.K = ckpt_every;
-    a.grad_final = grad_final; a.grad_x0 = grad_x0; a.grad_gains = grad_gains;
+    a.grad_final = grad_final; a.grad_x0 = grad_x0; a.grad_mem = grad_mem; a.grad_gains = grad_gains;
     a.tape = reinterpret_cast<float*>(workspace); a.tape_ld = (int64_t)sh.grid * sh.block;
     a.n_types = het ? ctx->n_types : 1; a.table = ctx->d_table;
     a.alive = params->alive;

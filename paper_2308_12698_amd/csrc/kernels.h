@@ -76,7 +76,8 @@ struct AdjArgs {
     int32_t n_steps;
     int32_t K;                   /* checkpoint interval */
     const float* grad_final;     /* [30][ld] */
-    float* grad_x0;              /* [30][ld] */
+    float* grad_x0;              /* [17][ld]: rows 0-16 */
+    float* grad_mem;             /* [13][ld] or null: rows 17-29 */
     float* grad_gains;           /* [9][ld] or null */
     float* tape;                 /* layouts at launch_adjoint */
     int64_t tape_ld;             /* threads in the grid (a multiple of 64) */

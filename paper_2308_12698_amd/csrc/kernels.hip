@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(kAdjBlock)
         if (steps > 0)
             agent_backward(c, lim, g, A.ckpt, ld, bo, A.K, n_seg_all, steps, A.step0, A.wp, A.cmd_ld,
                            A.n_epochs, A.resample, tape, tape_step, lb, lam, gk);
-        store_adj(A.grad_x0, ld, bo, lam);
+        store_adj(A.grad_x0, A.grad_mem, ld, bo, lam);
         if (A.grad_gains) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) elem(A.grad_gains + k * ld, bo) = gk[k];
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(kAdjPipeBlock)
             __syncthreads();
         }
         if (!producer && valid) {
-            store_adj(A.grad_x0, ld, bo, lam);
+            store_adj(A.grad_x0, A.grad_mem, ld, bo, lam);
             if (A.grad_gains) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) elem(A.grad_gains + k * ld, bo) = gk[k];

@@ -423,17 +423,22 @@ __device__ __forceinline__ void load_adj(const float* base, int64_t ld, uint32_t
     l.J = row(29);
 }
 
-__device__ __forceinline__ void store_adj(float* base, int64_t ld, uint32_t bo, const AgentAdj& l) {
-    auto row = [&](int k) -> float& { return elem(row_ptr(base, ld, k), bo); };
+/* Cotangent of the initial state: rows 0-16 to x0 ([17][ld]), rows 17-29
+ * to mem ([13][ld]) when it is given. */
+__device__ __forceinline__ void store_adj(float* x0, float* mem, int64_t ld, uint32_t bo, const AgentAdj& l) {
+    auto row = [&](int k) -> float& { return elem(row_ptr(x0, ld, k), bo); };
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        row(k) = l.p[k]; row(3 + k) = l.v[k]; row(10 + k) = l.w[k];
-        row(17 + k) = l.ip[k]; row(20 + k) = l.ia[k];
-        row(23 + k) = l.ir[k]; row(26 + k) = l.wprev[k];
-    }
+    for (int k = 0; k < 3; ++k) { row(k) = l.p[k]; row(3 + k) = l.v[k]; row(10 + k) = l.w[k]; }
 #pragma unroll
     for (int k = 0; k < 4; ++k) { row(6 + k) = l.q[k]; row(13 + k) = l.d[k]; }
-    row(29) = l.J;
+    if (mem) {
+        auto mrow = [&](int k) -> float& { return elem(row_ptr(mem, ld, k), bo); };
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            mrow(k) = l.ip[k]; mrow(3 + k) = l.ia[k]; mrow(6 + k) = l.ir[k]; mrow(9 + k) = l.wprev[k];
+        }
+        mrow(12) = l.J;
+    }
 }
 
 /* Tape slots: one block of kTapeRows x 64 floats per wave and step, a row

@@ -259,8 +259,10 @@ class Simulator:
                       want_gains=True, workspace=None, alive=None, stream=None):
         """Reverse sweep of a checkpointed closed-loop step() call.
 
-        grad_final: [30, ld] cotangent of the final physical rows.  Returns
-        (grad_x0 [30, ld], grad_gains [9, ld] or None)."""
+        grad_final: [30, ld] cotangent of the final state.  Returns
+        (grad_x0 [30, ld], grad_gains [9, ld] or None): rows 0-16 of grad_x0
+        are the library's grad_x0 (the initial rigid-body and rotor state),
+        rows 17-29 its grad_mem (controller memory and cost)."""
         _check_rows("grad_final", grad_final, 30, n_agents or grad_final.shape[1])
         if not grad_final.is_contiguous():
             raise ValueError("grad_final must be contiguous")
@@ -288,8 +290,8 @@ class Simulator:
         gg = torch.zeros((9, ld), dtype=torch.float32, device=grad_final.device) if want_gains else None
         L.check(self._lib.potato_step_backward(self._h, C.byref(pp), C.byref(cm), float(dt), n,
                                                int(n_steps), _ptr(ckpt), int(ckpt_every), ld,
-                                               _ptr(grad_final), _ptr(gx0), _ptr(gg), _ptr(workspace),
-                                               nbytes, _stream_handle(stream)))
+                                               _ptr(grad_final), _ptr(gx0), _ptr(gx0[17:]), _ptr(gg),
+                                               _ptr(workspace), nbytes, _stream_handle(stream)))
         return gx0, gg
 
     def detect_collisions(self, state, alive, *, n_agents=None, type_idx=None, died=None,

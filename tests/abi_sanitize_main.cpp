@@ -84,7 +84,7 @@ int main() {
     expect(potato_order_by_type(nullptr, nullptr, 10, nullptr, nullptr, 0, nullptr) == POTATO_EINVAL, "order null");
     expect(potato_backward_workspace_bytes(nullptr, &pp, 10, 5) == -1, "backward workspace null");
     expect(potato_step_backward(nullptr, &pp, &cm, 1e-3f, 10, 10, nullptr, 5, 10, nullptr, nullptr, nullptr,
-                                nullptr, 0, nullptr) == POTATO_EINVAL, "backward null");
+                                nullptr, nullptr, 0, nullptr) == POTATO_EINVAL, "backward null");
     expect(potato_collision_workspace_bytes(0) == -1 && potato_collision_workspace_bytes(1000) > 0,
            "collision workspace");
     expect(potato_detect_collisions(nullptr, &st, &pp, 10, nullptr, nullptr, nullptr, 0, nullptr) == POTATO_EINVAL,

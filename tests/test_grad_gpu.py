@@ -329,3 +329,38 @@ def test_pipelined_adjoint_is_bitwise_the_one_wave_adjoint(torch_dev, het):
         dead = alive_small == 0
         seed0 = np.random.default_rng(8).normal(size=(30, small.n)).astype(np.float32)
         assert np.array_equal(runs[0][1][:, dead], seed0[:, dead]) and not runs[0][2][:, dead].any()
+
+
+def test_backward_contract_17_rows_and_optional_memory(torch_dev, diff_run):
+    """Through the C ABI: grad_x0 is the 17 rows of the rigid body and rotors
+    ([17][ld]) and grad_mem, when given, the 13 rows of controller memory and
+    cost ([13][ld]); buffers of exactly those rows with guard rows after them
+    come back with every guard element untouched, and the values equal the
+    binding's 30-row result."""
+    import ctypes as C
+    torch, dev = torch_dev
+    from paper_2308_12698_amd import _lib as L
+    sw, sim = diff_run["sw"], diff_run["sim"]
+    n, K, guard, sentinel = sw.n, sw.extra["ckpt_every"], 4, -7777.0
+    pp = L.Params(None, None, C.c_void_p(diff_run["gains_t"].data_ptr()), n, None)
+    wp = diff_run["wp_t"]
+    cm = L.Cmds(None, C.c_void_p(wp.data_ptr()), wp.shape[0], 0, wp.shape[2], 0)
+    nbytes = int(sim._lib.potato_backward_workspace_bytes(sim._h, C.byref(pp), n, K))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for with_mem in (False, True):
+        gx = torch.full((17 + guard, n), sentinel, device=dev)
+        gm = torch.full((13 + guard, n), sentinel, device=dev) if with_mem else None
+        gg = torch.zeros((9, n), device=dev)
+        rc = sim._lib.potato_step_backward(sim._h, C.byref(pp), C.byref(cm), float(sw.dt), n, sw.n_steps,
+                                           C.c_void_p(diff_run["ckpt"].data_ptr()), K, n,
+                                           C.c_void_p(diff_run["gfin"].data_ptr()), C.c_void_p(gx.data_ptr()),
+                                           None if gm is None else C.c_void_p(gm.data_ptr()),
+                                           C.c_void_p(gg.data_ptr()), C.c_void_p(ws.data_ptr()), nbytes, None)
+        L.check(rc)
+        torch.cuda.synchronize()
+        assert torch.all(gx[17:] == sentinel)
+        assert np.array_equal(gx[:17].cpu().numpy(), diff_run["gx0"][:17])
+        assert np.array_equal(gg.cpu().numpy(), diff_run["gg"])
+        if with_mem:
+            assert torch.all(gm[13:] == sentinel)
+            assert np.array_equal(gm[:13].cpu().numpy(), diff_run["gx0"][17:30])
