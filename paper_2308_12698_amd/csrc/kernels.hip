@@ -116,9 +116,11 @@ __device__ __forceinline__ void advance_vehicle(const StepArgs& A, const VehCons
                     wp[k] = elem(uniform(A.wp + ((int64_t)epoch * 3 + k) * A.cmd_ld), bo);
                 next_epoch_step = epoch < A.n_epochs - 1 ? next_epoch_step + A.resample : INT64_MAX;
             }
-            veh_guidance<KIND>(c, x, wp, u);
         }
-        veh_rk4<KIND, CARRY>(c, lim, x, lo, u);
+        VehTrig T;
+        veh_trig<KIND>(x, T);
+        if (MODE == 1) veh_guidance<KIND>(c, x, T, wp, u);
+        veh_rk4<KIND, CARRY>(c, lim, x, T, lo, u);
     }
 #pragma unroll
     for (int k = 0; k < 7; ++k)
