@@ -87,6 +87,13 @@ struct AdjArgs {
     Limits lim;
 };
 
+/* Mixed vehicle kinds in the caller's order are stepped grouped by kind
+ * within chunks of up to this many block widths.  Unless a grid is given,
+ * such a launch takes as many blocks as the chip holds at once (fewer if
+ * the swarm needs fewer); each block owns ceil(n / grid) agents, rounded
+ * up to a multiple of 64. */
+constexpr int kKindGroup = 4;
+
 /* Launch one rollout kernel (n_steps of args) on `stream`. */
 hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int grid_blocks,
                           hipStream_t stream);

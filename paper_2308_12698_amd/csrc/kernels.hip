@@ -28,6 +28,11 @@
  * order by type.  k_count_nonfinite: agents with a NaN or infinite row.
  * No MFMA: nothing in a quadrotor step is a dense contraction.
  */
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.h"
 #include "quad_adjoint.h"
 #include "scan.h"
@@ -134,6 +139,84 @@ __device__ __forceinline__ void advance_vehicle(const StepArgs& A, const VehCons
     for (int k = 0; k < 3; ++k) p[k] = x[k];
 }
 
+/* Mixed vehicle kinds in the caller's order: a block sorts a chunk of up
+ * to kKindGroup block widths of consecutive agents by kind, stably, from
+ * wave ballots and a prefix over the (width, wave) groups' counts.  Each
+ * kind starts on a multiple of 64 sorted positions, so that no group of
+ * 64 holds two kinds (the gaps hold -1).  The sort key puts the longest
+ * step first (aircraft, then quadrotors, then cars), so that the groups
+ * handed out last are short.  Afterwards slot[p] is the offset from base
+ * of the agent at sorted position p, n_groups the groups of 64 that hold
+ * an agent, and `next` (the next group to hand out) is 0.  Contains
+ * barriers: every thread of the block calls it with the same arguments. */
+constexpr int kKinds = 3;
+struct KindSort {
+    int32_t count[kKindGroup * 8][kKinds];        /* per (width, wave) group */
+    int32_t first[kKindGroup * 8][kKinds];        /* its first sorted position */
+    int32_t slot[kKindGroup * 512 + kKinds * 64];
+    int32_t n_groups;
+    int32_t next;
+};
+
+__device__ __forceinline__ int kind_key(int kind) {
+    return kind == KIND_WING ? 0 : kind == KIND_QUAD ? 1 : 2;
+}
+
+__device__ __forceinline__ void group_by_kind(const StepArgs& A, const TypeConst* tab, int64_t base, int64_t end,
+                                              int ch, KindSort& S) {
+    const int B = blockDim.x, t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63, n_waves = (B + 63) >> 6, n_groups = ch * n_waves;
+    const uint64_t below = (uint64_t(1) << lane) - 1;
+    int key[kKindGroup];
+    uint64_t same[kKindGroup];
+#pragma unroll
+    for (int c = 0; c < kKindGroup; ++c) {
+        key[c] = kKinds;                          /* past the end: not placed */
+        same[c] = 0;
+        if (c < ch) {
+            const int64_t j = base + (int64_t)c * B + t;
+            if (j < end) key[c] = kind_key(tab[type_entry(A.type, (uint32_t)j, A.n_types)].kind);
+#pragma unroll
+            for (int k = 0; k < kKinds; ++k) {
+                const uint64_t m = __ballot(key[c] == k);
+                if (key[c] == k) same[c] = m;
+                if (lane == 0) S.count[c * n_waves + wave][k] = __popcll(m);
+            }
+        }
+    }
+    __syncthreads();
+    /* every wave has left the previous chunk's hand-out loop */
+    if (t <= kKinds) {
+        /* key t starts after every smaller key's agents rounded up to 64,
+         * then its (width, wave) groups in order; thread kKinds counts the
+         * groups of 64 */
+        int32_t run = 0;
+        for (int k = 0; k < t; ++k) {
+            int32_t total = 0;
+            for (int g = 0; g < n_groups; ++g) total += S.count[g][k];
+            run += (total + 63) & ~63;
+        }
+        if (t < kKinds) {
+            for (int g = 0; g < n_groups; ++g) {
+                S.first[g][t] = run;
+                run += S.count[g][t];
+            }
+        } else {
+            S.n_groups = run >> 6;
+        }
+    }
+    if (t == 0) S.next = 0;
+    for (int p = t; p < ch * B + kKinds * 64; p += B) S.slot[p] = -1;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kKindGroup; ++c)
+        if (c < ch && key[c] < kKinds)
+            S.slot[S.first[c * n_waves + wave][key[c]] + __popcll(same[c] & below)] = c * B + t;
+    __syncthreads();
+    /* the next call writes count, first, n_groups, next and slot only after
+     * a barrier that every thread reaches once it is done with this call's */
+}
+
 template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY, bool KINDS>
 __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
     static_assert(!(KINDS && CKPT), "checkpoints (the adjoint) cover quadrotors only");
@@ -152,7 +235,8 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 #endif
     const int64_t ld = A.ld;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.n; j += stride) {
+    /* One agent's whole launch. */
+    auto advance = [&](int64_t j) {
         /* agent index < 2^30, so byte offsets into rows fit 32 bits.  Row
          * addresses are uniform: every active lane starts at step 0 and
          * steps together, so the epoch and checkpoint slot agree too. */
@@ -176,7 +260,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         };
         if (A.alive && !elem(A.alive, i)) {
             snap_stored();
-            continue;
+            return;
         }
 
         int64_t left = (int64_t)c.budget - A.step0;
@@ -184,7 +268,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
         const int steps = left < A.n_steps ? (int)left : A.n_steps;
         if (steps == 0) {
             snap_stored();
-            continue;
+            return;
         }
         if (KINDS && c.kind != KIND_QUAD) {
             float pf[3];
@@ -196,7 +280,7 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 #pragma unroll
                 for (int k = 0; k < 3; ++k) snap(k) = pf[k];
             }
-            continue;
+            return;
         }
 
         Agent a;
@@ -316,7 +400,41 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
 #pragma unroll
             for (int k = 0; k < 3; ++k) snap(k) = a.p[k];
         }
+    };
+    if constexpr (KINDS && HET && !PERM) {
+        /* cars, aircraft and quadrotors mixed in the caller's order: each
+         * block owns ceil(n / grid) consecutive agents (a multiple of 64)
+         * and steps them in chunks of up to kKindGroup block widths,
+         * grouped by kind, so that a wave's 64 agents are of one kind
+         * instead of running every kind's loop in turn; the block's waves
+         * take the groups in turn, so that they finish together.  An agent's
+         * arithmetic does not depend on its lane, so the results are the
+         * same bits.  The chunk loop's bounds are the same for the whole
+         * block, so every thread reaches the barriers. */
+        __shared__ KindSort sorted;
+        const int64_t B = blockDim.x;
+        const int64_t per_block = ((A.n + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
+        const int64_t lo = (int64_t)blockIdx.x * per_block;
+        const int64_t hi = lo + per_block < A.n ? lo + per_block : A.n;
+        const int lane = threadIdx.x & 63;
+        for (int64_t base = lo; base < hi; base += kKindGroup * B) {
+            const int64_t end = base + kKindGroup * B < hi ? base + kKindGroup * B : hi;
+            group_by_kind(A, tab, base, end, (int)((end - base + B - 1) / B), sorted);
+            /* the sorted groups of 64 go to whichever wave asks first */
+            const int n_groups = sorted.n_groups;
+            for (;;) {
+                int g = 0;
+                if (lane == 0) g = atomicAdd(&sorted.next, 1);
+                g = __builtin_amdgcn_readfirstlane(g);
+                if (g >= n_groups) break;
+                const int32_t off = sorted.slot[g * 64 + lane];
+                if (off >= 0) advance(base + off);
+            }
+        }
+    } else {
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.n; j += stride) advance(j);
     }
+
 }
 
 /* Reverse sweep of the checkpointed closed-loop rollout: one agent per lane
@@ -586,10 +704,44 @@ size_t rollout_lds_bytes(const Variant& v, int n_types) {
     return ((sizeof(Limits) + 15) / 16) * 16 + (size_t)(v.het ? n_types : 1) * sizeof(TypeConst);
 }
 
+/* Blocks of `block` threads the chip holds at once for kernel fn: the
+ * occupancy per compute unit times the compute units of the current
+ * device, cached per (device, kernel, block, LDS bytes). */
+static hipError_t kind_fill_blocks(const void* fn, int block, int n_types, const Variant& v, int* out) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t lds = rollout_lds_bytes(v, n_types);
+    const auto key = std::make_tuple(dev, fn, block, lds);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int per_cu = 0, n_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *out = cache[key] = std::max(1, per_cu * n_cu);
+    return hipSuccess;
+}
+
 hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int grid_blocks,
                           hipStream_t stream) {
     const void* fn = rollout_kernel(v);
     int64_t grid = grid_blocks > 0 ? grid_blocks : (a.n + block - 1) / block;
+    if (grid_blocks <= 0 && v.kinds && v.het && !v.perm) {
+        /* mixed kinds grouped per block: one round of blocks, as many as
+         * the chip holds at once, so that each sorts chunks as wide as the
+         * swarm allows */
+        int fill = 0;
+        hipError_t e = kind_fill_blocks(fn, block, a.n_types, v, &fill);
+        if (e != hipSuccess) return e;
+        grid = std::min<int64_t>(grid, fill);
+    }
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     void* args[] = {const_cast<StepArgs*>(&a)};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)block), args,

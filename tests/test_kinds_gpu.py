@@ -203,7 +203,8 @@ def test_kinds_full_size(oracle, torch_dev):
     """1,048,576 agents (half quadrotors, a quarter cars, a quarter
     aircraft) in the type order: every agent against the references after
     1,000 steps, then 2,048 sampled agents after 10,000 steps (waypoints
-    redrawn every 2,000 steps for the quadrotors)."""
+    redrawn every 2,000 steps for the quadrotors); the launch in index
+    order equals the type-ordered one bitwise."""
     torch, dev = torch_dev
     sw = I.config_kinds()
     print("kinds full size: 1,048,576 agents, 1,000 steps then 10,000", flush=True)
@@ -212,6 +213,8 @@ def test_kinds_full_size(oracle, torch_dev):
     ref = oracle_run(oracle, sw, 1000)
     assert_kinds_parity(got, ref, sw)
     del ref
+    # the kinds shuffled in index order: each block groups its agents by kind
+    assert np.array_equal(gpu_run(torch_dev, sw, 1000, steps_per_launch=1000), got)
     got = gpu_run(torch_dev, sw, 10000, steps_per_launch=1000, ordered=True)
     sample = np.sort(np.random.default_rng(21).choice(sw.n, 2048, replace=False))
     ref = oracle_run(oracle, sw, 10000, agents=sample)
