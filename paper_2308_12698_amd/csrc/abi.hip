@@ -58,6 +58,7 @@ struct potato_ctx {
     int device = 0;
     int n_types = 0;
     bool kinds = false;                /* some type is a car or fixed-wing aircraft */
+    int n_groups = 0;                  /* classes grouped within a block (2..kMaxGroups), or 0 */
     std::vector<potato_type_params> params;
     std::vector<TypeConst> consts;
     TypeConst* d_table = nullptr;
@@ -154,7 +155,7 @@ TypeConst derive_vehicle(const potato_type_params& p, const potato_limits& L) {
         v.g = L.g;
     }
     c.budget = p.step_budget;
-    c.kind = p.kind;
+    c.kind = (int16_t)p.kind;
     return c;
 }
 
@@ -305,12 +306,13 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     a.snap = nullptr;
     a.lim = make_limits(ctx->limits, dt);
     if (!P.v.het) a.n_types = 1;      /* homogeneous launch: only type 0 is staged */
+    a.n_groups = P.v.het && !P.v.perm ? ctx->n_groups : 0;
 
     const potato_options& o = ctx->opts;
-    /* kinds mixed in the caller's order are grouped per block: the widest
-     * blocks measured best (at 1M agents, 512 threads: 9.3e10 agent-steps/s
-     * against 8.2e10 with 256 and 7.0e10 with 128) */
-    Tuned t{P.v.kinds && P.v.het && !P.v.perm ? 512 : 256, 100, 0};
+    /* agents grouped per block: the widest blocks measured best (mixed
+     * kinds at 1M agents, 512 threads: 9.3e10 agent-steps/s against 8.2e10
+     * with 256 and 7.0e10 with 128) */
+    Tuned t{rollout_grouped(P.v, P.a) ? 512 : 256, 100, 0};
     auto it = ctx->tuned.find(TuneKey{P.v.mode, P.v.het, P.v.gains, P.v.perm});
     if (it != ctx->tuned.end()) t = it->second;
     if (o.form == POTATO_FORM_PLAIN) {
@@ -413,6 +415,26 @@ potato_status potato_create(potato_ctx** out, const potato_type_params* types, i
         const bool quad = types[t].kind == POTATO_KIND_QUAD;
         ctx->consts.push_back(quad ? derive(types[t], *limits) : derive_vehicle(types[t], *limits));
         ctx->kinds = ctx->kinds || !quad;
+    }
+    /* classes of types that take the same steps of the same loop (equal
+     * budget and kind), numbered longest first: by budget, then by the
+     * kind's step (measured per agent-step at 1M agents: quadrotor, then
+     * fixed wing, then car).  Launches with a per-agent type and no
+     * processing order group their agents by class within each block when
+     * there are 2..kMaxGroups classes. */
+    {
+        auto cost = [](int32_t kind) { return kind == KIND_QUAD ? 2 : kind == KIND_WING ? 1 : 0; };
+        std::vector<std::pair<int32_t, int>> cls;
+        for (int t = 0; t < n_types; ++t) cls.emplace_back(ctx->consts[t].budget, cost(ctx->consts[t].kind));
+        std::sort(cls.begin(), cls.end(), std::greater<std::pair<int32_t, int>>());
+        cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
+        const bool group = cls.size() >= 2 && cls.size() <= (size_t)kMaxGroups;
+        ctx->n_groups = group ? (int)cls.size() : 0;
+        for (int t = 0; t < n_types; ++t) {
+            const std::pair<int32_t, int> key(ctx->consts[t].budget, cost(ctx->consts[t].kind));
+            ctx->consts[t].group =
+                group ? (int16_t)(std::find(cls.begin(), cls.end(), key) - cls.begin()) : 0;
+        }
     }
     /* rank of each type: longest budget first, ties by index */
     std::vector<int32_t> order(n_types), rank(n_types);
@@ -554,7 +576,7 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
         Plan P = make_plan(ctx, &ss, params, cmds, dt, n_agents, nullptr, 0);
         int per_cu = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rollout_kernel(P.v), b,
-                                                         rollout_lds_bytes(P.v, ctx->n_types));
+                                                         rollout_lds_bytes(P.v, P.a, b));
         if (e != hipSuccess) break;
         const int64_t full = (n_agents + b - 1) / b;
         std::vector<int> grids = {0};

@@ -44,6 +44,8 @@ struct StepArgs {
     int32_t n_types;
     const TypeConst* table;      /* device [n_types] */
     const uint8_t* alive;        /* [ld] or null: 0 = dead, not advanced */
+    int32_t n_groups;            /* classes of types grouped within a block (a per-agent
+                                    type and no processing order), or 0: none */
     float* snap;                 /* [3][n] device view of pinned host memory, or null: every
                                     agent's position after this launch (not with ckpt) */
     Limits lim;
@@ -87,12 +89,19 @@ struct AdjArgs {
     Limits lim;
 };
 
-/* Mixed vehicle kinds in the caller's order are stepped grouped by kind
- * within chunks of up to this many block widths.  Unless a grid is given,
- * such a launch takes as many blocks as the chip holds at once (fewer if
- * the swarm needs fewer); each block owns ceil(n / grid) agents, rounded
- * up to a multiple of 64. */
-constexpr int kKindGroup = 4;
+/* Agents of a per-agent type in the caller's order (no checkpoints) are
+ * stepped grouped by class (types of equal step budget and kind; 2 to
+ * kMaxGroups classes) within chunks of up to kGroupWidths block widths.
+ * Unless a grid is given, such a launch takes as many blocks as the chip
+ * holds at once (fewer if the swarm needs fewer); each block owns
+ * ceil(n / grid) agents, rounded up to a multiple of 64.  The sort takes
+ * group_lds_words(block) words of LDS after the type table. */
+constexpr int kGroupWidths = 4;
+constexpr int kMaxGroups = 8;
+__host__ __device__ constexpr int64_t group_lds_words(int block) {
+    return 2 * (int64_t)kGroupWidths * (block / 64) * kMaxGroups + (int64_t)kGroupWidths * block +
+           kMaxGroups * 64 + 2;
+}
 
 /* Launch one rollout kernel (n_steps of args) on `stream`. */
 hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int grid_blocks,
@@ -118,8 +127,10 @@ constexpr int kAdjPipeBlock = 128;
 #define POTATO_ADJOINT_PIPE 1
 #endif
 
-/* Dynamic LDS bytes the variant needs for n_types. */
-size_t rollout_lds_bytes(const Variant& v, int n_types);
+/* Dynamic LDS bytes of a launch: the limits, a.n_types type-table entries
+ * and, when it groups its agents, the sort's words. */
+size_t rollout_lds_bytes(const Variant& v, const StepArgs& a, int block);
+bool rollout_grouped(const Variant& v, const StepArgs& a);
 
 /* Processing order by type (see potato_order_by_type): workspace of
  * order_workspace_words(n, n_types) int32 words. */

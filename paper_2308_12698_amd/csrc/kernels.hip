@@ -139,82 +139,91 @@ __device__ __forceinline__ void advance_vehicle(const StepArgs& A, const VehCons
     for (int k = 0; k < 3; ++k) p[k] = x[k];
 }
 
-/* Mixed vehicle kinds in the caller's order: a block sorts a chunk of up
- * to kKindGroup block widths of consecutive agents by kind, stably, from
- * wave ballots and a prefix over the (width, wave) groups' counts.  Each
- * kind starts on a multiple of 64 sorted positions, so that no group of
- * 64 holds two kinds (the gaps hold -1).  The sort key puts the longest
- * step first (aircraft, then quadrotors, then cars), so that the groups
- * handed out last are short.  Afterwards slot[p] is the offset from base
- * of the agent at sorted position p, n_groups the groups of 64 that hold
- * an agent, and `next` (the next group to hand out) is 0.  Contains
- * barriers: every thread of the block calls it with the same arguments. */
-constexpr int kKinds = 3;
-struct KindSort {
-    int32_t count[kKindGroup * 8][kKinds];        /* per (width, wave) group */
-    int32_t first[kKindGroup * 8][kKinds];        /* its first sorted position */
-    int32_t slot[kKindGroup * 512 + kKinds * 64];
-    int32_t n_groups;
-    int32_t next;
+/* Grouping a block's agents by class (a launch with a per-agent type and
+ * no processing order, whose types fall into 2..kMaxGroups classes of equal
+ * step budget and kind).  The block sorts a chunk of up to kGroupWidths
+ * block widths of consecutive agents by class, stably, from wave ballots
+ * and a prefix over the (width, wave) cells' counts.  Each class starts on
+ * a multiple of 64 sorted positions, so that no group of 64 holds two
+ * classes (the gaps hold -1).  Classes are numbered longest step first, so
+ * that the groups handed out last are short. */
+struct GroupLds {
+    int32_t* count;   /* [cells][kMaxGroups] agents of each class per (width, wave) cell */
+    int32_t* first;   /* [cells][kMaxGroups] their first sorted position */
+    int32_t* slot;    /* [kGroupWidths * B + kMaxGroups * 64] offset from base, or -1 */
+    int32_t* misc;    /* [0] groups of 64 that hold an agent, [1] the next one to hand out */
 };
 
-__device__ __forceinline__ int kind_key(int kind) {
-    return kind == KIND_WING ? 0 : kind == KIND_QUAD ? 1 : 2;
+__device__ __forceinline__ GroupLds group_lds(int32_t* area, int B) {
+    const int cells = kGroupWidths * (B / 64) * kMaxGroups;
+    GroupLds L;
+    L.count = area;
+    L.first = area + cells;
+    L.slot = area + 2 * cells;
+    L.misc = L.slot + kGroupWidths * B + kMaxGroups * 64;
+    return L;
 }
 
-__device__ __forceinline__ void group_by_kind(const StepArgs& A, const TypeConst* tab, int64_t base, int64_t end,
-                                              int ch, KindSort& S) {
+/* Sort the chunk [base, end) (ch block widths, ch <= kGroupWidths).
+ * Afterwards slot[p] is the offset from base of the agent at sorted
+ * position p, misc[0] the number of groups of 64 and misc[1] = 0.
+ * Contains barriers: every thread of the block calls it with the same
+ * arguments. */
+__device__ __forceinline__ void group_agents(const StepArgs& A, const TypeConst* tab, int64_t base, int64_t end,
+                                             int ch, const GroupLds& L) {
     const int B = blockDim.x, t = threadIdx.x;
-    const int wave = t >> 6, lane = t & 63, n_waves = (B + 63) >> 6, n_groups = ch * n_waves;
+    const int wave = t >> 6, lane = t & 63, n_waves = B >> 6, n_cells = ch * n_waves, nk = A.n_groups;
     const uint64_t below = (uint64_t(1) << lane) - 1;
-    int key[kKindGroup];
-    uint64_t same[kKindGroup];
+    int key[kGroupWidths];
+    uint64_t same[kGroupWidths];
 #pragma unroll
-    for (int c = 0; c < kKindGroup; ++c) {
-        key[c] = kKinds;                          /* past the end: not placed */
+    for (int c = 0; c < kGroupWidths; ++c) {
+        key[c] = kMaxGroups;                      /* past the end: not placed */
         same[c] = 0;
         if (c < ch) {
             const int64_t j = base + (int64_t)c * B + t;
-            if (j < end) key[c] = kind_key(tab[type_entry(A.type, (uint32_t)j, A.n_types)].kind);
+            if (j < end) key[c] = tab[type_entry(A.type, (uint32_t)j, A.n_types)].group;
+            int32_t* cnt = L.count + (c * n_waves + wave) * kMaxGroups;
 #pragma unroll
-            for (int k = 0; k < kKinds; ++k) {
-                const uint64_t m = __ballot(key[c] == k);
-                if (key[c] == k) same[c] = m;
-                if (lane == 0) S.count[c * n_waves + wave][k] = __popcll(m);
+            for (int k = 0; k < kMaxGroups; ++k) {
+                if (k < nk) {
+                    const uint64_t m = __ballot(key[c] == k);
+                    if (key[c] == k) same[c] = m;
+                    if (lane == 0) cnt[k] = __popcll(m);
+                }
             }
         }
     }
     __syncthreads();
     /* every wave has left the previous chunk's hand-out loop */
-    if (t <= kKinds) {
-        /* key t starts after every smaller key's agents rounded up to 64,
-         * then its (width, wave) groups in order; thread kKinds counts the
-         * groups of 64 */
+    if (t <= nk) {
+        /* class t starts after every smaller class's agents rounded up to
+         * 64, then its cells in order; thread nk counts the groups */
         int32_t run = 0;
         for (int k = 0; k < t; ++k) {
             int32_t total = 0;
-            for (int g = 0; g < n_groups; ++g) total += S.count[g][k];
+            for (int cell = 0; cell < n_cells; ++cell) total += L.count[cell * kMaxGroups + k];
             run += (total + 63) & ~63;
         }
-        if (t < kKinds) {
-            for (int g = 0; g < n_groups; ++g) {
-                S.first[g][t] = run;
-                run += S.count[g][t];
+        if (t < nk) {
+            for (int cell = 0; cell < n_cells; ++cell) {
+                L.first[cell * kMaxGroups + t] = run;
+                run += L.count[cell * kMaxGroups + t];
             }
         } else {
-            S.n_groups = run >> 6;
+            L.misc[0] = run >> 6;
         }
     }
-    if (t == 0) S.next = 0;
-    for (int p = t; p < ch * B + kKinds * 64; p += B) S.slot[p] = -1;
+    if (t == 0) L.misc[1] = 0;
+    for (int p = t; p < ch * B + nk * 64; p += B) L.slot[p] = -1;
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kKindGroup; ++c)
-        if (c < ch && key[c] < kKinds)
-            S.slot[S.first[c * n_waves + wave][key[c]] + __popcll(same[c] & below)] = c * B + t;
+    for (int c = 0; c < kGroupWidths; ++c)
+        if (c < ch && key[c] < nk)
+            L.slot[L.first[(c * n_waves + wave) * kMaxGroups + key[c]] + __popcll(same[c] & below)] = c * B + t;
     __syncthreads();
-    /* the next call writes count, first, n_groups, next and slot only after
-     * a barrier that every thread reaches once it is done with this call's */
+    /* the next call writes these arrays only after a barrier that every
+     * thread reaches once it is done with this call's */
 }
 
 template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY, bool KINDS>
@@ -401,37 +410,45 @@ __global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepA
             for (int k = 0; k < 3; ++k) snap(k) = a.p[k];
         }
     };
-    if constexpr (KINDS && HET && !PERM) {
-        /* cars, aircraft and quadrotors mixed in the caller's order: each
-         * block owns ceil(n / grid) consecutive agents (a multiple of 64)
-         * and steps them in chunks of up to kKindGroup block widths,
-         * grouped by kind, so that a wave's 64 agents are of one kind
-         * instead of running every kind's loop in turn; the block's waves
-         * take the groups in turn, so that they finish together.  An agent's
-         * arithmetic does not depend on its lane, so the results are the
-         * same bits.  The chunk loop's bounds are the same for the whole
-         * block, so every thread reaches the barriers. */
-        __shared__ KindSort sorted;
+    if constexpr (HET && !PERM && !CKPT) {
+        /* a per-agent type in the caller's order: each block owns
+         * ceil(n / grid) consecutive agents (a multiple of 64) and steps
+         * them in groups of 64.  When the types fall into classes (equal
+         * step budget and kind), the groups are sorted by class, chunk by
+         * chunk of up to kGroupWidths block widths, so that a wave's 64
+         * agents take the same number of steps of the same kind's loop
+         * instead of waiting for the longest budget and running every
+         * kind's loop in turn; the block's waves then take the groups in
+         * turn, so that they finish together.  Otherwise wave w steps the
+         * chunk's group w.  An agent's arithmetic does not depend on its
+         * lane, so the results are the same bits either way.  The chunk
+         * loop's bounds and `grouped` are the same for the whole block, so
+         * every thread reaches the barriers. */
+        const bool grouped = A.n_groups >= 2;
+        const GroupLds L = group_lds(reinterpret_cast<int32_t*>(tab + A.n_types), blockDim.x);
         const int64_t B = blockDim.x;
+        const int64_t width = grouped ? kGroupWidths * B : B;
         const int64_t per_block = ((A.n + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
         const int64_t lo = (int64_t)blockIdx.x * per_block;
         const int64_t hi = lo + per_block < A.n ? lo + per_block : A.n;
-        const int lane = threadIdx.x & 63;
-        for (int64_t base = lo; base < hi; base += kKindGroup * B) {
-            const int64_t end = base + kKindGroup * B < hi ? base + kKindGroup * B : hi;
-            group_by_kind(A, tab, base, end, (int)((end - base + B - 1) / B), sorted);
-            /* the sorted groups of 64 go to whichever wave asks first */
-            const int n_groups = sorted.n_groups;
-            for (;;) {
-                int g = 0;
-                if (lane == 0) g = atomicAdd(&sorted.next, 1);
-                g = __builtin_amdgcn_readfirstlane(g);
-                if (g >= n_groups) break;
-                const int32_t off = sorted.slot[g * 64 + lane];
-                if (off >= 0) advance(base + off);
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, n_waves = blockDim.x >> 6;
+        auto take = [&]() {
+            int g = 0;
+            if (lane == 0) g = atomicAdd(&L.misc[1], 1);
+            return __builtin_amdgcn_readfirstlane(g);
+        };
+        for (int64_t base = lo; base < hi; base += width) {
+            const int64_t end = base + width < hi ? base + width : hi;
+            int n_out = (int)((end - base + 63) / 64);
+            if (grouped) {
+                group_agents(A, tab, base, end, (int)((end - base + B - 1) / B), L);
+                n_out = L.misc[0];
             }
-        }
-    } else {
+            for (int g = grouped ? take() : wave; g < n_out; g = grouped ? take() : g + n_waves) {
+                const int32_t off = grouped ? L.slot[g * 64 + lane] : g * 64 + lane;
+                if (off >= 0 && base + off < end) advance(base + off);
+            }
+        }    } else {
         for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.n; j += stride) advance(j);
     }
 
@@ -700,20 +717,24 @@ hipError_t launch_adjoint(bool het, bool gains, bool perm, bool pipe, const AdjA
                            dim3((unsigned)(pipe ? kAdjPipeBlock : kAdjBlock)), args, lds, stream);
 }
 
-size_t rollout_lds_bytes(const Variant& v, int n_types) {
-    return ((sizeof(Limits) + 15) / 16) * 16 + (size_t)(v.het ? n_types : 1) * sizeof(TypeConst);
+bool rollout_grouped(const Variant& v, const StepArgs& a) {
+    return v.het && !v.perm && !v.ckpt && a.n_groups >= 2;
 }
 
-/* Blocks of `block` threads the chip holds at once for kernel fn: the
- * occupancy per compute unit times the compute units of the current
- * device, cached per (device, kernel, block, LDS bytes). */
-static hipError_t kind_fill_blocks(const void* fn, int block, int n_types, const Variant& v, int* out) {
+size_t rollout_lds_bytes(const Variant& v, const StepArgs& a, int block) {
+    return ((sizeof(Limits) + 15) / 16) * 16 + (size_t)(v.het ? a.n_types : 1) * sizeof(TypeConst) +
+           (rollout_grouped(v, a) ? (size_t)group_lds_words(block) * sizeof(int32_t) : 0);
+}
+
+/* Blocks of `block` threads the chip holds at once for kernel fn with lds
+ * bytes of dynamic LDS: the occupancy per compute unit times the compute
+ * units of the current device, cached per (device, kernel, block, lds). */
+static hipError_t fill_blocks(const void* fn, int block, size_t lds, int* out) {
     static std::mutex mu;
     static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    const size_t lds = rollout_lds_bytes(v, n_types);
     const auto key = std::make_tuple(dev, fn, block, lds);
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
@@ -733,19 +754,19 @@ hipError_t launch_rollout(const Variant& v, const StepArgs& a, int block, int gr
                           hipStream_t stream) {
     const void* fn = rollout_kernel(v);
     int64_t grid = grid_blocks > 0 ? grid_blocks : (a.n + block - 1) / block;
-    if (grid_blocks <= 0 && v.kinds && v.het && !v.perm) {
-        /* mixed kinds grouped per block: one round of blocks, as many as
-         * the chip holds at once, so that each sorts chunks as wide as the
+    const size_t lds = rollout_lds_bytes(v, a, block);
+    if (grid_blocks <= 0 && rollout_grouped(v, a)) {
+        /* agents grouped per block: one round of blocks, as many as the
+         * chip holds at once, so that each sorts chunks as wide as the
          * swarm allows */
         int fill = 0;
-        hipError_t e = kind_fill_blocks(fn, block, a.n_types, v, &fill);
+        hipError_t e = fill_blocks(fn, block, lds, &fill);
         if (e != hipSuccess) return e;
         grid = std::min<int64_t>(grid, fill);
     }
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     void* args[] = {const_cast<StepArgs*>(&a)};
-    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)block), args,
-                           rollout_lds_bytes(v, a.n_types), stream);
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)block), args, lds, stream);
 }
 
 hipError_t launch_count_nonfinite(const float* rows, int64_t ld, int64_t n, int n_rows, unsigned long long* count,

@@ -82,9 +82,10 @@ struct TypeConst {
         VehConst veh;
     };
     int32_t budget;
-    int32_t kind;                                 /* 0 quadrotor, 1 car, 2 fixed wing */
+    int16_t kind;                                 /* 0 quadrotor, 1 car, 2 fixed wing */
+    int16_t group;                                /* class for grouping agents within a block */
 };
-static_assert(sizeof(TypeConst) == 44 * 4, "type table entry: 42 constants, budget, kind");
+static_assert(sizeof(TypeConst) == 44 * 4, "type table entry: 42 constants, budget, kind and group");
 
 enum { KIND_QUAD = 0, KIND_CAR = 1, KIND_WING = 2 };
 

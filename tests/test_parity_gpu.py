@@ -374,6 +374,45 @@ def test_types_match_single_type_runs(torch_dev):
         assert_parity(homo, alone, sub, tol=1e-5)
 
 
+def test_grouped_launch_equals_the_type_order(torch_dev):
+    """In the caller's order the eight types (eight step budgets, so eight
+    classes) are grouped within each block; the result equals the
+    type-ordered launch bit for bit, whatever the launch shape (one round of
+    blocks, one block holding several chunks, 64-thread blocks with a few
+    chunks each, a captured graph, one step per launch), also with dead
+    agents, which stay as they were."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config3(scale=300)
+    steps = 2500
+
+    def run(ordered, alive=None, **opts):
+        sim = Simulator(sw.types, sw.glob, mode=1, debug=True, **opts)
+        st = _dev(torch, dev, sw.state)
+        ti = _dev(torch, dev, sw.type_idx)
+        perm = sim.order_by_type(ti) if ordered else None
+        sim.step(st, steps, sw.dt, type_idx=ti, perm=perm, wp=_dev(torch, dev, sw.wp),
+                 resample_every=sw.resample_every, carry=carry_zeros(torch_dev, sw.n),
+                 alive=_dev(torch, dev, alive))
+        torch.cuda.synchronize()
+        out = st.cpu().numpy()
+        sim.close()
+        return out
+
+    print(f"grouped launch: {sw.n} agents, {steps} steps", flush=True)
+    ref = run(True, form="fused", steps_per_launch=500)
+    for opts in (dict(form="fused", steps_per_launch=500),
+                 dict(form="fused", block=512, steps_per_launch=1000, grid_blocks=1),
+                 dict(form="fused", block=64, steps_per_launch=2500, grid_blocks=3),
+                 dict(form="fused", block=128, steps_per_launch=250, use_graph=True),
+                 dict(form="plain")):
+        assert np.array_equal(run(False, **opts), ref), opts
+    alive = (np.arange(sw.n) % 7 != 3).astype(np.uint8)
+    got = run(False, alive, form="fused", steps_per_launch=1000)
+    assert np.array_equal(got, run(True, alive, form="fused", steps_per_launch=1000))
+    assert np.array_equal(got[:, alive == 0], sw.state[:, alive == 0])
+
+
 def test_order_by_type_is_the_stable_budget_order(torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
