@@ -418,12 +418,13 @@ potato_status potato_create(potato_ctx** out, const potato_type_params* types, i
     }
     /* classes of types that take the same steps of the same loop (equal
      * budget and kind), numbered longest first: by budget, then by the
-     * kind's step (measured per agent-step at 1M agents: quadrotor, then
-     * fixed wing, then car).  Launches with a per-agent type and no
-     * processing order group their agents by class within each block when
-     * there are 2..kMaxGroups classes. */
+     * kind's step (measured per agent-step at 1M agents, each kind alone in
+     * the type order: fixed wing 11.0 ps, quadrotor 9.5, car 8.2).
+     * Launches with a per-agent type and no processing order group their
+     * agents by class within each block when there are 2..kMaxGroups
+     * classes. */
     {
-        auto cost = [](int32_t kind) { return kind == KIND_QUAD ? 2 : kind == KIND_WING ? 1 : 0; };
+        auto cost = [](int32_t kind) { return kind == KIND_WING ? 2 : kind == KIND_QUAD ? 1 : 0; };
         std::vector<std::pair<int32_t, int>> cls;
         for (int t = 0; t < n_types; ++t) cls.emplace_back(ctx->consts[t].budget, cost(ctx->consts[t].kind));
         std::sort(cls.begin(), cls.end(), std::greater<std::pair<int32_t, int>>());
