@@ -255,7 +255,6 @@ __device__ __forceinline__ void step_vjp(const TypeConst& c, const Limits& L, co
     const float rq = rsq(qr0 * qr0 + qr1 * qr1 + qr2 * qr2);
     const float qd[3] = {qr0 * rq, qr1 * rq, qr2 * rq};
     const float* q = a.q;
-    const float qew = q[0] * qd[0] + q[1] * qd[1] + q[2] * qd[2];
     const float qex = q[0] * qd[1] - q[1] * qd[0] + q[3] * qd[2];
     const float qey = q[0] * qd[2] - q[2] * qd[0] - q[3] * qd[1];
     const float qez = q[2] * qd[1] - q[1] * qd[2] - q[3] * qd[0];
