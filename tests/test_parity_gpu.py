@@ -413,6 +413,37 @@ def test_grouped_launch_equals_the_type_order(torch_dev):
     assert np.array_equal(got[:, alive == 0], sw.state[:, alive == 0])
 
 
+def test_ungrouped_launch_beyond_eight_classes(oracle, torch_dev):
+    """Twelve types of twelve step budgets (more classes than a block
+    groups): the caller's order runs the launch's plain 64-agent groups,
+    bitwise equal to the type order and within 1e-4 of the oracle."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    types = I.hetero_types(12, seed_stream=5)
+    for t, ty in enumerate(types):
+        ty["budget"] = 100 * (t + 1)
+    r = I.rng(3, 7)
+    n = 2500
+    labels = r.integers(0, 12, n).astype(np.uint8)
+    state = I.hover_state(I._box_positions(r, n))
+    wp = I.f32(I._box_positions(r, n)[None])
+    sw = I.Swarm("twelve", 1, 1e-3, 1200, state, types, I.globals_f32(), type_idx=labels, wp=wp,
+                 resample_every=0)
+    outs = []
+    for ordered in (False, True):
+        sim = Simulator(types, sw.glob, mode=1, steps_per_launch=400, debug=True)
+        st = _dev(torch, dev, state)
+        ti = _dev(torch, dev, labels)
+        sim.step(st, 1200, sw.dt, type_idx=ti, perm=sim.order_by_type(ti) if ordered else None,
+                 wp=_dev(torch, dev, wp), carry=carry_zeros(torch_dev, n))
+        torch.cuda.synchronize()
+        outs.append(st.cpu().numpy())
+        sim.close()
+    assert np.array_equal(outs[0], outs[1])
+    ref = oracle_rollout(oracle, sw, 1200)
+    assert_parity(outs[0].astype(np.float64), ref, sw)
+
+
 def test_order_by_type_is_the_stable_budget_order(torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
