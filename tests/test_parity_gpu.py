@@ -235,7 +235,8 @@ def test_heterogeneous_batch_matches_oracle(oracle, torch_dev):
 def test_heterogeneous_full_size_every_agent(oracle, torch_dev):
     """The full heterogeneous swarm (1,007,616 agents, 8 types) for its
     first 1,000 steps in the type order, one launch: every agent against the
-    oracle (about 1e9 FP64 agent-steps on the host)."""
+    oracle (about 1e9 FP64 agent-steps on the host); the same launch in the
+    caller's order (grouped per block) gives the same bits."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
     sw = I.config3()
@@ -245,7 +246,13 @@ def test_heterogeneous_full_size_every_agent(oracle, torch_dev):
     perm = sim.order_by_type(ti)
     sim.step(st, 1000, sw.dt, type_idx=ti, perm=perm, wp=_dev(torch, dev, sw.wp),
              resample_every=sw.resample_every, carry=carry_zeros(torch_dev, sw.n))
+    # the caller's order: each block groups its agents by budget class
+    su = _dev(torch, dev, sw.state)
+    sim.step(su, 1000, sw.dt, type_idx=ti, wp=_dev(torch, dev, sw.wp), resample_every=sw.resample_every,
+             carry=carry_zeros(torch_dev, sw.n))
     torch.cuda.synchronize()
+    assert torch.equal(st, su)
+    del su
     got = st.cpu().numpy().astype(np.float64)
     sim.close()
     assert np.isfinite(got).all()
