@@ -545,6 +545,10 @@ __global__ void __launch_bounds__(kAdjPipeBlock)
     const Limits& lim = A.lim;
     const int64_t ld = A.ld;
     const bool producer = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
+    /* the reversing wave is the critical path (the recomputing wave waits
+     * for it at every segment barrier): it issues first whenever both are
+     * ready on a SIMD */
+    if (!producer) __builtin_amdgcn_s_setprio(3);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t lb = lane << 2;
     const int64_t tape_step = (int64_t)kTapeRows * 64;
