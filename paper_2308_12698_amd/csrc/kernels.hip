@@ -15,7 +15,10 @@
  *   GAINS per-agent controller gains;
  *   CKPT  checkpoints every ckpt_every steps for the adjoint (always with
  *         CARRY: the adjoint replays the compensated integrator);
- *   PERM  processing order (agents grouped by type);
+ *   PERM  processing order (agents grouped by type); without it, a
+ *         launch whose types fall into 2-8 classes of equal budget and
+ *         kind sorts each block's agents by class in LDS and hands the
+ *         64-agent groups to its waves (group_agents);
  *   CARRY rounding carries of p, v, J and the position-loop integral kept
  *         in the caller's carry rows (without: uncompensated updates);
  *   KINDS the type table also holds cars and fixed-wing aircraft: a lane
