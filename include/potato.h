@@ -164,7 +164,11 @@ typedef struct {
  *          potato_order_by_type).  NULL = identity.  The device reads an
  *          entry outside [0, n_agents) as n_agents - 1: nothing outside the
  *          rows is addressed, but an order that is not a permutation leaves
- *          agents unadvanced and races on others.
+ *          agents unadvanced and races on others.  Without an order, a
+ *          launch whose types fall into 2 to 8 classes of equal step budget
+ *          and kind groups each block's agents by class itself (the same
+ *          results, bit for bit; with more classes, pass the order for
+ *          waves of one budget and kind).
  *   gains  float[9][gains_ld] per-agent gains (NULL: the type's gains).
  *   alive  uint8[n_agents]: agents with 0 are dead and are neither advanced
  *          nor differentiated (their state and cotangent pass through);
