@@ -247,6 +247,20 @@ def test_heterogeneous_budgets_and_dead_agents_through_the_pipe(oracle, torch_de
     torch.cuda.synchronize()
     assert torch.equal(st, ref) and torch.equal(ct, rc)
     assert np.array_equal(snaps.numpy().reshape(-1, 3, n), np.stack(ref_snaps))
+    # the caller's order (each block groups its agents by budget class)
+    # writes the same snapshots and ends in the same state
+    su = torch.from_numpy(sw.state).to(dev)
+    cu = torch.zeros((10, n), dtype=torch.float32, device=dev)
+    snaps_u = torch.full((n_epochs, per, 3, n), -1.0, dtype=torch.float32, pin_memory=True)
+    pipe_u = Pipe(sim, n)
+    for e in range(n_epochs):
+        pipe_u.push(wps[e])
+        pipe_u.run(su, epoch_steps, sw.dt, type_idx=ti, alive=alive, snap_every=snap_every, snaps=snaps_u[e],
+                   carry=cu)
+    pipe_u.sync()
+    pipe_u.close()
+    assert torch.equal(su, st) and torch.equal(cu, ct)
+    assert np.array_equal(snaps_u.numpy(), snaps.numpy())
     dead = alive.cpu().numpy() == 0
     assert np.array_equal(st.cpu().numpy()[:, dead], sw.state[:, dead])
     assert np.array_equal(snaps.numpy()[-1, -1][:, dead], sw.state[0:3, dead])
