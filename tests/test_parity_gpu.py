@@ -420,6 +420,31 @@ def test_grouped_launch_equals_the_type_order(torch_dev):
     assert np.array_equal(got[:, alive == 0], sw.state[:, alive == 0])
 
 
+def test_grouped_launch_with_per_agent_gains(oracle, torch_dev):
+    """Per-agent gains beside three budget classes, in the caller's order:
+    the per-block grouping carries each agent's gains with it (bitwise the
+    type order; within 1e-4 of the oracle)."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    dw = I.config4(n=3000, n_steps=600)
+    types = [dict(t, budget=b) for t, b in zip(I.hetero_types(3, seed_stream=2), (600, 250, 430))]
+    labels = np.random.default_rng(4).integers(0, 3, dw.n).astype(np.uint8)
+    sw = I.Swarm("gains3", 1, dw.dt, 600, dw.state, types, dw.glob, type_idx=labels, gains=dw.gains, wp=dw.wp,
+                 resample_every=0)
+    outs = []
+    for ordered in (False, True):
+        sim = Simulator(types, sw.glob, mode=1, steps_per_launch=200, debug=True)
+        st = _dev(torch, dev, sw.state)
+        ti = _dev(torch, dev, labels)
+        sim.step(st, 600, sw.dt, type_idx=ti, perm=sim.order_by_type(ti) if ordered else None,
+                 gains=_dev(torch, dev, sw.gains), wp=_dev(torch, dev, sw.wp), carry=carry_zeros(torch_dev, sw.n))
+        torch.cuda.synchronize()
+        outs.append(st.cpu().numpy())
+        sim.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert_parity(outs[0].astype(np.float64), oracle_rollout(oracle, sw, 600), sw)
+
+
 def test_ungrouped_launch_beyond_eight_classes(oracle, torch_dev):
     """Twelve types of twelve step budgets (more classes than a block
     groups): the caller's order runs the launch's plain 64-agent groups,
