@@ -57,7 +57,7 @@ BWD_FLOPS_PER_AGENT_STEP = FLOPS_PER_AGENT_STEP + REV_FLOPS_PER_AGENT_STEP   # 3
 # read once per agent-step).
 TAPE_ROWS = 31            # step-start state without J and w_prev (26), held command (4), branch bits (1)
 # Algorithmic HBM bytes per agent of one collision pass (collisions_form).
-COLLISION_BYTES_PER_AGENT = 122
+COLLISION_BYTES_PER_AGENT = 141
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 # The autotuner's results for these workloads on this build (keyed by device,
 # build digest, variant, agent count and probe length): a hit fixes the launch
@@ -404,10 +404,12 @@ def collisions_form(torch, dev, timed, N):
 
     ms = timed(detect, reps=5)
     # algorithmic bytes of a pass: positions and mask read by the bounding
-    # box, the count and the scatter; ranks written and read; the sorted
-    # (x, y, z, r) and ids written once and read once; the mask written; the
-    # bucket counts and starts (about 2.1 buckets per agent) written and read
-    # twice each.  Per agent: 13 + 13 + 4 + 17 + 20 + 20 + 1 + 34 = 122 B.
+    # box, the tile counts and the tile pass (13 B each); the items (x, y, z,
+    # r and id, 20 B) written by the tile pass, read and written by the
+    # window sort and read by the query (80 B); the bucket starts (2.13 per
+    # agent) written by the sort and read by the query (17 B); the tile
+    # counts written, scanned and read (about 4 B); the mask written (1 B).
+    # Per agent: 39 + 80 + 17 + 4 + 1 = 141 B.
     gbs = COLLISION_BYTES_PER_AGENT * N / (ms * 1e-3) / 1e9
     out = {"agents_per_s": N / (ms * 1e-3), "n_agents": N, "ms": ms,
            "died_per_pass": int(died.item()) // 6,

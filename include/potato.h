@@ -328,10 +328,11 @@ potato_status potato_detect_collisions(potato_ctx* ctx, const potato_state* stat
  * cannot allocate device memory (code under hipGraph capture, serving loops
  * with a fixed memory budget, harnesses that forbid hipMalloc).  Same
  * arguments, decisions and errors as potato_detect_collisions, but the
- * pass's scratch memory (bucket counts and starts, the sorted positions) is
- * a static device array of the library, sized for
- * POTATO_NOALLOC_MAX_AGENTS agents (about 40 MiB, held by every GPU the
- * library runs on until the process ends); the call allocates nothing.
+ * pass's scratch memory (the positions in partition and in bucket order,
+ * the bucket starts, the partition offsets) is a static device array of the
+ * library, sized for POTATO_NOALLOC_MAX_AGENTS agents (about 90 MiB, held
+ * by every GPU the library runs on until the process ends); the call
+ * allocates nothing.
  * Errors: POTATO_EINVAL as in potato_detect_collisions, and for
  * n_agents > POTATO_NOALLOC_MAX_AGENTS.  Every call on one GPU shares that
  * GPU's array: calls that overlap on one GPU (other streams, other host

@@ -146,7 +146,6 @@ hipError_t launch_count_nonfinite(const float* rows, int64_t ld, int64_t n, int 
                                   hipStream_t stream);
 
 /* Collision detection on a hashed grid (see collide.hip). */
-uint32_t collision_buckets(int64_t n);
 int64_t collision_workspace_bytes(int64_t n);
 /* Largest swarm of the allocation-free collision entry point. */
 constexpr int64_t kNoAllocMaxAgents = int64_t(1) << 20;

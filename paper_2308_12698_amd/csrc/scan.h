@@ -1,8 +1,9 @@
 /*
  * scan.h -- exclusive prefix sum of int32 counts on the device, in three
  * launches: per-chunk scans with chunk totals, one block scanning the
- * totals, and the totals added back.  Used by the collision pass (bucket
- * starts) and by the type order (per-block output offsets).  Each
+ * totals, and the totals added back.  Used by the collision pass (its
+ * partition offsets, which add the totals where they are read) and by the
+ * type order (per-block output offsets).  Each
  * translation unit that includes it gets its own copy of the kernels.
  */
 #pragma once
@@ -72,6 +73,15 @@ inline void launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t* tota
     hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(kScanBlock), 0, s, in, out, totals, m);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, s, totals, chunks, grand);
     hipLaunchKernelGGL(k_scan_add, dim3(chunks), dim3(kScanBlock), 0, s, out, totals, m);
+}
+
+/* The same without the last launch: the prefix sum of element i is
+ * out[i] + totals[i / kScanBlock], added by the consumer. */
+inline void launch_exclusive_scan_chunks(const int32_t* in, int32_t* out, int32_t* totals, int32_t* grand,
+                                         uint32_t m, hipStream_t s) {
+    const uint32_t chunks = scan_chunks(m);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(kScanBlock), 0, s, in, out, totals, m);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, s, totals, chunks, grand);
 }
 
 }  // namespace

@@ -135,13 +135,23 @@ def test_collision_workspace_size(lib):
     lib.potato_collision_workspace_bytes.restype = C.c_int64
     lib.potato_collision_workspace_bytes.argtypes = [C.c_int64]
     assert lib.potato_collision_workspace_bytes(0) == -1
-    for n, k in ((1000, 11), (1 << 20, 21), (3, 10)):
+    for n, k in ((1000, 11), (1 << 20, 21), (3, 10), ((1 << 24) + 1, 26), ((1 << 30) - 1, 30)):
         # bucket budget 2^k >= 2n (at least 2^10) plus 2 ghost columns per 32
         m = 2 ** k + 2 ** (k + 1 - 5)
-        # sorted (x, y, z, r) and ids of agents and ghosts [2n]; ranks [n] x 2;
-        # count [m]; start [m + 1]; chunk totals; bounding box [6] and its
+        # partitions of 2^s buckets (s >= 12), at most 16,384 of them, cover
+        # the m + 1 bucket starts; tiles of 2,048 agents or a multiple, at
+        # most 2,048 tiles
+        s = 12
+        while math.ceil((m + 1) / 2 ** s) > 16384:
+            s += 1
+        parts = math.ceil((m + 1) / 2 ** s)
+        tile = 2048 * math.ceil(n / (2048 * 2048))
+        cells = parts * math.ceil(n / tile)
+        # items (x, y, z, r) in partition and in bucket order [2n] each; ids
+        # [2n] each; bucket starts [parts * 2^s]; partition-tile offsets
+        # [cells + 1]; chunk totals of their scan; bounding box [6] and its
         # partials over at most 1,024 blocks; per-block counts of the dead
-        expect = 16 * 2 * n + 4 * (2 * n + 2 * n + m + (m + 1) + math.ceil(m / 1024) + 6 + 6 * 1024
+        expect = 16 * 4 * n + 4 * (4 * n + parts * 2 ** s + cells + 1 + math.ceil(cells / 1024) + 6 + 6 * 1024
                                    + math.ceil(n / 256)) + 256
         assert lib.potato_collision_workspace_bytes(n) == expect
 

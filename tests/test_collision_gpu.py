@@ -84,6 +84,25 @@ def test_detection_degenerate_geometry(oracle, torch_dev):
     print(f"degenerate geometry: {ref_died} died", flush=True)
 
 
+def test_detection_dense_cluster(oracle, torch_dev):
+    """5,000 agents at one point among 7,000 spread ones: the cluster's bucket
+    partition holds more items than the sort assembles in LDS, so it takes
+    the two-read placement; the same decisions as the brute-force
+    reference."""
+    rng = np.random.default_rng(5)
+    n = 12000
+    pos = np.empty((3, n))
+    pos[:, :5000] = np.array([[10.0], [10.0], [5.0]])
+    pos[:, 5000:] = rng.uniform(0.0, 1.0, size=(3, n - 5000)) * np.array([[50.0], [50.0], [10.0]])
+    state = I.hover_state(pos.astype(np.float32).astype(np.float64))
+    alive = (rng.random(n) > 0.1).astype(np.uint8)
+    t = I.base_type()
+    got, died = gpu_detect(torch_dev, state, [t], alive)
+    ref, ref_died = oracle.detect_collisions(state, [t["radius"]], alive)
+    assert np.array_equal(got, ref) and died == ref_died
+    assert not got[:5000].any()
+
+
 def test_detection_with_type_radii(oracle, torch_dev):
     n = 15000
     state = dense_swarm(n, (25, 25, 5), seed=7)
@@ -106,6 +125,60 @@ def test_detection_full_size_sampled(oracle, torch_dev):
     hit = oracle.collides(sw.state, [sw.types[0]["radius"]], alive, q)
     assert np.array_equal(got[q] == 0, hit == 1)
     assert died == int((got == 0).sum()) > 0
+
+
+def test_detection_two_sort_windows_per_partition(oracle, torch_dev):
+    """16,777,217 agents at the scale swarm's density: the sort's bucket
+    partitions then hold two windows of 4,096 buckets each (one window per
+    partition would take more than 16,384 partitions).  Every decision of a
+    sample of 512 agents, each against all others, and of the first and
+    last agent."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    n = (1 << 24) + 1
+    rng = np.random.default_rng(24)
+    pos = rng.random((3, n), dtype=np.float32) * np.array([[400.0], [400.0], [20.0]], np.float32)
+    t = I.base_type()
+    sim = Simulator([t], I.globals_f32(), mode=1)
+    st = torch.zeros((30, n), dtype=torch.float32, device=dev)
+    st[:3] = torch.from_numpy(pos).to(dev)
+    a = torch.ones(n, dtype=torch.uint8, device=dev)
+    died = torch.zeros(1, dtype=torch.int64, device=dev)
+    sim.detect_collisions(st, a, died=died)
+    torch.cuda.synchronize()
+    got = a.cpu().numpy()
+    sim.close()
+    del st
+    q = np.concatenate([[0, n - 1], rng.choice(n, 512, replace=False)])
+    hit = oracle.collides(pos, [t["radius"]], np.ones(n, np.uint8), q)
+    assert np.array_equal(got[q] == 0, hit == 1)
+    assert died.item() == int((got == 0).sum()) > 0 and hit.any() and not hit.all()
+    print(f"collisions n={n}: {died.item()} died", flush=True)
+
+
+def test_died_accumulates_over_calls_on_one_workspace(oracle, torch_dev):
+    """Three passes over one workspace that starts filled with 0xff bytes:
+    each pass adds its own count of dead agents to ``died`` and matches the
+    reference."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    n = 20000
+    state = dense_swarm(n, (20, 20, 5), seed=11)
+    t = I.base_type()
+    sim = Simulator([t], I.globals_f32(), mode=1)
+    st = torch.from_numpy(state).to(dev)
+    ws = torch.full((int(sim._lib.potato_collision_workspace_bytes(n)),), 255, dtype=torch.uint8, device=dev)
+    died = torch.zeros(1, dtype=torch.int64, device=dev)
+    total = 0
+    for seed in range(3):
+        alive = (np.random.default_rng(seed).random(n) > 0.3).astype(np.uint8)
+        a = torch.from_numpy(alive).to(dev)
+        sim.detect_collisions(st, a, died=died, workspace=ws)
+        ref, ref_died = oracle.detect_collisions(state, [t["radius"]], alive)
+        assert np.array_equal(a.cpu().numpy(), ref)
+        total += ref_died
+        assert died.item() == total > 0
+    sim.close()
 
 
 def test_second_pass_is_a_fixed_point(torch_dev):
