@@ -287,7 +287,10 @@ class Simulator:
         if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=grad_final.device)
         gx0 = torch.empty((30, ld), dtype=torch.float32, device=grad_final.device)
-        gg = torch.zeros((9, ld), dtype=torch.float32, device=grad_final.device) if want_gains else None
+        # the kernel writes every agent's gain cotangent (zero for dead
+        # agents); only columns past n_agents need the fill
+        alloc = torch.empty if n == ld else torch.zeros
+        gg = alloc((9, ld), dtype=torch.float32, device=grad_final.device) if want_gains else None
         L.check(self._lib.potato_step_backward(self._h, C.byref(pp), C.byref(cm), float(dt), n,
                                                int(n_steps), _ptr(ckpt), int(ckpt_every), ld,
                                                _ptr(grad_final), _ptr(gx0), _ptr(gx0[17:]), _ptr(gg),
