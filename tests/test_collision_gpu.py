@@ -103,6 +103,31 @@ def test_detection_dense_cluster(oracle, torch_dev):
     assert not got[:5000].any()
 
 
+def test_detection_thin_line(oracle, torch_dev):
+    """6,000 agents along a 1 km line of cells: two per cell, at opposite
+    corners of its y-z section, one cell apart along x with +-5 cm of
+    jitter, so neighbours along the line collide or not by the jitter.  The
+    grid then has one y row and one z layer (the 9 row ranges of every
+    query coincide), and one bucket partition holds more items than the sort
+    assembles in LDS, spread over 3,000 buckets.  The same decisions as the
+    brute-force reference."""
+    rng = np.random.default_rng(6)
+    t = I.base_type()
+    h = np.float32(2.02) * np.float32(t["radius"])          # cell edge
+    n = 6000
+    cells = np.repeat(np.arange(n // 2), 2)
+    pos = np.empty((3, n))
+    pos[0] = (cells + 0.5) * h + rng.uniform(-0.05, 0.05, n)
+    pos[1] = np.where(np.arange(n) % 2 == 0, 8.05, 8.95) * h
+    pos[2] = np.where(np.arange(n) % 2 == 0, 20.05, 20.95) * h
+    state = I.hover_state(pos.astype(np.float32).astype(np.float64))
+    alive = (rng.random(n) > 0.05).astype(np.uint8)
+    got, died = gpu_detect(torch_dev, state, [t], alive)
+    ref, ref_died = oracle.detect_collisions(state, [t["radius"]], alive)
+    assert np.array_equal(got, ref) and died == ref_died
+    assert 0 < died < int(alive.sum())
+
+
 def test_detection_with_type_radii(oracle, torch_dev):
     n = 15000
     state = dense_swarm(n, (25, 25, 5), seed=7)
