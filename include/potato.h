@@ -139,7 +139,7 @@ typedef struct {
 typedef struct {
     int32_t mode;              /* POTATO_OPEN_LOOP or POTATO_CLOSED_LOOP */
     int32_t form;              /* POTATO_FORM_* */
-    int32_t block;             /* threads per block: 64, 128, 256, 512 or 0 */
+    int32_t block;             /* threads per block: 64, 128, 256, 512, 1024 or 0 */
     int32_t steps_per_launch;  /* fused form, >= 1 or 0 */
     int32_t grid_blocks;       /* fused form: blocks in the grid-stride loop, 0 = one agent per thread */
     int32_t use_graph;
@@ -242,7 +242,7 @@ potato_status potato_step(potato_ctx* ctx, const potato_state* state, const pota
                           float* ckpt, int32_t ckpt_every, void* stream);
 
 /*
- * Time the fused form over a grid of (block in {64, 128, 256, 512}, steps
+ * Time the fused form over a grid of (block in {64, 128, 256, 512, 1024}, steps
  * per launch in {25, 50, 100, 200, 500, 1000} up to probe_steps, grid of one
  * agent per thread or 1x / 2x the resident blocks) on a scratch copy of the
  * given inputs (the caller's buffers are not modified), store the fastest on

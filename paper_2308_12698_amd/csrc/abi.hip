@@ -228,8 +228,8 @@ potato_status check_options(const potato_options& o) {
         return fail(POTATO_EINVAL, "options.mode must be 0 (open loop) or 1 (closed loop)");
     if (o.form < POTATO_FORM_AUTO || o.form > POTATO_FORM_FUSED)
         return fail(POTATO_EINVAL, "options.form must be 0, 1 or 2");
-    if (!(o.block == 0 || o.block == 64 || o.block == 128 || o.block == 256 || o.block == 512))
-        return fail(POTATO_EINVAL, "options.block must be 0, 64, 128, 256 or 512");
+    if (!(o.block == 0 || o.block == 64 || o.block == 128 || o.block == 256 || o.block == 512 || o.block == 1024))
+        return fail(POTATO_EINVAL, "options.block must be 0, 64, 128, 256, 512 or 1024");
     if (o.steps_per_launch < 0 || o.grid_blocks < 0)
         return fail(POTATO_EINVAL, "options.steps_per_launch and grid_blocks must be >= 0");
     return POTATO_OK;
@@ -311,8 +311,9 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
     const potato_options& o = ctx->opts;
     /* agents grouped per block: the widest blocks measured best (mixed
      * kinds at 1M agents, 512 threads: 9.3e10 agent-steps/s against 8.2e10
-     * with 256 and 7.0e10 with 128) */
-    Tuned t{rollout_grouped(P.v, P.a) ? 512 : 256, 100, 0};
+     * with 256 and 7.0e10 with 128): more agents per block fill the groups
+     * of rare classes, and more waves share out the groups more evenly */
+    Tuned t{rollout_grouped(P.v, P.a) ? 1024 : 256, 100, 0};
     auto it = ctx->tuned.find(TuneKey{P.v.mode, P.v.het, P.v.gains, P.v.perm});
     if (it != ctx->tuned.end()) t = it->second;
     if (o.form == POTATO_FORM_PLAIN) {
@@ -551,7 +552,7 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
     Tuned win{256, 100, 0};
     struct Cand { Tuned t; double ms; };
     std::vector<Cand> cands;
-    const int blocks[] = {64, 128, 256, 512};
+    const int blocks[] = {64, 128, 256, 512, 1024};
     /* steps per launch: the candidates up to probe_steps (at least one) */
     std::vector<int> steps_opts;
     for (int S : {25, 50, 100, 200, 500, 1000})

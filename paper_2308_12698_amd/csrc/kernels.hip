@@ -230,7 +230,7 @@ __device__ __forceinline__ void group_agents(const StepArgs& A, const TypeConst*
 }
 
 template <int MODE, bool HET, bool GAINS, bool CKPT, bool PERM, bool CARRY, bool KINDS>
-__global__ void __launch_bounds__(512) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
+__global__ void __launch_bounds__(1024) POTATO_ROLLOUT_ATTR k_rollout(const StepArgs A) {
     static_assert(!(KINDS && CKPT), "checkpoints (the adjoint) cover quadrotors only");
     static_assert(CARRY || !CKPT, "checkpoints hold the carries");
     extern __shared__ float4 lds_raw[];

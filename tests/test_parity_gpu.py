@@ -385,8 +385,9 @@ def test_grouped_launch_equals_the_type_order(torch_dev):
     """In the caller's order the eight types (eight step budgets, so eight
     classes) are grouped within each block; the result equals the
     type-ordered launch bit for bit, whatever the launch shape (one round of
-    blocks, one block holding several chunks, 64-thread blocks with a few
-    chunks each, a captured graph, one step per launch), also with dead
+    blocks, one block holding several chunks, two 1024-thread blocks,
+    64-thread blocks with a few chunks each, a captured graph, one step per
+    launch), also with dead
     agents, which stay as they were."""
     torch, dev = torch_dev
     from paper_2308_12698_amd.sim import Simulator
@@ -410,6 +411,7 @@ def test_grouped_launch_equals_the_type_order(torch_dev):
     ref = run(True, form="fused", steps_per_launch=500)
     for opts in (dict(form="fused", steps_per_launch=500),
                  dict(form="fused", block=512, steps_per_launch=1000, grid_blocks=1),
+                 dict(form="fused", block=1024, steps_per_launch=1000, grid_blocks=2),
                  dict(form="fused", block=64, steps_per_launch=2500, grid_blocks=3),
                  dict(form="fused", block=128, steps_per_launch=250, use_graph=True),
                  dict(form="plain")):
