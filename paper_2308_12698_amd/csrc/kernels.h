@@ -100,7 +100,7 @@ constexpr int kGroupWidths = 4;
 constexpr int kMaxGroups = 8;
 __host__ __device__ constexpr int64_t group_lds_words(int block) {
     return 2 * (int64_t)kGroupWidths * (block / 64) * kMaxGroups + (int64_t)kGroupWidths * block +
-           kMaxGroups * 64 + 2;
+           kMaxGroups * 64 + 2 * ((int64_t)kGroupWidths * (block / 64) + kMaxGroups) + 4 * kMaxGroups + 2;
 }
 
 /* Launch one rollout kernel (n_steps of args) on `stream`. */

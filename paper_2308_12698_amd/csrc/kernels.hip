@@ -146,32 +146,43 @@ __device__ __forceinline__ void advance_vehicle(const StepArgs& A, const VehCons
  * no processing order, whose types fall into 2..kMaxGroups classes of equal
  * step budget and kind).  The block sorts a chunk of up to kGroupWidths
  * block widths of consecutive agents by class, stably, from wave ballots
- * and a prefix over the (width, wave) cells' counts.  Each class starts on
- * a multiple of 64 sorted positions, so that no group of 64 holds two
- * classes (the gaps hold -1).  Classes are numbered longest step first, so
- * that the groups handed out last are short. */
+ * and a prefix over the (width, wave) cells' counts.  Each class's agents
+ * fill whole groups of 64 first; what is left of each class (fewer than 64)
+ * is packed with the leftovers of the other classes of its kind, longest
+ * budget first, so that a group never holds two kinds (the gaps hold -1)
+ * and a rare class does not cost a whole group of its own.  Classes are
+ * numbered longest step first, and the groups are handed out in the order
+ * of the class of their first agent, so that the groups handed out last are
+ * short. */
 struct GroupLds {
     int32_t* count;   /* [cells][kMaxGroups] agents of each class per (width, wave) cell */
-    int32_t* first;   /* [cells][kMaxGroups] their first sorted position */
+    int32_t* first;   /* [cells][kMaxGroups] rank in its class of the cell's first agent */
     int32_t* slot;    /* [kGroupWidths * B + kMaxGroups * 64] offset from base, or -1 */
+    int32_t* order;   /* [kGroupWidths * B / 64 + kMaxGroups] groups in hand-out order */
+    int32_t* head;    /* [kGroupWidths * B / 64 + kMaxGroups] class of each group's first agent */
+    int32_t* cls;     /* [kMaxGroups][4] class total, kind, start of its whole groups, of its leftover */
     int32_t* misc;    /* [0] groups of 64 that hold an agent, [1] the next one to hand out */
 };
 
 __device__ __forceinline__ GroupLds group_lds(int32_t* area, int B) {
     const int cells = kGroupWidths * (B / 64) * kMaxGroups;
+    const int groups = kGroupWidths * (B / 64) + kMaxGroups;
     GroupLds L;
     L.count = area;
     L.first = area + cells;
     L.slot = area + 2 * cells;
-    L.misc = L.slot + kGroupWidths * B + kMaxGroups * 64;
+    L.order = L.slot + kGroupWidths * B + kMaxGroups * 64;
+    L.head = L.order + groups;
+    L.cls = L.head + groups;
+    L.misc = L.cls + 4 * kMaxGroups;
     return L;
 }
 
 /* Sort the chunk [base, end) (ch block widths, ch <= kGroupWidths).
  * Afterwards slot[p] is the offset from base of the agent at sorted
- * position p, misc[0] the number of groups of 64 and misc[1] = 0.
- * Contains barriers: every thread of the block calls it with the same
- * arguments. */
+ * position p, order[] the groups of 64 in hand-out order, misc[0] their
+ * number and misc[1] = 0.  Contains barriers: every thread of the block
+ * calls it with the same arguments. */
 __device__ __forceinline__ void group_agents(const StepArgs& A, const TypeConst* tab, int64_t base, int64_t end,
                                              int ch, const GroupLds& L) {
     const int B = blockDim.x, t = threadIdx.x;
@@ -198,32 +209,77 @@ __device__ __forceinline__ void group_agents(const StepArgs& A, const TypeConst*
         }
     }
     __syncthreads();
-    /* every wave has left the previous chunk's hand-out loop */
-    if (t <= nk) {
-        /* class t starts after every smaller class's agents rounded up to
-         * 64, then its cells in order; thread nk counts the groups */
+    /* every wave has left the previous chunk's hand-out loop.  Class t: its
+     * cells' ranks within the class, its total and its kind */
+    if (t < nk) {
         int32_t run = 0;
-        for (int k = 0; k < t; ++k) {
-            int32_t total = 0;
-            for (int cell = 0; cell < n_cells; ++cell) total += L.count[cell * kMaxGroups + k];
-            run += (total + 63) & ~63;
+        for (int cell = 0; cell < n_cells; ++cell) {
+            L.first[cell * kMaxGroups + t] = run;
+            run += L.count[cell * kMaxGroups + t];
         }
-        if (t < nk) {
-            for (int cell = 0; cell < n_cells; ++cell) {
-                L.first[cell * kMaxGroups + t] = run;
-                run += L.count[cell * kMaxGroups + t];
-            }
-        } else {
-            L.misc[0] = run >> 6;
-        }
+        int kind = 0;
+        for (int ty = 0; ty < A.n_types; ++ty)
+            if (tab[ty].group == t) kind = tab[ty].kind;
+        L.cls[4 * t + 0] = run;
+        L.cls[4 * t + 1] = kind;
     }
     if (t == 0) L.misc[1] = 0;
     for (int p = t; p < ch * B + nk * 64; p += B) L.slot[p] = -1;
     __syncthreads();
+    if (t == 0) {
+        /* whole groups class by class, then the leftovers kind by kind
+         * (kinds in the order of their longest class), each kind's run
+         * rounded up to 64 */
+        int32_t pos = 0;
+        for (int k = 0; k < nk; ++k) {
+            L.cls[4 * k + 2] = pos;
+            pos += L.cls[4 * k] & ~63;
+        }
+        uint32_t placed = 0;
+        for (int k0 = 0; k0 < nk; ++k0) {
+            if (placed >> k0 & 1u) continue;
+            const int kind = L.cls[4 * k0 + 1];
+            for (int k = k0; k < nk; ++k) {
+                if (L.cls[4 * k + 1] != kind) continue;
+                placed |= 1u << k;
+                L.cls[4 * k + 3] = pos;
+                pos += L.cls[4 * k] & 63;
+            }
+            pos = (pos + 63) & ~63;
+        }
+        L.misc[0] = pos >> 6;
+    }
+    __syncthreads();
+    const int n_out = L.misc[0];
+    /* each group's first agent's class (a group never starts in a gap) */
+    for (int g = t; g < n_out; g += B) {
+        const int32_t p0 = g * 64;
+        int h = 0;
+        for (int k = 0; k < nk; ++k) {
+            const int32_t total = L.cls[4 * k], whole = L.cls[4 * k + 2], left = L.cls[4 * k + 3];
+            if ((p0 >= whole && p0 < whole + (total & ~63)) || (p0 >= left && p0 < left + (total & 63))) h = k;
+        }
+        L.head[g] = h;
+    }
 #pragma unroll
     for (int c = 0; c < kGroupWidths; ++c)
-        if (c < ch && key[c] < nk)
-            L.slot[L.first[(c * n_waves + wave) * kMaxGroups + key[c]] + __popcll(same[c] & below)] = c * B + t;
+        if (c < ch && key[c] < nk) {
+            const int k = key[c];
+            const int32_t q = L.first[(c * n_waves + wave) * kMaxGroups + k] + __popcll(same[c] & below);
+            const int32_t whole = L.cls[4 * k] & ~63;
+            L.slot[q < whole ? L.cls[4 * k + 2] + q : L.cls[4 * k + 3] + (q - whole)] = c * B + t;
+        }
+    __syncthreads();
+    /* hand-out order: by the class of the first agent, then by position */
+    for (int g = t; g < n_out; g += B) {
+        const int h = L.head[g];
+        int r = 0;
+        for (int u = 0; u < n_out; ++u) {
+            const int hu = L.head[u];
+            r += (hu < h || (hu == h && u < g)) ? 1 : 0;
+        }
+        L.order[r] = g;
+    }
     __syncthreads();
     /* the next call writes these arrays only after a barrier that every
      * thread reaches once it is done with this call's */
@@ -448,7 +504,7 @@ __global__ void __launch_bounds__(1024) POTATO_ROLLOUT_ATTR k_rollout(const Step
                 n_out = L.misc[0];
             }
             for (int g = grouped ? take() : wave; g < n_out; g = grouped ? take() : g + n_waves) {
-                const int32_t off = grouped ? L.slot[g * 64 + lane] : g * 64 + lane;
+                const int32_t off = grouped ? L.slot[L.order[g] * 64 + lane] : g * 64 + lane;
                 if (off >= 0 && base + off < end) advance(base + off);
             }
         }    } else {
