@@ -438,8 +438,10 @@ def fwd_bwd_form(torch, dev, timed, N):
         carry = torch.zeros((10, dw.n), dtype=torch.float32, device=dev)
         gains = torch.from_numpy(dw.gains).to(dev)
         dwp = torch.from_numpy(dw.wp).to(dev)
-        # the forward's launch shape is the autotuner's, as for the other forms
-        tuned = dsim.autotune(x0, dw.dt, dw.n_steps, gains=gains, wp=dwp, carry=carry, cache=LAUNCH_SHAPES)
+        # the forward's launch shape is the autotuner's, as for the other
+        # forms, timed on the checkpointing variant that this forward runs
+        tuned = dsim.autotune(x0, dw.dt, dw.n_steps, gains=gains, wp=dwp, carry=carry, ckpt_every=K,
+                              cache=LAUNCH_SHAPES)
         dsim.set_options(form="fused", **tuned)
         tgt = torch.from_numpy(dw.extra["target"]).to(dev)
         ckpt = torch.empty((dw.n_steps // K, 40, dw.n), device=dev)

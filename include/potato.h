@@ -246,13 +246,18 @@ potato_status potato_step(potato_ctx* ctx, const potato_state* state, const pota
  * per launch in {25, 50, 100, 200, 500, 1000} up to probe_steps, grid of one
  * agent per thread or 1x / 2x the resident blocks) on a scratch copy of the
  * given inputs (the caller's buffers are not modified), store the fastest on
- * the context for this mode and type layout, and return it in *best (may be
- * NULL).  probe_steps is the number of time steps per timed trial.  Allocates scratch memory for the
- * duration of the call and synchronises `stream`.
+ * the context for this mode, type layout and checkpointing, and return it
+ * in *best (may be NULL).  probe_steps is the number of time steps per
+ * timed trial.  ckpt_every > 0 times the variant that writes checkpoints
+ * every ckpt_every steps (into scratch memory), which potato_step runs when
+ * given a checkpoint buffer; its result applies to such calls, 0 times and
+ * tunes the variant without.  Errors as potato_step with the same
+ * arguments; POTATO_EINVAL for ckpt_every < 0.  Allocates scratch memory
+ * for the duration of the call and synchronises `stream`.
  */
 potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                               const potato_cmds* cmds, float dt, int64_t n_agents, int32_t probe_steps,
-                              potato_options* best, void* stream);
+                              int32_t ckpt_every, potato_options* best, void* stream);
 
 /*
  * Build a processing order for heterogeneous batches: perm (device

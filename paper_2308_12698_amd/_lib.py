@@ -83,7 +83,7 @@ def load():
     L.potato_destroy.argtypes = [P]
     L.potato_set_options.argtypes = [P, P]
     L.potato_step.argtypes = [P, P, P, P, F, I64, I32, P, I32, P]
-    L.potato_autotune.argtypes = [P, P, P, P, F, I64, I32, P, P]
+    L.potato_autotune.argtypes = [P, P, P, P, F, I64, I32, I32, P, P]
     L.potato_order_workspace_bytes.argtypes = [I64, I32]
     L.potato_order_workspace_bytes.restype = I64
     L.potato_order_by_type.argtypes = [P, P, I64, P, P, I64, P]

@@ -45,9 +45,9 @@ potato_status hip_fail(hipError_t e, const char* where) {
 bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
 
 struct TuneKey {
-    int mode, het, gains, perm;
+    int mode, het, gains, perm, ckpt;
     bool operator<(const TuneKey& o) const {
-        return std::tie(mode, het, gains, perm) < std::tie(o.mode, o.het, o.gains, o.perm);
+        return std::tie(mode, het, gains, perm, ckpt) < std::tie(o.mode, o.het, o.gains, o.perm, o.ckpt);
     }
 };
 struct Tuned { int block, steps, grid; };
@@ -314,7 +314,7 @@ Plan make_plan(potato_ctx* ctx, const potato_state* st, const potato_params* pp,
      * with 256 and 7.0e10 with 128): more agents per block fill the groups
      * of rare classes, and more waves share out the groups more evenly */
     Tuned t{rollout_grouped(P.v, P.a) ? 1024 : 256, 100, 0};
-    auto it = ctx->tuned.find(TuneKey{P.v.mode, P.v.het, P.v.gains, P.v.perm});
+    auto it = ctx->tuned.find(TuneKey{P.v.mode, P.v.het, P.v.gains, P.v.perm, P.v.ckpt});
     if (it != ctx->tuned.end()) t = it->second;
     if (o.form == POTATO_FORM_PLAIN) {
         /* one step per launch is HBM bound: 128-thread blocks measured best
@@ -527,18 +527,26 @@ potato_status potato_step(potato_ctx* ctx, const potato_state* state, const pota
 
 potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const potato_params* params,
                               const potato_cmds* cmds, float dt, int64_t n_agents, int32_t probe_steps,
-                              potato_options* best, void* stream) {
+                              int32_t ckpt_every, potato_options* best, void* stream) {
     ApiRange range("potato_autotune");
-    potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, probe_steps, nullptr, 0);
+    if (ckpt_every < 0) return fail(POTATO_EINVAL, "ckpt_every must be >= 0");
+    /* validation only asks whether checkpoints are written (any non-null
+     * pointer stands for the scratch buffer allocated below) */
+    potato_status s = validate_step(ctx, state, params, cmds, dt, n_agents, probe_steps,
+                                    ckpt_every > 0 ? state->rows : nullptr, ckpt_every);
     if (s != POTATO_OK) return s;
     if (probe_steps < 1) return fail(POTATO_EINVAL, "probe_steps must be >= 1");
     std::lock_guard<std::mutex> g(ctx->mu);
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    /* scratch copy of the state rows and, if given, of the carries */
+    /* scratch copy of the state rows and, if given, of the carries; with
+     * ckpt_every, checkpoint slots for probe_steps steps */
     const size_t bytes = sizeof(float) * kRows * (size_t)state->ld;
     const size_t cbytes = state->carry ? sizeof(float) * kCarryRows * (size_t)state->carry_ld : 0;
+    const size_t kbytes = ckpt_every > 0 ? sizeof(float) * kCkptRows * (size_t)state->ld *
+                                               (size_t)((probe_steps + ckpt_every - 1) / ckpt_every)
+                                         : 0;
     float* scratch = nullptr;
-    hipError_t e = hipMalloc(&scratch, bytes + cbytes);
+    hipError_t e = hipMalloc(&scratch, bytes + cbytes + kbytes);
     if (e != hipSuccess) return fail(POTATO_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
     e = hipMemcpyAsync(scratch, state->rows, bytes, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess && cbytes)
@@ -547,6 +555,7 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
     if (e == hipSuccess) e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     potato_state ss{scratch, state->ld, state->carry ? scratch + kRows * state->ld : nullptr, state->carry_ld};
+    float* ckpt_scratch = ckpt_every > 0 ? scratch + (bytes + cbytes) / sizeof(float) : nullptr;
     int n_cu = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
     Tuned win{256, 100, 0};
@@ -561,7 +570,7 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
     ctx->opts.form = POTATO_FORM_FUSED;
     /* probe_steps steps with one shape, after one untimed launch of it */
     auto probe = [&](const Tuned& t, double& ms_out) -> hipError_t {
-        Plan P = make_plan(ctx, &ss, params, cmds, dt, n_agents, nullptr, 0);
+        Plan P = make_plan(ctx, &ss, params, cmds, dt, n_agents, ckpt_scratch, ckpt_every);
         P.block = t.block; P.steps = t.steps; P.grid = t.grid;
         hipError_t pe = enqueue(P, P.steps, hs);
         if (pe == hipSuccess) pe = hipEventRecord(t0, hs);
@@ -573,9 +582,17 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
         ms_out = ms;
         return pe;
     };
+    /* the engine clock ramps up over the first launches of a busy GPU (2.0
+     * to 2.4 GHz over some tens of milliseconds at 1M agents): three untimed
+     * trials of a middle shape first, so that the candidates are timed at
+     * the clock they will run at */
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+        double ms = 0.0;
+        e = probe(Tuned{256, steps_opts.back(), 0}, ms);
+    }
     for (int b : blocks) {
         if (e != hipSuccess) break;
-        Plan P = make_plan(ctx, &ss, params, cmds, dt, n_agents, nullptr, 0);
+        Plan P = make_plan(ctx, &ss, params, cmds, dt, n_agents, ckpt_scratch, ckpt_every);
         int per_cu = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rollout_kernel(P.v), b,
                                                          rollout_lds_bytes(P.v, P.a, b));
@@ -623,7 +640,7 @@ potato_status potato_autotune(potato_ctx* ctx, const potato_state* state, const 
     if (e != hipSuccess) return hip_fail(e, "potato_autotune");
     const bool het = params->type != nullptr;
     ctx->tuned[TuneKey{ctx->opts.mode, het, ctx->opts.mode == 1 && params->gains != nullptr,
-                       het && params->perm != nullptr}] = win;
+                       het && params->perm != nullptr, ckpt_every > 0}] = win;
     drop_graphs(ctx);
     if (best) {
         *best = ctx->opts;

@@ -223,8 +223,10 @@ class Simulator:
 
     def autotune(self, state, dt, probe_steps=200, *, n_agents=None, type_idx=None, perm=None,
                  gains=None, motor_cmd=None, wp=None, resample_every=0, step0=0, carry=None,
-                 stream=None, cache=None):
+                 ckpt_every=0, stream=None, cache=None):
         """Time the fused form's launch shapes on a scratch copy; keep the best.
+        ``ckpt_every`` > 0 tunes the variant that writes checkpoints (the
+        forward of step_backward's rollouts).
 
         ``cache`` (default: the POTATO_AUTOTUNE_CACHE environment variable) is
         a JSON file of earlier results, keyed by device, build (build_digest),
@@ -239,7 +241,7 @@ class Simulator:
             self.tuned_from_cache = False
             best = L.Options()
             L.check(self._lib.potato_autotune(self._h, C.byref(st), C.byref(pp), C.byref(cm),
-                                              float(dt), n, int(probe_steps), C.byref(best),
+                                              float(dt), n, int(probe_steps), int(ckpt_every), C.byref(best),
                                               _stream_handle(stream)))
             return dict(block=best.block, steps_per_launch=best.steps_per_launch,
                         grid_blocks=best.grid_blocks)
@@ -251,7 +253,7 @@ class Simulator:
         key = "|".join(str(x) for x in (
             getattr(props, "gcnArchName", props.name), build_digest(), self.mode, self.n_types,
             type_idx is not None, gains is not None, perm is not None, carry is not None, n,
-            int(probe_steps)))
+            int(probe_steps)) + ((f"ckpt{int(ckpt_every)}",) if ckpt_every else ()))
         return autotune_cached(path, key, run)
 
     def step_backward(self, ckpt, ckpt_every, n_steps, dt, grad_final, *, n_agents=None,

@@ -78,7 +78,7 @@ int main() {
     expect(potato_destroy(nullptr) == POTATO_OK, "destroy null");
     expect(potato_set_options(nullptr, &opt) == POTATO_EINVAL, "set_options null");
     expect(potato_step(nullptr, &st, &pp, &cm, 1e-3f, 10, 1, nullptr, 0, nullptr) == POTATO_EINVAL, "step null");
-    expect(potato_autotune(nullptr, &st, &pp, &cm, 1e-3f, 10, 10, nullptr, nullptr) == POTATO_EINVAL, "autotune null");
+    expect(potato_autotune(nullptr, &st, &pp, &cm, 1e-3f, 10, 10, 0, nullptr, nullptr) == POTATO_EINVAL, "autotune null");
     expect(potato_order_workspace_bytes(0, 8) == -1 && potato_order_workspace_bytes(10, 0) == -1, "order workspace");
     expect(potato_order_workspace_bytes(1000, 8) > 0, "order workspace size");
     expect(potato_order_by_type(nullptr, nullptr, 10, nullptr, nullptr, 0, nullptr) == POTATO_EINVAL, "order null");

@@ -110,7 +110,7 @@ def test_step_rejects_null_context(lib):
     cm = L.Cmds(None, None, 0, 0, 10, 0)
     assert lib.potato_step(None, C.byref(st), C.byref(pp), C.byref(cm), 1e-3, 10, 10, None, 0,
                            None) == L.EINVAL
-    assert lib.potato_autotune(None, C.byref(st), C.byref(pp), C.byref(cm), 1e-3, 10, 10, None,
+    assert lib.potato_autotune(None, C.byref(st), C.byref(pp), C.byref(cm), 1e-3, 10, 10, 0, None,
                                None) == L.EINVAL
     assert lib.potato_destroy(None) == L.OK
 

@@ -163,6 +163,39 @@ def test_checkpoint_interval_does_not_change_the_gradient(torch_dev):
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 
 
+def test_autotune_of_the_checkpointing_forward(torch_dev):
+    """autotune(ckpt_every=K) times the variant that writes checkpoints, on
+    scratch memory (the caller's state and carries are untouched), and the
+    tuned shape then serves checkpointing calls: their checkpoints, final
+    state and gradients equal those of an untuned run bit for bit."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd.sim import Simulator
+    sw = I.config4(n=3000, n_steps=200)
+    K = 50
+    gains = torch.from_numpy(sw.gains).to(dev)
+    wp = torch.from_numpy(sw.wp).to(dev)
+    lam = torch.from_numpy(np.random.default_rng(2).normal(size=(30, sw.n)).astype(np.float32)).to(dev)
+    outs = []
+    for tune in (False, True):
+        sim = Simulator(sw.types, sw.glob, mode=1)
+        x = torch.from_numpy(sw.state).to(dev)
+        carry = torch.zeros_like(x[:10])
+        if tune:
+            before = x.clone()
+            shape = sim.autotune(x, sw.dt, 200, gains=gains, wp=wp, carry=carry, ckpt_every=K)
+            torch.cuda.synchronize()
+            assert torch.equal(x, before) and not carry.any()
+            assert shape["block"] in (64, 128, 256, 512, 1024) and 1 <= shape["steps_per_launch"] <= 200
+        ckpt = torch.empty((200 // K, 40, sw.n), device=dev)
+        sim.step(x, 200, sw.dt, gains=gains, wp=wp, ckpt=ckpt, ckpt_every=K, carry=carry)
+        gx0, gg = sim.step_backward(ckpt, K, 200, sw.dt, lam, gains=gains, wp=wp)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in (x, ckpt, gx0, gg)])
+        sim.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 def test_autograd_function_matches_direct_call(diff_run, torch_dev):
     torch, dev = torch_dev
     from paper_2308_12698_amd.autograd import rollout
