@@ -265,6 +265,31 @@ def test_backward_rejects_invalid_arguments(diff_run, torch_dev):
     open_sim.close()
 
 
+def test_autotune_rejects_checkpoints_it_cannot_write(diff_run, torch_dev):
+    """Tuning the checkpointing forward takes the checks of potato_step with
+    a checkpoint buffer: ckpt_every < 0, no carries, open loop."""
+    torch, dev = torch_dev
+    from paper_2308_12698_amd import _lib as L
+    from paper_2308_12698_amd.sim import Simulator
+    sw = diff_run["sw"]
+    sim = Simulator(sw.types, sw.glob, mode=1)
+    x = torch.from_numpy(sw.state).to(dev)
+    carry = torch.zeros_like(x[:10])
+    with pytest.raises(L.PotatoError) as e:
+        sim.autotune(x, sw.dt, 50, gains=diff_run["gains_t"], wp=diff_run["wp_t"], carry=carry, ckpt_every=-1)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.PotatoError) as e:
+        sim.autotune(x, sw.dt, 50, gains=diff_run["gains_t"], wp=diff_run["wp_t"], ckpt_every=10)
+    assert e.value.status == L.EINVAL and "carr" in str(e.value)
+    sim.close()
+    open_sim = Simulator(sw.types, sw.glob, mode=0)
+    cmd = torch.zeros((4, sw.n), device=dev)
+    with pytest.raises(L.PotatoError) as e:
+        open_sim.autotune(x, sw.dt, 50, motor_cmd=cmd, carry=carry, ckpt_every=10)
+    assert e.value.status == L.EUNSUPPORTED
+    open_sim.close()
+
+
 def test_adjoint_in_the_controller_limits(oracle, torch_dev):
     """Gradients through the saturations and clamps (inputs.limits_swarm:
     rotors at the speed limit and at 0, the vertical-acceleration floor,
