@@ -445,7 +445,10 @@ def fwd_bwd_form(torch, dev, timed, N):
         dsim.set_options(form="fused", **tuned)
         tgt = torch.from_numpy(dw.extra["target"]).to(dev)
         ckpt = torch.empty((dw.n_steps // K, 40, dw.n), device=dev)
-        gfin = torch.empty((30, dw.n), device=dev)
+        # cotangent of the final state: the cost's rows (0-2 from the final
+        # position, 29 a constant) are written per call, the others stay zero
+        gfin = torch.zeros((30, dw.n), device=dev)
+        gfin[29] = dw.extra["cost_weight"]
         ws = None
 
         def fwd():
@@ -454,9 +457,7 @@ def fwd_bwd_form(torch, dev, timed, N):
             dsim.step(x, dw.n_steps, dw.dt, gains=gains, wp=dwp, ckpt=ckpt, ckpt_every=K, carry=carry)
 
         def bwd():
-            gfin.zero_()
-            gfin[0:3] = 2.0 * (x[0:3] - tgt)
-            gfin[29] = dw.extra["cost_weight"]
+            torch.sub(x[0:3], tgt, out=gfin[0:3]).mul_(2.0)
             return dsim.step_backward(ckpt, K, dw.n_steps, dw.dt, gfin, gains=gains, wp=dwp,
                                       workspace=ws)
 
